@@ -1,0 +1,162 @@
+"""CPU oracle for periodic voxel-grid elastic homogenisation -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library (the HIP path)
+never imports, links or calls it, and it shares no code with it.
+
+Contents
+--------
+* ``ceff_oracle.c`` (loaded through ctypes): FP64 operator, Jacobi-PCG solve,
+  stress averages, the paper-form APT step reference and the closed-form
+  gradient.
+* ``dense.py``: brute-force dense solve for tiny grids, assembled from the
+  strain energy alone (an independent route to the same discrete problem).
+
+Conventions: fields are numpy arrays shaped (nz, ny, nx) (x fastest);
+vector fields (3, nz, ny, nx); Voigt order 11, 22, 33, 23, 13, 12 with
+engineering shear strain, so unit load J = 4 sets eps_yz = eps_zy = 1/2.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = ctypes.CDLL(path)
+        L.or_stress.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_residual.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_average_stress.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_pcg.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_int64]
+        L.or_pcg.restype = ctypes.c_int64
+        L.or_apt_steps.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int64, _dp]
+        L.or_gradient.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _prep(K, G, h):
+    K = np.ascontiguousarray(K, np.float64)
+    G = np.ascontiguousarray(G, np.float64)
+    if K.shape != G.shape or K.ndim != 3:
+        raise ValueError("K and G must be 3-D arrays of the same shape (nz, ny, nx)")
+    if not (np.all(K > 0) and np.all(G > 0)):
+        raise ValueError("moduli must be positive")
+    nz, ny, nx = K.shape
+    dims = np.array([nx, ny, nz], np.int64)
+    hh = np.array(h, np.float64)
+    return K, G, dims, hh
+
+
+def unit_strain(J: int) -> np.ndarray:
+    """Tensor components (xx, yy, zz, yz, xz, xy) of the J-th unit Voigt strain (J = 0..5)."""
+    E = np.zeros(6)
+    E[J] = 1.0 if J < 3 else 0.5
+    return E
+
+
+def stress(K, G, E, u, h=(1.0, 1.0, 1.0)):
+    """Stresses (6, nz, ny, nx): xx, yy, zz at cells; yz, xz, xy at edges."""
+    K, G, dims, hh = _prep(K, G, h)
+    u = np.ascontiguousarray(u, np.float64).reshape((3,) + K.shape)
+    out = np.empty((6,) + K.shape)
+    lib().or_stress(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(np.asarray(E, np.float64)), _d(u), _d(out))
+    return out
+
+
+def residual(K, G, E, u, h=(1.0, 1.0, 1.0)):
+    """Out-of-balance force div(C:(E + grad u)) at faces, shape (3, nz, ny, nx)."""
+    K, G, dims, hh = _prep(K, G, h)
+    u = np.ascontiguousarray(u, np.float64).reshape((3,) + K.shape)
+    out = np.empty((3,) + K.shape)
+    lib().or_residual(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(np.asarray(E, np.float64)), _d(u), _d(out))
+    return out
+
+
+def average_stress(K, G, E, u, h=(1.0, 1.0, 1.0)):
+    """Volume-averaged stress in Voigt order (6,)."""
+    K, G, dims, hh = _prep(K, G, h)
+    u = np.ascontiguousarray(u, np.float64).reshape((3,) + K.shape)
+    out = np.empty(6)
+    lib().or_average_stress(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(np.asarray(E, np.float64)), _d(u), _d(out))
+    return out
+
+
+def solve_load(K, G, J, h=(1.0, 1.0, 1.0), rtol=1e-11, max_iter=1_000_000, u0=None, want_hist=False):
+    """Jacobi-PCG solve for unit load J.  Returns (u, iters, relres[, hist])."""
+    K, G, dims, hh = _prep(K, G, h)
+    u = np.zeros((3,) + K.shape) if u0 is None else np.array(u0, np.float64).reshape((3,) + K.shape)
+    rel = np.zeros(1)
+    cap = 200_000 if want_hist else 0
+    hist = np.zeros(max(cap, 1))
+    it = lib().or_pcg(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(unit_strain(J)), rtol, max_iter,
+                      _d(u), _d(rel), _d(hist) if cap else None, cap)
+    if want_hist:
+        return u, int(it), float(rel[0]), hist[:min(it + 1, cap)]
+    return u, int(it), float(rel[0])
+
+
+def ceff(K, G, h=(1.0, 1.0, 1.0), rtol=1e-11, loads=range(6), return_fields=False, max_iter=1_000_000):
+    """Effective stiffness (6x6, FP64): column J = volume-averaged stress under unit load J."""
+    C = np.full((6, 6), np.nan)
+    fields = {}
+    info = {}
+    for J in loads:
+        u, it, rel = solve_load(K, G, J, h, rtol, max_iter)
+        C[:, J] = average_stress(K, G, unit_strain(J), u, h)
+        info[J] = (it, rel)
+        if return_fields:
+            fields[J] = u
+    if return_fields:
+        return C, info, fields
+    return C, info
+
+
+def apt_steps(K, G, J, nsteps, courant, strouhal, h=(1.0, 1.0, 1.0), state=None):
+    """Run `nsteps` APT iterations in the paper's (p, tau, v) variables.
+
+    Returns the state dict {p, txx, tyy, tzz, tyz, txz, txy, v} after the
+    steps.  With state=None the iteration starts from the affine initial
+    state (v = 0, stresses of the uniform strain)."""
+    K, G, dims, hh = _prep(K, G, h)
+    N = K.size
+    init = 1 if state is None else 0
+    buf = np.zeros(10 * N) if state is None else np.concatenate([
+        state[k].ravel() for k in ("p", "txx", "tyy", "tzz", "tyz", "txz", "txy")] + [state["v"].ravel()])
+    buf = np.ascontiguousarray(buf)
+    lib().or_apt_steps(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(unit_strain(J)), courant, strouhal,
+                       init, nsteps, _d(buf))
+    sh = K.shape
+    names = ("p", "txx", "tyy", "tzz", "tyz", "txz", "txy")
+    out = {nm: buf[i * N:(i + 1) * N].reshape(sh).copy() for i, nm in enumerate(names)}
+    out["v"] = buf[7 * N:].reshape((3,) + sh).copy()
+    return out
+
+
+def gradient(K, G, fields, W, h=(1.0, 1.0, 1.0)):
+    """dJ/dK, dJ/dG for J = sum W_IJ C_IJ, from the six converged fields."""
+    K, G, dims, hh = _prep(K, G, h)
+    u6 = np.ascontiguousarray(np.stack([np.asarray(fields[J], np.float64).reshape((3,) + K.shape)
+                                        for J in range(6)]))
+    W = np.ascontiguousarray(np.asarray(W, np.float64).reshape(36))
+    dK = np.empty(K.shape); dG = np.empty(K.shape)
+    lib().or_gradient(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(u6), _d(W), _d(dK), _d(dG))
+    return dK, dG

@@ -1,0 +1,411 @@
+/*
+ * CPU oracle for periodic voxel-grid elastic homogenisation (FP64).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; it exists so that tests and the benchmark's CPU baseline
+ * can check the GPU path against a plain, slow, independent implementation.
+ * It shares no code, header or constant with the GPU library.
+ *
+ * What it computes (paper: "Theory", eqs. 1-3 and the volume averages that
+ * define C*; "Numerical solution strategy", the APT equations):
+ *
+ *   For a macroscopic strain E (a symmetric 3x3 tensor), find a periodic
+ *   displacement fluctuation u on the staggered grid such that the stress
+ *   sigma = C : (E + grad u) is divergence free.  Then <sigma_I> over the grid
+ *   is column J of the effective stiffness when E is the J-th unit Voigt
+ *   strain (engineering shear, so E_yz = E_zy = 1/2 for J = 4).
+ *
+ * Discretisation (staggered grid of the paper's "Discretization" section,
+ * read with periodic wrap, see the design notes for the readings):
+ *   cell (i,j,k)        : normal strains/stresses, K, G
+ *   x-face u_x[i,j,k]   : between cells i-1 and i
+ *   xy-edge [i,j,k]     : shared by cells (i-1|i, j-1|j, k); shear modulus is
+ *                         the harmonic mean of those four cells
+ *   exx = E_xx + (ux[i+1]-ux[i])/hx,   exy = E_xy + ((ux[j]-ux[j-1])/hy + (uy[i]-uy[i-1])/hx)/2
+ *   sxx = K*theta + 2G(exx - theta/3),  sxy = 2 G_e exy
+ *   (div s)_x[i,j,k] = (sxx[i]-sxx[i-1])/hx + (sxy[j+1]-sxy[j])/hy + (sxz[k+1]-sxz[k])/hz
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC (see oracle/build.py).
+ * Arrays: x fastest, linear index i + nx*(j + ny*k); vector fields are stored
+ * component-major: f[c*N + idx].  Tensor strain components are passed as
+ * E[6] = (xx, yy, zz, yz, xz, xy) (tensor, not engineering, shear).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int64_t nx, ny, nz;
+    double hx, hy, hz;
+} grid_t;
+
+static inline int64_t wrap(int64_t a, int64_t n) { a %= n; return a < 0 ? a + n : a; }
+static inline int64_t at(const grid_t *g, int64_t i, int64_t j, int64_t k) {
+    return wrap(i, g->nx) + g->nx * (wrap(j, g->ny) + g->ny * wrap(k, g->nz));
+}
+
+/* Harmonic mean of the shear moduli of the four cells sharing an edge.
+ * plane = 0: xy-edge (cells differ in i and j), 1: xz-edge (i and k),
+ * 2: yz-edge (j and k). */
+static double edge_modulus(const grid_t *g, const double *G, int plane, int64_t i, int64_t j, int64_t k) {
+    double s;
+    if (plane == 0)
+        s = 1.0 / G[at(g, i - 1, j - 1, k)] + 1.0 / G[at(g, i, j - 1, k)] +
+            1.0 / G[at(g, i - 1, j, k)] + 1.0 / G[at(g, i, j, k)];
+    else if (plane == 1)
+        s = 1.0 / G[at(g, i - 1, j, k - 1)] + 1.0 / G[at(g, i, j, k - 1)] +
+            1.0 / G[at(g, i - 1, j, k)] + 1.0 / G[at(g, i, j, k)];
+    else
+        s = 1.0 / G[at(g, i, j - 1, k - 1)] + 1.0 / G[at(g, i, j, k - 1)] +
+            1.0 / G[at(g, i, j - 1, k)] + 1.0 / G[at(g, i, j, k)];
+    return 4.0 / s;
+}
+
+/* Total strain (E + grad u) at every cell and edge.
+ * eps[0..2] normal strains at cells, eps[3] yz-edge, eps[4] xz-edge,
+ * eps[5] xy-edge (tensor components). */
+static void strains(const grid_t *g, const double E[6], const double *u, double *eps) {
+    const int64_t N = g->nx * g->ny * g->nz;
+    const double *ux = u, *uy = u + N, *uz = u + 2 * N;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < g->nz; k++)
+        for (int64_t j = 0; j < g->ny; j++)
+            for (int64_t i = 0; i < g->nx; i++) {
+                int64_t c = at(g, i, j, k);
+                eps[0 * N + c] = E[0] + (ux[at(g, i + 1, j, k)] - ux[c]) / g->hx;
+                eps[1 * N + c] = E[1] + (uy[at(g, i, j + 1, k)] - uy[c]) / g->hy;
+                eps[2 * N + c] = E[2] + (uz[at(g, i, j, k + 1)] - uz[c]) / g->hz;
+                eps[3 * N + c] = E[3] + 0.5 * ((uy[c] - uy[at(g, i, j, k - 1)]) / g->hz +
+                                               (uz[c] - uz[at(g, i, j - 1, k)]) / g->hy);
+                eps[4 * N + c] = E[4] + 0.5 * ((ux[c] - ux[at(g, i, j, k - 1)]) / g->hz +
+                                               (uz[c] - uz[at(g, i - 1, j, k)]) / g->hx);
+                eps[5 * N + c] = E[5] + 0.5 * ((ux[c] - ux[at(g, i, j - 1, k)]) / g->hy +
+                                               (uy[c] - uy[at(g, i - 1, j, k)]) / g->hx);
+            }
+}
+
+/* Hooke's law, isotropic: sigma = K tr(eps) I + 2 G dev(eps) at cells,
+ * sigma_e = 2 G_e eps_e at edges. */
+static void hooke(const grid_t *g, const double *K, const double *G, const double *eps, double *sig) {
+    const int64_t N = g->nx * g->ny * g->nz;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < g->nz; k++)
+        for (int64_t j = 0; j < g->ny; j++)
+            for (int64_t i = 0; i < g->nx; i++) {
+                int64_t c = at(g, i, j, k);
+                double th = eps[c] + eps[N + c] + eps[2 * N + c];
+                for (int d = 0; d < 3; d++)
+                    sig[d * N + c] = K[c] * th + 2.0 * G[c] * (eps[d * N + c] - th / 3.0);
+                sig[3 * N + c] = 2.0 * edge_modulus(g, G, 2, i, j, k) * eps[3 * N + c];
+                sig[4 * N + c] = 2.0 * edge_modulus(g, G, 1, i, j, k) * eps[4 * N + c];
+                sig[5 * N + c] = 2.0 * edge_modulus(g, G, 0, i, j, k) * eps[5 * N + c];
+            }
+}
+
+/* r = div sigma at the faces (the out-of-balance force of eq. 1). */
+static void divergence(const grid_t *g, const double *sig, double *r) {
+    const int64_t N = g->nx * g->ny * g->nz;
+    const double *sxx = sig, *syy = sig + N, *szz = sig + 2 * N;
+    const double *syz = sig + 3 * N, *sxz = sig + 4 * N, *sxy = sig + 5 * N;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < g->nz; k++)
+        for (int64_t j = 0; j < g->ny; j++)
+            for (int64_t i = 0; i < g->nx; i++) {
+                int64_t c = at(g, i, j, k);
+                r[c] = (sxx[c] - sxx[at(g, i - 1, j, k)]) / g->hx +
+                       (sxy[at(g, i, j + 1, k)] - sxy[c]) / g->hy +
+                       (sxz[at(g, i, j, k + 1)] - sxz[c]) / g->hz;
+                r[N + c] = (sxy[at(g, i + 1, j, k)] - sxy[c]) / g->hx +
+                           (syy[c] - syy[at(g, i, j - 1, k)]) / g->hy +
+                           (syz[at(g, i, j, k + 1)] - syz[c]) / g->hz;
+                r[2 * N + c] = (sxz[at(g, i + 1, j, k)] - sxz[c]) / g->hx +
+                               (syz[at(g, i, j + 1, k)] - syz[c]) / g->hy +
+                               (szz[c] - szz[at(g, i, j, k - 1)]) / g->hz;
+            }
+}
+
+static double dot(int64_t n, const double *a, const double *b) {
+    double s = 0.0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
+    for (int64_t t = 0; t < n; t++) s += a[t] * b[t];
+    return s;
+}
+
+/* ---- exported entry points ------------------------------------------------ */
+
+/* Stresses (6N, order xx yy zz at cells, yz xz xy at edges) for displacement u. */
+void or_stress(const int64_t dims[3], const double h[3], const double *K, const double *G,
+               const double E[6], const double *u, double *sig) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    const int64_t N = g.nx * g.ny * g.nz;
+    double *eps = malloc(sizeof(double) * 6 * N);
+    strains(&g, E, u, eps);
+    hooke(&g, K, G, eps, sig);
+    free(eps);
+}
+
+/* Residual r = div(C : (E + grad u)) at faces (3N). */
+void or_residual(const int64_t dims[3], const double h[3], const double *K, const double *G,
+                 const double E[6], const double *u, double *r) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    const int64_t N = g.nx * g.ny * g.nz;
+    double *sig = malloc(sizeof(double) * 6 * N);
+    or_stress(dims, h, K, G, E, u, sig);
+    divergence(&g, sig, r);
+    free(sig);
+}
+
+/* Volume averages of the six stress components (Voigt order 11 22 33 23 13 12),
+ * each over its own node set (cells or edges, N points each). */
+void or_average_stress(const int64_t dims[3], const double h[3], const double *K, const double *G,
+                       const double E[6], const double *u, double out[6]) {
+    const int64_t N = dims[0] * dims[1] * dims[2];
+    double *sig = malloc(sizeof(double) * 6 * N);
+    or_stress(dims, h, K, G, E, u, sig);
+    for (int c = 0; c < 6; c++) {
+        double s = 0.0;
+        for (int64_t t = 0; t < N; t++) s += sig[c * N + t];
+        out[c] = s / (double)N;
+    }
+    free(sig);
+}
+
+/* Diagonal of the stiffness operator A = -div C grad (Jacobi preconditioner). */
+static void diagonal(const grid_t *g, const double *K, const double *G, double *dg) {
+    const int64_t N = g->nx * g->ny * g->nz;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < g->nz; k++)
+        for (int64_t j = 0; j < g->ny; j++)
+            for (int64_t i = 0; i < g->nx; i++) {
+                int64_t c = at(g, i, j, k);
+                double Mc = K[c] + 4.0 * G[c] / 3.0;
+                double Mx = K[at(g, i - 1, j, k)] + 4.0 * G[at(g, i - 1, j, k)] / 3.0;
+                double My = K[at(g, i, j - 1, k)] + 4.0 * G[at(g, i, j - 1, k)] / 3.0;
+                double Mz = K[at(g, i, j, k - 1)] + 4.0 * G[at(g, i, j, k - 1)] / 3.0;
+                double hx2 = g->hx * g->hx, hy2 = g->hy * g->hy, hz2 = g->hz * g->hz;
+                dg[c] = (Mx + Mc) / hx2 +
+                        (edge_modulus(g, G, 0, i, j, k) + edge_modulus(g, G, 0, i, j + 1, k)) / hy2 +
+                        (edge_modulus(g, G, 1, i, j, k) + edge_modulus(g, G, 1, i, j, k + 1)) / hz2;
+                dg[N + c] = (My + Mc) / hy2 +
+                            (edge_modulus(g, G, 0, i, j, k) + edge_modulus(g, G, 0, i + 1, j, k)) / hx2 +
+                            (edge_modulus(g, G, 2, i, j, k) + edge_modulus(g, G, 2, i, j, k + 1)) / hz2;
+                dg[2 * N + c] = (Mz + Mc) / hz2 +
+                                (edge_modulus(g, G, 1, i, j, k) + edge_modulus(g, G, 1, i + 1, j, k)) / hx2 +
+                                (edge_modulus(g, G, 2, i, j, k) + edge_modulus(g, G, 2, i, j + 1, k)) / hy2;
+            }
+}
+
+static void remove_mean(int64_t N, double *v) {
+    for (int c = 0; c < 3; c++) {
+        double m = 0.0;
+        for (int64_t t = 0; t < N; t++) m += v[c * N + t];
+        m /= (double)N;
+        for (int64_t t = 0; t < N; t++) v[c * N + t] -= m;
+    }
+}
+
+/* Jacobi-preconditioned conjugate gradients for A u = div(C:E), A = -div C grad,
+ * on the zero-mean subspace (A is singular only on the three rigid translations).
+ * u: in = initial guess, out = solution.  Stops when ||b - A u|| <= rtol ||b||.
+ * Returns the iteration count; *relres gets the final true relative residual
+ * (recomputed from u, not the recursive one).  hist (optional, length hist_cap)
+ * receives the recursive relative residual of every iteration. */
+int64_t or_pcg(const int64_t dims[3], const double h[3], const double *K, const double *G,
+               const double E[6], double rtol, int64_t max_iter, double *u, double *relres,
+               double *hist, int64_t hist_cap) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    const int64_t N = g.nx * g.ny * g.nz, n3 = 3 * N;
+    const double zero[6] = {0, 0, 0, 0, 0, 0};
+    double *r = malloc(sizeof(double) * n3), *z = malloc(sizeof(double) * n3);
+    double *p = malloc(sizeof(double) * n3), *q = malloc(sizeof(double) * n3);
+    double *dg = malloc(sizeof(double) * n3), *b = malloc(sizeof(double) * n3);
+    diagonal(&g, K, G, dg);
+    or_residual(dims, h, K, G, E, u, r); /* r = div C (E + grad u) = b - A u */
+    {
+        double *u0 = calloc(n3, sizeof(double));
+        or_residual(dims, h, K, G, E, u0, b); /* b = div C E */
+        free(u0);
+    }
+    double bnorm = sqrt(dot(n3, b, b));
+    int64_t it = 0;
+    if (bnorm == 0.0) {
+        *relres = 0.0;
+        goto done;
+    }
+    for (int64_t t = 0; t < n3; t++) z[t] = r[t] / dg[t];
+    remove_mean(N, z);
+    memcpy(p, z, sizeof(double) * n3);
+    double rz = dot(n3, r, z);
+    for (it = 0; it < max_iter; it++) {
+        double rn = sqrt(dot(n3, r, r)) / bnorm;
+        if (hist && it < hist_cap) hist[it] = rn;
+        if (rn <= rtol) break;
+        /* q = A p = -div C grad p */
+        or_residual(dims, h, K, G, zero, p, q);
+        for (int64_t t = 0; t < n3; t++) q[t] = -q[t];
+        double alpha = rz / dot(n3, p, q);
+        for (int64_t t = 0; t < n3; t++) {
+            u[t] += alpha * p[t];
+            r[t] -= alpha * q[t];
+        }
+        for (int64_t t = 0; t < n3; t++) z[t] = r[t] / dg[t];
+        remove_mean(N, z);
+        double rz_new = dot(n3, r, z);
+        double beta = rz_new / rz;
+        rz = rz_new;
+        for (int64_t t = 0; t < n3; t++) p[t] = z[t] + beta * p[t];
+    }
+    remove_mean(N, u);
+    or_residual(dims, h, K, G, E, u, r);
+    *relres = sqrt(dot(n3, r, r)) / bnorm;
+done:
+    free(r); free(z); free(p); free(q); free(dg); free(b);
+    return it;
+}
+
+/* Accelerated pseudo-transient iterations written in the paper's own variables
+ * (pressure p, deviator tau, velocity v; "Solution of the system of equations").
+ * Readings (design notes): the physical time step is 1, so v plays the role of
+ * the displacement fluctuation; the pseudo moduli are the local moduli
+ * (K~ = K, G~ = G), giving K~dt = c K, G~dt = c G with c = ell*St/Lx and
+ * dt/rho~ = ell*Lx/(St*H~) at a face, H~ = max of K + 4G/3 over the two cells
+ * the face separates; ell = courant / sqrt(1/hx^2 + 1/hy^2 + 1/hz^2); the
+ * relaxation terms are taken implicitly; the solid viscosity term is dropped.
+ * Initial state: v = 0, p = -K tr E, tau = 2G dev E (cells), tau_e = 2 G_e E_e.
+ *
+ * state (10N): p, txx, tyy, tzz (cells), tyz, txz, txy (edges), vx, vy, vz (faces).
+ * If init != 0 the state is first set to the initial state above.  Runs nsteps. */
+void or_apt_steps(const int64_t dims[3], const double h[3], const double *K, const double *G,
+                  const double E[6], double courant, double strouhal, int init, int64_t nsteps,
+                  double *state) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    const int64_t N = g.nx * g.ny * g.nz;
+    double *p = state, *txx = state + N, *tyy = state + 2 * N, *tzz = state + 3 * N;
+    double *tyz = state + 4 * N, *txz = state + 5 * N, *txy = state + 6 * N;
+    double *v = state + 7 * N;
+    double Lx = fmax(fmax(g.nx * g.hx, g.ny * g.hy), g.nz * g.hz);
+    double ell = courant / sqrt(1.0 / (g.hx * g.hx) + 1.0 / (g.hy * g.hy) + 1.0 / (g.hz * g.hz));
+    double c = ell * strouhal / Lx;           /* pseudo step / physical step */
+    double rho_fac = ell * Lx / strouhal;     /* dt~/rho~ = rho_fac / H~ */
+    double *eps = malloc(sizeof(double) * 6 * N);
+    if (init) {
+        double trE = E[0] + E[1] + E[2];
+        for (int64_t t = 0; t < N; t++) {
+            int64_t i = t % g.nx, j = (t / g.nx) % g.ny, k = t / (g.nx * g.ny);
+            p[t] = -K[t] * trE;
+            txx[t] = 2.0 * G[t] * (E[0] - trE / 3.0);
+            tyy[t] = 2.0 * G[t] * (E[1] - trE / 3.0);
+            tzz[t] = 2.0 * G[t] * (E[2] - trE / 3.0);
+            tyz[t] = 2.0 * edge_modulus(&g, G, 2, i, j, k) * E[3];
+            txz[t] = 2.0 * edge_modulus(&g, G, 1, i, j, k) * E[4];
+            txy[t] = 2.0 * edge_modulus(&g, G, 0, i, j, k) * E[5];
+            v[t] = v[N + t] = v[2 * N + t] = 0.0;
+        }
+    }
+    double *sig = malloc(sizeof(double) * 6 * N), *r = malloc(sizeof(double) * 3 * N);
+    for (int64_t s = 0; s < nsteps; s++) {
+        /* strain rates from the current velocities (with the macroscopic strain) */
+        strains(&g, E, v, eps);
+        for (int64_t t = 0; t < N; t++) {
+            int64_t i = t % g.nx, j = (t / g.nx) % g.ny, k = t / (g.nx * g.ny);
+            double th = eps[t] + eps[N + t] + eps[2 * N + t];
+            double Kdt = c * K[t], Gdt = c * G[t];
+            /* (1/K~) dp/dt~ + p/(K dt) = -div v, implicit in p */
+            p[t] = (p[t] - Kdt * th) / (1.0 + Kdt / K[t]);
+            /* (1/2G~) dtau/dt~ + tau/(2G dt) = dev(strain rate), implicit in tau */
+            txx[t] = (txx[t] + 2.0 * Gdt * (eps[t] - th / 3.0)) / (1.0 + Gdt / G[t]);
+            tyy[t] = (tyy[t] + 2.0 * Gdt * (eps[N + t] - th / 3.0)) / (1.0 + Gdt / G[t]);
+            tzz[t] = (tzz[t] + 2.0 * Gdt * (eps[2 * N + t] - th / 3.0)) / (1.0 + Gdt / G[t]);
+            /* edges: pseudo and physical shear modulus are the edge's harmonic G_e */
+            double Ge, Gedt;
+            Ge = edge_modulus(&g, G, 2, i, j, k); Gedt = c * Ge;
+            tyz[t] = (tyz[t] + 2.0 * Gedt * eps[3 * N + t]) / (1.0 + Gedt / Ge);
+            Ge = edge_modulus(&g, G, 1, i, j, k); Gedt = c * Ge;
+            txz[t] = (txz[t] + 2.0 * Gedt * eps[4 * N + t]) / (1.0 + Gedt / Ge);
+            Ge = edge_modulus(&g, G, 0, i, j, k); Gedt = c * Ge;
+            txy[t] = (txy[t] + 2.0 * Gedt * eps[5 * N + t]) / (1.0 + Gedt / Ge);
+        }
+        /* momentum with pseudo inertia: rho~ dv/dt~ = div(-p I + tau) */
+        for (int64_t t = 0; t < N; t++) {
+            sig[t] = -p[t] + txx[t];
+            sig[N + t] = -p[t] + tyy[t];
+            sig[2 * N + t] = -p[t] + tzz[t];
+            sig[3 * N + t] = tyz[t];
+            sig[4 * N + t] = txz[t];
+            sig[5 * N + t] = txy[t];
+        }
+        divergence(&g, sig, r);
+        for (int64_t t = 0; t < N; t++) {
+            int64_t i = t % g.nx, j = (t / g.nx) % g.ny, k = t / (g.nx * g.ny);
+            double Hc = K[t] + 4.0 * G[t] / 3.0;
+            int64_t nb[3] = {at(&g, i - 1, j, k), at(&g, i, j - 1, k), at(&g, i, j, k - 1)};
+            for (int d = 0; d < 3; d++) {
+                double Hn = K[nb[d]] + 4.0 * G[nb[d]] / 3.0;
+                double Hf = Hc > Hn ? Hc : Hn;
+                v[d * N + t] += rho_fac / Hf * r[d * N + t];
+            }
+        }
+    }
+    free(eps); free(sig); free(r);
+}
+
+/* Gradient of J = sum_IJ W_IJ C_IJ with respect to per-voxel K and G.
+ * u6: the six converged fluctuation fields (6 x 3N, load-major), for unit Voigt
+ * loads.  Uses the stationarity of each solution, so only the explicit
+ * dependence of the strain energy on the moduli enters:
+ *   dC_IJ/dK_c = theta^I theta^J / N
+ *   dC_IJ/dG_c = [2 sum_d e'^I_dd e'^J_dd + sum_{edges e at c} (G_e/G_c)^2 eps^I_e eps^J_e] / N
+ * where e' is the deviatoric normal strain and the edge sum runs over the 12
+ * edges that touch cell c (d G_e / d G_c = G_e^2 / (4 G_c^2); edge energy 2 G_e eps^2
+ * counted for both symmetric components). */
+void or_gradient(const int64_t dims[3], const double h[3], const double *K, const double *G,
+                 const double *u6, const double W[36], double *dK, double *dG) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    const int64_t N = g.nx * g.ny * g.nz;
+    double *eps = malloc(sizeof(double) * 36 * N);
+    for (int J = 0; J < 6; J++) {
+        double E[6] = {0, 0, 0, 0, 0, 0};
+        E[J] = J < 3 ? 1.0 : 0.5;
+        strains(&g, E, u6 + (int64_t)J * 3 * N, eps + (int64_t)J * 6 * N);
+    }
+    (void)K;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < g.nz; k++)
+        for (int64_t j = 0; j < g.ny; j++)
+            for (int64_t i = 0; i < g.nx; i++) {
+                int64_t c = at(&g, i, j, k);
+                double gk = 0.0, gg = 0.0;
+                /* the 12 edges touching cell c: (plane, di, dj, dk) offsets of the edge index */
+                static const int eoff[12][4] = {
+                    {0, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 1, 1, 0},
+                    {1, 0, 0, 0}, {1, 1, 0, 0}, {1, 0, 0, 1}, {1, 1, 0, 1},
+                    {2, 0, 0, 0}, {2, 0, 1, 0}, {2, 0, 0, 1}, {2, 0, 1, 1}};
+                for (int I = 0; I < 6; I++)
+                    for (int J = 0; J < 6; J++) {
+                        double w = W[I * 6 + J];
+                        if (w == 0.0) continue;
+                        const double *a = eps + (int64_t)I * 6 * N, *b = eps + (int64_t)J * 6 * N;
+                        double tha = a[c] + a[N + c] + a[2 * N + c];
+                        double thb = b[c] + b[N + c] + b[2 * N + c];
+                        gk += w * tha * thb;
+                        double dev = 0.0;
+                        for (int d = 0; d < 3; d++)
+                            dev += (a[d * N + c] - tha / 3.0) * (b[d * N + c] - thb / 3.0);
+                        double ed = 0.0;
+                        for (int e = 0; e < 12; e++) {
+                            int pl = eoff[e][0];
+                            int64_t ei = i + eoff[e][1], ej = j + eoff[e][2], ek = k + eoff[e][3];
+                            int64_t ec = at(&g, ei, ej, ek);
+                            double Ge = edge_modulus(&g, G, pl, ei, ej, ek);
+                            int comp = pl == 0 ? 5 : (pl == 1 ? 4 : 3);
+                            double q = Ge / G[c];
+                            ed += q * q * a[comp * N + ec] * b[comp * N + ec];
+                        }
+                        gg += w * (2.0 * dev + ed);
+                    }
+                dK[c] = gk / (double)N;
+                dG[c] = gg / (double)N;
+            }
+    free(eps);
+}

@@ -1,0 +1,119 @@
+"""Brute-force dense solve of the periodic staggered-grid problem on tiny grids.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+This is a second, independent route to the discrete problem that
+``ceff_oracle.c`` solves.  It never forms a divergence: it writes the strain
+of a displacement field with numpy array shifts, assembles the strain matrix
+B column by column from unit displacements, weights it with the elastic
+energy density (paper, "Theory": the rate form of Hooke's law integrated
+with unit time step), and minimises the energy
+    W(u) = 1/2 sum_cells [K theta^2 + 2G sum_d (eps_dd - theta/3)^2]
+           + sum_edges 2 G_e eps_e^2
+by a dense least-squares solve of the normal equations B^T D B u = -B^T D e.
+The translations (the only null space) are removed with lstsq's minimum-norm
+solution.  C_IJ is then the volume average of stress (same definition as in
+the C oracle), so an index or sign mistake in either implementation shows up
+as a mismatch.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _fwd(a, axis):   # a[i+1] - a[i] along `axis` (periodic)
+    return np.roll(a, -1, axis=axis) - a
+
+
+def _bwd(a, axis):   # a[i] - a[i-1]
+    return a - np.roll(a, 1, axis=axis)
+
+
+# numpy axis of each Cartesian direction for arrays shaped (nz, ny, nx)
+_AX = {"x": 2, "y": 1, "z": 0}
+
+
+def strain_field(u, E, h=(1.0, 1.0, 1.0)):
+    """Tensor strain components (xx, yy, zz at cells; yz, xz, xy at edges)."""
+    ux, uy, uz = u
+    hx, hy, hz = h
+    exx = E[0] + _fwd(ux, _AX["x"]) / hx
+    eyy = E[1] + _fwd(uy, _AX["y"]) / hy
+    ezz = E[2] + _fwd(uz, _AX["z"]) / hz
+    eyz = E[3] + 0.5 * (_bwd(uy, _AX["z"]) / hz + _bwd(uz, _AX["y"]) / hy)
+    exz = E[4] + 0.5 * (_bwd(ux, _AX["z"]) / hz + _bwd(uz, _AX["x"]) / hx)
+    exy = E[5] + 0.5 * (_bwd(ux, _AX["y"]) / hy + _bwd(uy, _AX["x"]) / hx)
+    return np.stack([exx, eyy, ezz, eyz, exz, exy])
+
+
+def edge_moduli(G):
+    """Harmonic mean of G over the four cells around each edge: (yz, xz, xy)."""
+    inv = 1.0 / G
+    def sh(a, ax):
+        return np.roll(a, 1, axis=ax)
+    x, y, z = _AX["x"], _AX["y"], _AX["z"]
+    g_yz = 4.0 / (inv + sh(inv, y) + sh(inv, z) + sh(sh(inv, y), z))
+    g_xz = 4.0 / (inv + sh(inv, x) + sh(inv, z) + sh(sh(inv, x), z))
+    g_xy = 4.0 / (inv + sh(inv, x) + sh(inv, y) + sh(sh(inv, x), y))
+    return np.stack([g_yz, g_xz, g_xy])
+
+
+def stress_field(K, G, eps):
+    th = eps[0] + eps[1] + eps[2]
+    Ge = edge_moduli(G)
+    out = np.empty_like(eps)
+    for d in range(3):
+        out[d] = K * th + 2.0 * G * (eps[d] - th / 3.0)
+    for c in range(3):
+        out[3 + c] = 2.0 * Ge[c] * eps[3 + c]
+    return out
+
+
+def _energy_weights(K, G):
+    """Quadratic form of the energy density per node: returns a function that
+    maps strains (6, N) to the weighted strains D eps (so W = eps^T D eps / 2)."""
+    Ge = edge_moduli(G).reshape(3, -1)
+    Kf = K.ravel(); Gf = G.ravel()
+
+    def apply(eps):
+        th = eps[0] + eps[1] + eps[2]
+        out = np.empty_like(eps)
+        for d in range(3):
+            # d/d eps_dd of 1/2 [K th^2 + 2G sum (eps_dd - th/3)^2]
+            out[d] = Kf * th + 2.0 * Gf * (eps[d] - th / 3.0)
+        for c in range(3):
+            # d/d eps_e of 2 G_e eps_e^2 (counts both symmetric shear components)
+            out[3 + c] = 4.0 * Ge[c] * eps[3 + c]
+        return out
+    return apply
+
+
+def solve_dense(K, G, E, h=(1.0, 1.0, 1.0)):
+    """Displacement fluctuation minimising the discrete strain energy (3, nz, ny, nx)."""
+    shape = K.shape
+    N = K.size
+    zero = np.zeros(6)
+    B = np.empty((6 * N, 3 * N))
+    for col in range(3 * N):
+        u = np.zeros(3 * N); u[col] = 1.0
+        B[:, col] = strain_field(u.reshape((3,) + shape), zero, h).reshape(6 * N)
+    Dapply = _energy_weights(K, G)
+    DB = np.empty_like(B)
+    for col in range(3 * N):
+        DB[:, col] = Dapply(B[:, col].reshape(6, N)).reshape(6 * N)
+    A = B.T @ DB
+    e0 = strain_field(np.zeros((3,) + shape), E, h).reshape(6, N)
+    rhs = -B.T @ Dapply(e0).reshape(6 * N)
+    u, *_ = np.linalg.lstsq(A, rhs, rcond=1e-13)
+    return u.reshape((3,) + shape), A
+
+
+def ceff_dense(K, G, h=(1.0, 1.0, 1.0)):
+    """6x6 effective stiffness by dense energy minimisation, Voigt order."""
+    C = np.empty((6, 6))
+    for J in range(6):
+        E = np.zeros(6); E[J] = 1.0 if J < 3 else 0.5
+        u, _ = solve_dense(K, G, E, h)
+        sig = stress_field(K, G, strain_field(u, E, h))
+        C[:, J] = sig.reshape(6, -1).mean(axis=1)
+    return C
