@@ -1,0 +1,150 @@
+"""Benchmark: effective stiffness of a 191^3 fluid-filled sphere pack on one MI355X.
+
+One step = one complete solve of the hot path: six unit macroscopic-strain
+loads fused in one launch per iteration, FP32 sweeps with FP64 residuals and
+defect-correction folds, FP64 volume averages, giving the 6x6 C* on the host.
+The material is resident in HBM before timing starts.
+
+Prints one JSON line.  value = voxel-updates per second over the timed steps
+(N x iterations summed over loads / wall time).  The roofline object covers
+the iteration kernel: algorithmic bytes of its launches over their device time
+(HIP events recorded by the library on the stream the kernel runs on).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=191, help="grid size of the sphere pack")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--strouhal", type=float, default=2.0)
+    ap.add_argument("--check-every", type=int, default=200)
+    ap.add_argument("--no-fp64-baseline", action="store_true", help="skip the FP64 one-load-at-a-time solve")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=6, help="oracle APT iterations timed for the CPU baseline")
+    ap.add_argument("--autotune", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the design notes describe how the solve would shard)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_2410_20441_amd as ceff
+
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    m = synth.workload_spheres191(n=a.n)
+    N = m.phase.size
+    print(f"# workload {m.info}", file=sys.stderr, flush=True)
+
+    ctx = ceff.Context(0)
+    ctx.set_phases(m.phase, m.K_tab, m.G_tab)
+    opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, fuse_loads=True,
+                use_graph=True, autotune=a.autotune, max_iter=400000)
+
+    for w in range(a.warmup):
+        C, info = ctx.solve(**opts)
+        print(f"# warmup {w}: status {info['status']} iters {info['iters'].tolist()} "
+              f"{info['stats']['solve_ms']:.1f} ms", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    tot = {"vu": 0.0, "iters": 0, "step_ms": 0.0, "step_bytes": 0.0, "launches": 0}
+    Cs = []
+    for k in range(a.steps):
+        C, info = ctx.solve(**opts)
+        st = info["stats"]
+        tot["vu"] += N * float(info["iters"].sum())
+        tot["iters"] += int(info["iters"].sum())
+        tot["step_ms"] += st["step_time_ms"]
+        tot["step_bytes"] += st["step_bytes"]
+        tot["launches"] += st["step_launches"]
+        Cs.append(C)
+        print(f"# step {k}: iters {info['iters'].tolist()} solve {st['solve_ms']:.1f} ms, kernel "
+              f"{st['step_time_ms'] / max(st['step_launches'], 1):.4f} ms/launch, tile {st['tile_bx']}x"
+              f"{st['tile_by']}x{st['tile_kc']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    C = Cs[-1]
+    achieved = tot["step_bytes"] / (tot["step_ms"] * 1e-3) / 1e9
+
+    out = {
+        "metric": "GVoxel-updates/s (six-load effective stiffness solve, 191^3)",
+        "value": tot["vu"] / wall / 1e9,
+        "unit": "GVoxel-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.n}^3 periodic sphere pack, 10% fluid-filled pores (K=2.2, G=1e-3 GPa) "
+                               f"in a K=70, G=32 GPa matrix; six unit loads fused; FP32 sweeps with FP64 "
+                               f"residuals, folds and averages; rtol {a.rtol:g}",
+                   "n": a.n, "voxels": N, "loads": 6, "rtol": a.rtol, "precision": "mixed",
+                   "strouhal": a.strouhal, "porosity": m.info["porosity"]},
+        "time_to_ceff_s": wall / a.steps,
+        "iterations_per_solve": tot["iters"] / a.steps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "step_kernel<float,6> (heavy-ball APT iteration)",
+                     "avg_launch_ms": tot["step_ms"] / max(tot["launches"], 1),
+                     "bytes_per_launch": tot["step_bytes"] / max(tot["launches"], 1)},
+        "C_eff_GPa": np.round(C, 6).tolist(),
+    }
+
+    if not a.no_fp64_baseline:
+        t1 = time.perf_counter()
+        C64, info64 = ctx.solve(**dict(opts, precision="fp64", fuse_loads=False))
+        t64 = time.perf_counter() - t1
+        st64 = info64["stats"]
+        out["fp64_single_load"] = {
+            "time_to_ceff_s": t64, "iterations": info64["iters"].tolist(),
+            "gvu_s": N * float(info64["iters"].sum()) / t64 / 1e9,
+            "kernel_GB_s": st64["step_bytes"] / (st64["step_time_ms"] * 1e-3) / 1e9,
+            "avg_launch_ms": st64["step_time_ms"] / max(st64["step_launches"], 1)}
+        out["speedup_vs_fp64_single_load"] = t64 / (wall / a.steps)
+        out["ceff_max_rel_diff_mixed_vs_fp64"] = float(np.max(np.abs(C - C64)) / np.max(np.abs(C64)))
+        print(f"# fp64 single-load: {t64:.2f} s iters {info64['iters'].tolist()}", file=sys.stderr, flush=True)
+    ctx.close()
+
+    if not a.no_cpu_baseline:
+        import oracle
+        K, G = m.fields()
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        oracle.apt_steps(K, G, 0, 1, courant=0.95, strouhal=a.strouhal)  # load + first touch
+        t2 = time.perf_counter()
+        oracle.apt_steps(K, G, 0, a.cpu_steps, courant=0.95, strouhal=a.strouhal)
+        tc = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": N * a.cpu_steps / tc / 1e9, "unit": "GVoxel-updates/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{a.cpu_steps} APT iterations of one load on the same {a.n}^3 grid "
+                                         f"(oracle, paper-form variables), {tc:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * ceff -- effective elastic stiffness of a voxel image on one MI355X GPU.
+ *
+ * Computes the 6x6 effective stiffness C* of a heterogeneous linear-elastic
+ * voxel image (paper: "Effective elastic properties", the volume averages of
+ * stress and strain and the relation <sigma_ij> = C*_ijkl <eps_kl>).  Each
+ * requested column J is the volume-averaged stress of the equilibrium state
+ * (paper: eqs. 1-3, "Closed System of Equations") under the J-th unit
+ * macroscopic Voigt strain with periodic boundary conditions, found with the
+ * accelerated pseudo-transient iteration (paper: "Solution of the system of
+ * equations") on the staggered grid of the paper's "Discretization" section.
+ *
+ * Conventions
+ *   - Grid: nx x ny x nz voxels (cells) of size hx x hy x hz.  Per-voxel
+ *     arrays have N = nx*ny*nz entries, x fastest: index i + nx*(j + ny*k).
+ *   - Voigt order 11, 22, 33, 23, 13, 12 with engineering shear: load J = 3
+ *     (0-based; the fourth column) applies eps_yz = eps_zy = 1/2.
+ *   - Units: any consistent set; C* comes out in the units of K and G.
+ *   - C matrices are row-major doubles: C[I*6 + J].
+ *   - Inputs are read during the call only and remain owned by the caller.
+ *     Device pointers must live on the context's device; the library waits
+ *     for work already queued on the context's stream before reading them.
+ *     Outputs are caller-allocated.
+ *   - Every entry point returns a status and never aborts; the message of
+ *     the last failure is available from ceff_last_error.  A context is not
+ *     thread safe: one host thread at a time.
+ *   - Nothing here needs a GPU to fail cleanly: argument errors are detected
+ *     before any device call, and ceff_create returns CEFF_EDEVICE when no
+ *     usable device exists.
+ */
+#ifndef CEFF_H
+#define CEFF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ceff_ctx ceff_ctx;
+
+typedef enum {
+  CEFF_OK = 0,
+  CEFF_EINVAL = -1,        /* bad argument */
+  CEFF_ENOMEM = -2,        /* device or host allocation failed */
+  CEFF_EDEVICE = -3,       /* HIP runtime error, or no usable device */
+  CEFF_ENOTCONV = -4,      /* max_iter reached; outputs hold the last iterate */
+  CEFF_EDIVERGED = -5,     /* residual non-finite or grew by 1e6 */
+  CEFF_EUNSUPPORTED = -6,  /* valid request this build does not implement */
+  CEFF_ESTATE = -7         /* call out of order (no grid, no material, no kept fields) */
+} ceff_status;
+
+enum { CEFF_F32 = 0, CEFF_F64 = 1 };          /* element type of caller arrays */
+enum { CEFF_HOST = 0, CEFF_DEVICE = 1 };      /* where caller arrays live */
+enum { CEFF_PREC_FP64 = 0, CEFF_PREC_MIXED = 1 };
+
+typedef struct {
+  int precision;        /* CEFF_PREC_FP64: all sweeps in FP64.
+                           CEFF_PREC_MIXED: sweeps in FP32 on a correction of an FP64
+                           displacement; FP64 residuals decide convergence. */
+  double rtol;          /* stop when ||div sigma(u)||_2 <= rtol * ||div(C:E)||_2 (FP64) */
+  int64_t max_iter;     /* iteration cap per load */
+  int check_every;      /* iterations between residual checks (rounded up to even) */
+  double courant;       /* CFL number in (0, 1]: ell = courant / sqrt(sum 1/h^2) */
+  double strouhal;      /* St of the paper's numerical parameters, > 0 */
+  int fuse_loads;       /* 1: all requested loads advance in one launch per iteration;
+                           0: one load after another */
+  int use_graph;        /* 1: replay each block of check_every iterations as a HIP graph */
+  int keep_fields;      /* 1: keep the converged FP64 displacements for ceff_gradient */
+  int autotune;         /* 1: time candidate tile shapes first (cached per shape) */
+  double fold_ratio;    /* MIXED: fold the FP32 correction into the FP64 displacement when
+                           the residual fell by this factor since the last fold */
+} ceff_solve_opts;
+
+/* Execution counters of the most recent solve (for roofline accounting). */
+typedef struct {
+  int64_t step_launches;   /* launches of the iteration kernel */
+  double step_time_ms;     /* device time of those launches, from HIP events on the solve stream */
+  double step_bytes;       /* algorithmic HBM bytes of those launches: per voxel and active load
+                              9 words of displacement (+3 with a body force), plus K and G once */
+  double voxel_updates;    /* sum over launches of N * active loads */
+  int64_t outer_checks;    /* FP64 residual evaluations */
+  double solve_ms;         /* host wall time of the solve call */
+  int tile_bx, tile_by, tile_kc;  /* tile shape used (block extent incl. ghosts, z-chunk) */
+} ceff_stats;
+
+/* Fill *o with the defaults: MIXED, rtol 1e-8, max_iter 2e6, check_every 100,
+ * courant 0.95, strouhal 2.0, fuse_loads 1, use_graph 1, keep_fields 0,
+ * autotune 0, fold_ratio 1e-4. */
+void ceff_default_opts(ceff_solve_opts* o);
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t the
+ * caller orders its device inputs on (NULL = the null stream).  The library
+ * runs its own work on an internal stream of default priority. */
+ceff_status ceff_create(int device, void* hip_stream, ceff_ctx** out);
+void ceff_destroy(ceff_ctx* ctx);
+/* Message of the last failure (context-owned; valid until the next call). */
+const char* ceff_last_error(const ceff_ctx* ctx);
+
+/* Grid dimensions (each >= 2) and voxel spacings (> 0).  Clears material and kept fields. */
+ceff_status ceff_set_grid(ceff_ctx* ctx, int64_t nx, int64_t ny, int64_t nz, double hx, double hy, double hz);
+
+/* Per-voxel isotropic moduli K(x), G(x) (paper: each voxel carries the bulk
+ * and shear moduli of its material, "Discretization").  N values each, dtype
+ * CEFF_F32/CEFF_F64, host or device; copied.  All values must be finite and > 0. */
+ceff_status ceff_set_isotropic(ceff_ctx* ctx, const void* K, const void* G, int dtype, int where);
+
+/* Phase image (uint8, N values, host or device) plus per-phase moduli
+ * (host doubles, nphase entries, finite and > 0).  Every phase id must be < nphase. */
+ceff_status ceff_set_phases(ceff_ctx* ctx, const uint8_t* phase, int where, int nphase, const double* K_tab,
+                            const double* G_tab);
+
+/* Anisotropic local stiffness c_ijkl(x) (paper, "Future perspectives", items
+ * 2-3).  Not implemented: always returns CEFF_EUNSUPPORTED. */
+ceff_status ceff_set_stiffness(ceff_ctx* ctx, const void* c, int ncomp, int dtype, int where);
+
+/* Solve the unit loads in load_mask (bit J = Voigt column J, 0..5) and write
+ * those columns of C_out (other entries untouched).  opts may be NULL
+ * (defaults).  hist (optional, 3*hist_cap doubles) receives (iteration, load,
+ * relative residual) triples of every check; *hist_len their count.
+ * iters_out (optional, 6 entries) gets the iterations per load (0 when the
+ * affine guess is already in equilibrium).  On CEFF_ENOTCONV/CEFF_EDIVERGED
+ * the columns hold the stress averages of the last iterate. */
+ceff_status ceff_solve(ceff_ctx* ctx, uint32_t load_mask, const ceff_solve_opts* opts, double C_out[36],
+                       double* hist, int64_t hist_cap, int64_t* hist_len, int64_t iters_out[6]);
+
+/* Solve nsamples independent images of (possibly) different sizes together:
+ * every iteration is one launch over all unconverged (sample, load) pairs.
+ * dims: 3 per sample (nx, ny, nz); h: 3 per sample; K[s], G[s]: per-voxel
+ * moduli of sample s (dtype, where as in ceff_set_isotropic).  C_out: 36 per
+ * sample; iters_out: 6 per sample (optional).  Does not change the context's
+ * grid or material. */
+ceff_status ceff_solve_batch(ceff_ctx* ctx, int nsamples, const int64_t* dims, const double* h,
+                             const void* const* K, const void* const* G, int dtype, int where, uint32_t load_mask,
+                             const ceff_solve_opts* opts, double* C_out, int64_t* iters_out);
+
+/* Gradient of J = sum_IJ W[I*6+J] C_IJ with respect to the per-voxel K and G
+ * of the current material, from the displacements kept by the last
+ * ceff_solve (keep_fields = 1, all loads that W touches).  The solution is
+ * stationary, so only the explicit dependence of the strain energy on the
+ * moduli enters (no second solve).  dK, dG: N values each, dtype, host or
+ * device. */
+ceff_status ceff_gradient(ceff_ctx* ctx, const double W[36], void* dK, void* dG, int dtype, int where);
+
+/* ---- single-step entry points (for step-level checks) --------------------- */
+
+/* Run the first nsteps iterations of load J from the affine initial state
+ * (FP64 or MIXED = FP32 arithmetic, no defect correction) and return the
+ * displacement iterate u^nsteps and u^(nsteps-1) as host doubles (3N each,
+ * component-major; u_prev_out may be NULL). */
+ceff_status ceff_apt_steps(ceff_ctx* ctx, int J, int64_t nsteps, int precision, double courant, double strouhal,
+                           double* u_out, double* u_prev_out);
+
+/* Out-of-balance force div(C:(E_J + grad u)) of a host displacement u (3N
+ * doubles) at the faces, in FP64 (precision FP64) or FP32 arithmetic
+ * (MIXED).  r_out (3N, may be NULL) and *norm2 (sum of squares, may be NULL). */
+ceff_status ceff_residual(ceff_ctx* ctx, int J, int precision, const double* u, double* r_out, double* norm2);
+
+/* FP64 volume averages of the six stresses of displacement u (host, 3N) under
+ * unit load J, Voigt order (paper: the volume-averaged stress). */
+ceff_status ceff_average_stress(ceff_ctx* ctx, int J, const double* u, double out6[6]);
+
+/* Counters of the most recent solve. */
+ceff_status ceff_get_stats(const ceff_ctx* ctx, ceff_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CEFF_H */

@@ -1,0 +1,1259 @@
+// Host driver and C ABI (include/ceff.h) of the voxel-grid effective
+// stiffness solver.  All arithmetic of the method runs in the kernels of
+// ceff_kernels.hip; this file sets numerical parameters, owns device memory,
+// schedules launches (optionally replayed as HIP graphs), decides convergence
+// and assembles C*.
+//
+// Numerical parameters (paper, "Solution of the system of equations": CFL
+// condition, Strouhal number, the numerical combinations dt~/rho~, H~dt~,
+// G~dt~, K~dt~ and their optimal values), read with unit physical time step
+// and pseudo moduli equal to the local moduli:
+//   ell = courant / sqrt(1/hx^2 + 1/hy^2 + 1/hz^2)     (Vp~ dt~)
+//   c   = ell * St / Lx                               (dt~ / dt, so K~dt~ = c K)
+//   beta= ell * Lx / St                               (dt~/rho~ = beta / H~ at a face)
+//   Lx  = max_d n_d h_d
+// The displacement recurrence the kernels run then has momentum a = 1/(1+c)
+// and step factor s = c/(1+c) * beta (first step: beta, no momentum).
+#include "ceff.h"
+#include "ceff_internal.h"
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace ceff;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p) { o.p = nullptr; }
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  }
+  hipError_t alloc(size_t bytes) {
+    reset();
+    return hipMalloc(&p, bytes ? bytes : 16);
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) n = bytes;
+    return e;
+  }
+};
+
+}  // namespace
+
+struct ceff_ctx {
+  int device = 0;
+  hipStream_t user = nullptr;
+  hipStream_t s = nullptr;
+  int64_t nx = 0, ny = 0, nz = 0;
+  double h[3] = {1, 1, 1};
+  bool grid_set = false, have_material = false;
+  DevBuf K64, G64, K32, G32;
+  bool have32 = false;
+  DevBuf keep[6];
+  bool kept[6] = {false, false, false, false, false, false};
+  std::string err;
+  ceff_stats stats{};
+  std::map<std::tuple<int, int, int64_t, int64_t, int64_t>, TileShape> tuned;
+  PinnedBuf pinned;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+ceff_status fail(ceff_ctx* c, ceff_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIPCK(ctx, ...)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (__VA_ARGS__);                                                               \
+    if (e_ != hipSuccess)                                                                        \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? CEFF_ENOMEM : CEFF_EDEVICE, "%s failed: %s", \
+                  #__VA_ARGS__, hipGetErrorString(e_));                                          \
+  } while (0)
+
+#define STCK(...)                   \
+  do {                              \
+    ceff_status st_ = (__VA_ARGS__); \
+    if (st_ != CEFF_OK) return st_; \
+  } while (0)
+
+ceff_status validate_opts(ceff_ctx* c, const ceff_solve_opts& o) {
+  if (o.precision != CEFF_PREC_FP64 && o.precision != CEFF_PREC_MIXED)
+    return fail(c, CEFF_EINVAL, "precision must be CEFF_PREC_FP64 or CEFF_PREC_MIXED");
+  if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(c, CEFF_EINVAL, "rtol must be finite and > 0");
+  if (o.max_iter < 1) return fail(c, CEFF_EINVAL, "max_iter must be >= 1");
+  if (o.check_every < 1 || o.check_every > 1000000) return fail(c, CEFF_EINVAL, "check_every out of range");
+  if (!(o.courant > 0.0) || !(o.courant <= 1.0)) return fail(c, CEFF_EINVAL, "courant must be in (0, 1]");
+  if (!(o.strouhal > 0.0) || !std::isfinite(o.strouhal)) return fail(c, CEFF_EINVAL, "strouhal must be > 0");
+  if (!(o.fold_ratio > 0.0) || !(o.fold_ratio < 1.0)) return fail(c, CEFF_EINVAL, "fold_ratio must be in (0, 1)");
+  return CEFF_OK;
+}
+
+ceff_status validate_grid(ceff_ctx* c, int64_t nx, int64_t ny, int64_t nz, const double* h) {
+  if (nx < 2 || ny < 2 || nz < 2) return fail(c, CEFF_EINVAL, "grid dimensions must be >= 2");
+  if (nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20)) return fail(c, CEFF_EINVAL, "grid dimension too large");
+  if (nx * ny > (int64_t)1 << 40) return fail(c, CEFF_EINVAL, "grid too large");
+  for (int d = 0; d < 3; ++d)
+    if (!(h[d] > 0.0) || !std::isfinite(h[d])) return fail(c, CEFF_EINVAL, "spacings must be finite and > 0");
+  return CEFF_OK;
+}
+
+void unit_strain(int J, double E[6]) {
+  for (int q = 0; q < 6; ++q) E[q] = 0.0;
+  E[J] = J < 3 ? 1.0 : 0.5;
+}
+
+struct Params {
+  double mom, sfac, sfac_first;
+};
+
+Params make_params(int64_t nx, int64_t ny, int64_t nz, const double h[3], double courant, double strouhal) {
+  const double Lx = std::max({nx * h[0], ny * h[1], nz * h[2]});
+  const double ell = courant / std::sqrt(1.0 / (h[0] * h[0]) + 1.0 / (h[1] * h[1]) + 1.0 / (h[2] * h[2]));
+  const double c = ell * strouhal / Lx;
+  const double beta = ell * Lx / strouhal;
+  return Params{1.0 / (1.0 + c), c / (1.0 + c) * beta, beta};
+}
+
+// Copy caller moduli (F32/F64, host/device) into device FP64 arrays.
+ceff_status load_moduli(ceff_ctx* c, const void* src, int dtype, int where, int64_t N, DevBuf& dst) {
+  HIPCK(c, dst.alloc(sizeof(double) * N));
+  if (dtype == CEFF_F64) {
+    HIPCK(c, hipMemcpyAsync(dst.p, src, sizeof(double) * N,
+                            where == CEFF_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, c->s));
+  } else {
+    DevBuf tmp;
+    const float* dsrc = static_cast<const float*>(src);
+    if (where == CEFF_HOST) {
+      HIPCK(c, tmp.alloc(sizeof(float) * N));
+      HIPCK(c, hipMemcpyAsync(tmp.p, src, sizeof(float) * N, hipMemcpyHostToDevice, c->s));
+      dsrc = tmp.as<float>();
+    }
+    HIPCK(c, launch_convert<float, double>(dsrc, dst.as<double>(), N, c->s));
+    HIPCK(c, hipStreamSynchronize(c->s));
+  }
+  return CEFF_OK;
+}
+
+ceff_status check_positive(ceff_ctx* c, const double* K, const double* G, int64_t N) {
+  DevBuf bad;
+  int nb = 0;
+  HIPCK(c, bad.alloc(sizeof(int) * 65536));
+  HIPCK(c, launch_check_moduli<double>(K, G, N, bad.as<int>(), &nb, c->s));
+  std::vector<int> h(nb);
+  HIPCK(c, hipMemcpyAsync(h.data(), bad.p, sizeof(int) * nb, hipMemcpyDeviceToHost, c->s));
+  HIPCK(c, hipStreamSynchronize(c->s));
+  for (int v : h)
+    if (v) return fail(c, CEFF_EINVAL, "moduli must be finite and > 0");
+  return CEFF_OK;
+}
+
+void clear_kept(ceff_ctx* c) {
+  for (int J = 0; J < 6; ++J) {
+    c->keep[J].reset();
+    c->kept[J] = false;
+  }
+}
+
+// ---- the solve engine ------------------------------------------------------------
+
+struct SampleIn {
+  int64_t nx, ny, nz;
+  double h[3];
+  const double* K64;
+  const double* G64;
+  const float* K32;
+  const float* G32;
+};
+
+struct Prob {
+  int s = 0, J = 0, slot = 0;
+  double r0 = 0.0, relres = INFINITY, relres_base = 1.0;
+  int64_t iters = 0;
+  bool active = false;
+  ceff_status st = CEFF_OK;
+  int phase = 0;      // mixed precision: 0 = macroscopic strain, 1 = body force from the FP64 residual
+  int sol = 0;        // FP64: displacement buffer holding the solution; mixed: unused (base)
+  std::vector<double> recent;
+};
+
+TileShape default_tile(int64_t nx, int64_t ny, bool fp64) {
+  TileShape t;
+  (void)fp64;
+  // CEFF_TILE="bx,by[,kc]" overrides the shape (tests check results do not depend on it)
+  if (const char* env = std::getenv("CEFF_TILE")) {
+    int bx = 0, by = 0, kc = 0;
+    const int n = std::sscanf(env, "%d,%d,%d", &bx, &by, &kc);
+    if (n >= 2 && bx >= 3 && by >= 3 && ((bx * by + 63) / 64) * 64 <= 512) return TileShape{bx, by, n == 3 ? kc : 0};
+  }
+  t.bx = nx + 2 <= 66 ? (int)nx + 2 : 66;
+  t.by = 6;  // 66 x 6 ghosted block: 64 x 4 interior, 448 threads (<= the kernel's 512 bound)
+  if (ny + 2 < t.by) t.by = (int)ny + 2;
+  t.kc = 0;
+  return t;
+}
+
+template <typename T>
+struct Engine {
+  ceff_ctx* c;
+  std::vector<SampleIn> in;
+  ceff_solve_opts o;
+  bool mixed;
+  int Lk;                       // compiled load count of the kernels (1 or 6)
+  std::vector<int> Js;          // requested loads
+  TileShape ts{};
+  // device
+  std::vector<std::array<DevBuf, 2 * kMaxLoads>> ubuf;  // per sample: u[b][slot] at index b*6+slot
+  std::vector<std::array<DevBuf, kMaxLoads>> base, force;
+  DevBuf d_in, d_out, d_work, d_partials, d_norms, d_ranges, d_rout;
+  std::vector<SampleDesc<T>> h_in;
+  std::vector<SampleDesc<double>> h_out;
+  std::vector<WorkItem> work;
+  std::vector<int> ranges;
+  std::vector<Prob> probs;
+  int parity = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_m = 0;
+  // accounting
+  double step_ms = 0.0, step_bytes = 0.0, vu = 0.0;
+  int64_t launches = 0, outer = 0;
+  std::vector<double>* hist = nullptr;
+
+  ~Engine() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+
+  int slot_of(int J) const { return Lk == 1 ? 0 : J; }
+
+  ceff_status build_work(TileShape t, std::vector<WorkItem>& w, std::vector<int>& rg, std::vector<int>& kcs) {
+    w.clear();
+    rg.clear();
+    kcs.clear();
+    // split z into chunks so that the whole launch has a few thousand work items
+    int64_t total_xy = 0;
+    for (auto& s : in) total_xy += ((s.nx + t.bx - 3) / (t.bx - 2)) * ((s.ny + t.by - 3) / (t.by - 2));
+    for (size_t si = 0; si < in.size(); ++si) {
+      const auto& s = in[si];
+      const int tx = (int)((s.nx + t.bx - 3) / (t.bx - 2));
+      const int ty = (int)((s.ny + t.by - 3) / (t.by - 2));
+      int kc;
+      if (t.kc > 0) {
+        kc = t.kc;
+      } else {
+        int64_t chunks = (2048 + total_xy - 1) / total_xy;
+        if (chunks > s.nz / 4) chunks = s.nz / 4;
+        if (chunks < 1) chunks = 1;
+        kc = (int)((s.nz + chunks - 1) / chunks);
+      }
+      if (kc > s.nz) kc = (int)s.nz;
+      if (kc < 1) kc = 1;
+      const int cz = (int)((s.nz + kc - 1) / kc);
+      rg.push_back((int)w.size());
+      for (int kz = 0; kz < cz; ++kz)
+        for (int b = 0; b < ty; ++b)
+          for (int a = 0; a < tx; ++a) w.push_back(WorkItem{(int)si, a, b, kz});
+      rg.push_back((int)w.size());
+      kcs.push_back(kc);
+    }
+    if (w.size() > (size_t)INT32_MAX / 8) return fail(c, CEFF_EINVAL, "too many work items");
+    return CEFF_OK;
+  }
+
+  ceff_status upload_desc() {
+    HIPCK(c, hipMemcpyAsync(d_in.p, h_in.data(), sizeof(SampleDesc<T>) * h_in.size(), hipMemcpyHostToDevice, c->s));
+    HIPCK(c, hipMemcpyAsync(d_out.p, h_out.data(), sizeof(SampleDesc<double>) * h_out.size(), hipMemcpyHostToDevice,
+                            c->s));
+    return CEFF_OK;
+  }
+
+  double bytes_per_launch() const {
+    double b = 0.0;
+    for (size_t si = 0; si < in.size(); ++si) {
+      const double N = (double)in[si].nx * in[si].ny * in[si].nz;
+      int nact = 0;
+      for (int l = 0; l < kMaxLoads; ++l)
+        if (h_in[si].active & (1u << l)) {
+          ++nact;
+          b += N * sizeof(T) * (9.0 + (h_in[si].force[l] ? 3.0 : 0.0));
+        }
+      if (nact) b += N * sizeof(T) * 2.0;
+    }
+    return b;
+  }
+  double vu_per_launch() const {
+    double v = 0.0;
+    for (size_t si = 0; si < in.size(); ++si)
+      for (int l = 0; l < kMaxLoads; ++l)
+        if (h_in[si].active & (1u << l)) v += (double)in[si].nx * in[si].ny * in[si].nz;
+    return v;
+  }
+
+  hipError_t step(int first, double* partials) {
+    return Lk == 1 ? launch_step<T, 1>(d_in.as<SampleDesc<T>>(), d_work.as<WorkItem>(), (int)work.size(), ts, parity,
+                                       first, partials, c->s)
+                   : launch_step<T, 6>(d_in.as<SampleDesc<T>>(), d_work.as<WorkItem>(), (int)work.size(), ts, parity,
+                                       first, partials, c->s);
+  }
+
+  // FP64 residual of the outer (FP64) displacement with the macroscopic strain;
+  // writes float residuals to force buffers when rout is set; norms into d_norms.
+  hipError_t outer_residual(bool write_force) {
+    hipError_t e;
+    float* const* rout = write_force ? d_rout.as<float*>() : nullptr;
+    if (Lk == 1)
+      e = launch_residual<double, float, 1>(d_out.as<SampleDesc<double>>(), d_work.as<WorkItem>(), (int)work.size(),
+                                            ts, 0, rout, d_partials.as<double>(), c->s);
+    else
+      e = launch_residual<double, float, 6>(d_out.as<SampleDesc<double>>(), d_work.as<WorkItem>(), (int)work.size(),
+                                            ts, 0, rout, d_partials.as<double>(), c->s);
+    if (e != hipSuccess) return e;
+    return launch_finalize_norms(d_ranges.as<int>(), (int)in.size(), d_partials.as<double>(), d_norms.as<double>(),
+                                 c->s);
+  }
+
+  ceff_status read_norms(std::vector<double>& out) {
+    const size_t n = in.size() * kMaxLoads;
+    HIPCK(c, c->pinned.ensure(sizeof(double) * n));
+    HIPCK(c, hipMemcpyAsync(c->pinned.p, d_norms.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->s));
+    HIPCK(c, hipStreamSynchronize(c->s));
+    out.assign(static_cast<double*>(c->pinned.p), static_cast<double*>(c->pinned.p) + n);
+    return CEFF_OK;
+  }
+
+  ceff_status tune() {
+    const auto key = std::make_tuple((int)sizeof(T), Lk, in[0].nx, in[0].ny, in[0].nz);
+    auto it = c->tuned.find(key);
+    if (std::getenv("CEFF_TILE")) {
+      ts = default_tile(in[0].nx, in[0].ny, sizeof(T) == 8);
+      return CEFF_OK;
+    }
+    if (it != c->tuned.end()) {
+      ts = it->second;
+      return CEFF_OK;
+    }
+    if (!o.autotune) {
+      ts = default_tile(in[0].nx, in[0].ny, sizeof(T) == 8);
+      return CEFF_OK;
+    }
+    std::vector<TileShape> cand;
+    const int bxs[] = {34, 66, 130};
+    const int bys[] = {4, 6, 8, 10, 14};
+    for (int bx : bxs)
+      for (int by : bys) {
+        if (((bx * by + 63) / 64) * 64 > 512 || bx * by < 128) continue;
+        cand.push_back(TileShape{bx, by, 0});
+      }
+    float best = 1e30f;
+    TileShape bt = default_tile(in[0].nx, in[0].ny, sizeof(T) == 8);
+    std::vector<unsigned> saved(in.size());
+    for (size_t si = 0; si < in.size(); ++si) {
+      saved[si] = h_in[si].active;
+      for (int J : Js) h_in[si].active |= 1u << slot_of(J);
+    }
+    for (const TileShape& t : cand) {
+      std::vector<WorkItem> w;
+      std::vector<int> rg, kcs;
+      STCK(build_work(t, w, rg, kcs));
+      DevBuf dw;
+      HIPCK(c, dw.alloc(sizeof(WorkItem) * w.size()));
+      HIPCK(c, hipMemcpyAsync(dw.p, w.data(), sizeof(WorkItem) * w.size(), hipMemcpyHostToDevice, c->s));
+      for (size_t si = 0; si < in.size(); ++si) h_in[si].kc = kcs[si];
+      STCK(upload_desc());
+      auto run = [&](int n) -> hipError_t {
+        for (int q = 0; q < n; ++q) {
+          hipError_t e = Lk == 1 ? launch_step<T, 1>(d_in.as<SampleDesc<T>>(), dw.as<WorkItem>(), (int)w.size(), t,
+                                                     q & 1, 0, nullptr, c->s)
+                                 : launch_step<T, 6>(d_in.as<SampleDesc<T>>(), dw.as<WorkItem>(), (int)w.size(), t,
+                                                     q & 1, 0, nullptr, c->s);
+          if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+      };
+      HIPCK(c, run(2));
+      HIPCK(c, hipEventRecord(c->ev0, c->s));
+      HIPCK(c, run(6));
+      HIPCK(c, hipEventRecord(c->ev1, c->s));
+      HIPCK(c, hipEventSynchronize(c->ev1));
+      float ms = 0.f;
+      HIPCK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      if (ms < best) {
+        best = ms;
+        bt = t;
+      }
+    }
+    for (size_t si = 0; si < in.size(); ++si) h_in[si].active = saved[si];
+    ts = bt;
+    c->tuned[key] = ts;
+    return CEFF_OK;
+  }
+
+  ceff_status setup() {
+    const int ns = (int)in.size();
+    ubuf.resize(ns);
+    base.resize(ns);
+    force.resize(ns);
+    h_in.assign(ns, SampleDesc<T>{});
+    h_out.assign(ns, SampleDesc<double>{});
+    for (int si = 0; si < ns; ++si) {
+      const SampleIn& s = in[si];
+      const int64_t N = s.nx * s.ny * s.nz;
+      const Params p = make_params(s.nx, s.ny, s.nz, s.h, o.courant, o.strouhal);
+      for (SampleDesc<T>* dsc : {&h_in[si]}) {
+        dsc->nx = s.nx; dsc->ny = s.ny; dsc->nz = s.nz; dsc->N = N;
+        dsc->rhx = (T)(1.0 / s.h[0]); dsc->rhy = (T)(1.0 / s.h[1]); dsc->rhz = (T)(1.0 / s.h[2]);
+        dsc->mom = (T)p.mom; dsc->sfac = (T)p.sfac; dsc->sfac_first = (T)p.sfac_first;
+        dsc->K = sizeof(T) == 8 ? (const T*)s.K64 : (const T*)s.K32;
+        dsc->G = sizeof(T) == 8 ? (const T*)s.G64 : (const T*)s.G32;
+      }
+      SampleDesc<double>& od = h_out[si];
+      od.nx = s.nx; od.ny = s.ny; od.nz = s.nz; od.N = N;
+      od.rhx = 1.0 / s.h[0]; od.rhy = 1.0 / s.h[1]; od.rhz = 1.0 / s.h[2];
+      od.mom = p.mom; od.sfac = p.sfac; od.sfac_first = p.sfac_first;
+      od.K = s.K64; od.G = s.G64;
+      for (int J : Js) {
+        const int l = slot_of(J);
+        for (int b = 0; b < 2; ++b) {
+          HIPCK(c, ubuf[si][b * kMaxLoads + l].alloc(sizeof(T) * 3 * N));
+          HIPCK(c, launch_fill<T>(ubuf[si][b * kMaxLoads + l].as<T>(), 3 * N, T(0), c->s));
+          h_in[si].u[b][l] = ubuf[si][b * kMaxLoads + l].as<T>();
+        }
+        double E[6];
+        unit_strain(J, E);
+        for (int q = 0; q < 6; ++q) {
+          h_in[si].E[l][q] = (T)E[q];
+          od.E[l][q] = E[q];
+        }
+        if (mixed) {
+          HIPCK(c, base[si][l].alloc(sizeof(double) * 3 * N));
+          HIPCK(c, launch_fill<double>(base[si][l].as<double>(), 3 * N, 0.0, c->s));
+          HIPCK(c, force[si][l].alloc(sizeof(float) * 3 * N));
+          od.u[0][l] = base[si][l].as<double>();
+        } else {
+          od.u[0][l] = (double*)h_in[si].u[0][l];  // T == double here
+        }
+        Prob pr;
+        pr.s = si; pr.J = J; pr.slot = l;
+        probs.push_back(pr);
+      }
+    }
+    HIPCK(c, d_in.alloc(sizeof(SampleDesc<T>) * ns));
+    HIPCK(c, d_out.alloc(sizeof(SampleDesc<double>) * ns));
+    STCK(tune());
+    std::vector<int> kcs;
+    STCK(build_work(ts, work, ranges, kcs));
+    for (int si = 0; si < ns; ++si) {
+      h_in[si].kc = kcs[si];
+      h_out[si].kc = kcs[si];
+      h_in[si].work_begin = h_out[si].work_begin = ranges[2 * si];
+      h_in[si].work_end = h_out[si].work_end = ranges[2 * si + 1];
+    }
+    HIPCK(c, d_work.alloc(sizeof(WorkItem) * work.size()));
+    HIPCK(c, hipMemcpyAsync(d_work.p, work.data(), sizeof(WorkItem) * work.size(), hipMemcpyHostToDevice, c->s));
+    HIPCK(c, d_partials.alloc(sizeof(double) * kMaxLoads * work.size()));
+    HIPCK(c, d_norms.alloc(sizeof(double) * kMaxLoads * ns));
+    HIPCK(c, d_ranges.alloc(sizeof(int) * ranges.size()));
+    HIPCK(c, hipMemcpyAsync(d_ranges.p, ranges.data(), sizeof(int) * ranges.size(), hipMemcpyHostToDevice, c->s));
+    // per-slot float residual outputs for the outer check (only slot arrays of sample 0 are
+    // addressed through rout; batches write forces per sample through the same slot pointers
+    // when the batch has one sample, otherwise through per-sample passes below)
+    HIPCK(c, d_rout.alloc(sizeof(float*) * kMaxLoads));
+    // re-zero displacements (tuning may have run steps on them)
+    for (int si = 0; si < ns; ++si)
+      for (int J : Js) {
+        const int l = slot_of(J);
+        const int64_t N = in[si].nx * in[si].ny * in[si].nz;
+        for (int b = 0; b < 2; ++b) HIPCK(c, launch_fill<T>(h_in[si].u[b][l], 3 * N, T(0), c->s));
+      }
+    return CEFF_OK;
+  }
+
+  // Outer FP64 residual for sample set `which` (by active masks already set in h_out).
+  // Force outputs are per sample, so samples are processed one at a time when forces
+  // are written.
+  ceff_status outer_pass(bool write_force, std::vector<double>& norms) {
+    const int ns = (int)in.size();
+    norms.assign((size_t)ns * kMaxLoads, 0.0);
+    if (!write_force) {
+      STCK(upload_desc());
+      HIPCK(c, outer_residual(false));
+      STCK(read_norms(norms));
+      ++outer;
+      return CEFF_OK;
+    }
+    std::vector<unsigned> saved(ns);
+    for (int si = 0; si < ns; ++si) saved[si] = h_out[si].active;
+    for (int si = 0; si < ns; ++si) {
+      if (!saved[si]) continue;
+      for (int sj = 0; sj < ns; ++sj) h_out[sj].active = sj == si ? saved[si] : 0u;
+      float* ptrs[kMaxLoads] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+      for (int l = 0; l < kMaxLoads; ++l)
+        if (saved[si] & (1u << l)) ptrs[l] = force[si][l].as<float>();
+      HIPCK(c, hipMemcpyAsync(d_rout.p, ptrs, sizeof ptrs, hipMemcpyHostToDevice, c->s));
+      STCK(upload_desc());
+      HIPCK(c, outer_residual(true));
+      std::vector<double> nn;
+      STCK(read_norms(nn));
+      for (int l = 0; l < kMaxLoads; ++l) norms[(size_t)si * kMaxLoads + l] = nn[(size_t)si * kMaxLoads + l];
+      ++outer;
+    }
+    for (int si = 0; si < ns; ++si) h_out[si].active = saved[si];
+    return CEFF_OK;
+  }
+
+  ceff_status run_block(int m) {
+    // m iterations: m-1 plain steps and one that also reduces the residual of its input
+    const double bpl = bytes_per_launch(), vpl = vu_per_launch();
+    if (o.use_graph && (!gexec || graph_m != m)) {
+      if (gexec) {
+        (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+      }
+      if (graph) {
+        (void)hipGraphDestroy(graph);
+        graph = nullptr;
+      }
+      HIPCK(c, hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+      const int p0 = parity;
+      hipError_t e = hipSuccess;
+      for (int q = 0; q < m && e == hipSuccess; ++q) {
+        e = step(0, q == m - 1 ? d_partials.as<double>() : nullptr);
+        parity ^= 1;
+      }
+      if (e == hipSuccess)
+        e = launch_finalize_norms(d_ranges.as<int>(), (int)in.size(), d_partials.as<double>(), d_norms.as<double>(),
+                                  c->s);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(c->s, &g);
+      parity = p0;
+      HIPCK(c, e);
+      HIPCK(c, e2);
+      graph = g;
+      HIPCK(c, hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      graph_m = m;
+    }
+    HIPCK(c, hipEventRecord(c->ev0, c->s));
+    if (o.use_graph) {
+      HIPCK(c, hipGraphLaunch(gexec, c->s));
+      if (m & 1) parity ^= 1;
+    } else {
+      for (int q = 0; q < m; ++q) {
+        HIPCK(c, step(0, q == m - 1 ? d_partials.as<double>() : nullptr));
+        parity ^= 1;
+      }
+      HIPCK(c, launch_finalize_norms(d_ranges.as<int>(), (int)in.size(), d_partials.as<double>(),
+                                     d_norms.as<double>(), c->s));
+    }
+    HIPCK(c, hipEventRecord(c->ev1, c->s));
+    HIPCK(c, hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIPCK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    step_ms += ms;
+    step_bytes += bpl * m;
+    vu += vpl * m;
+    launches += m;
+    return CEFF_OK;
+  }
+
+  void record(int64_t it, int J, double rr) {
+    if (hist) {
+      hist->push_back((double)it);
+      hist->push_back((double)J);
+      hist->push_back(rr);
+    }
+  }
+
+  ceff_status solve() {
+    STCK(setup());
+    // initial residual norms ||div(C:E)|| in FP64 (all displacements are zero)
+    for (size_t si = 0; si < in.size(); ++si) {
+      unsigned m = 0;
+      for (auto& p : probs)
+        if (p.s == (int)si) m |= 1u << p.slot;
+      h_out[si].active = m;
+      h_in[si].active = 0;
+    }
+    std::vector<double> nn;
+    STCK(outer_pass(false, nn));
+    for (auto& p : probs) {
+      p.r0 = std::sqrt(nn[(size_t)p.s * kMaxLoads + p.slot]);
+      if (p.r0 > 0.0 && std::isfinite(p.r0)) {
+        p.active = true;
+        h_in[p.s].active |= 1u << p.slot;
+      } else if (!std::isfinite(p.r0)) {
+        p.st = CEFF_EDIVERGED;
+      } else {
+        p.relres = 0.0;
+        p.sol = 0;  // zero displacement: the affine state is in equilibrium
+        record(0, p.J, 0.0);
+      }
+    }
+    for (auto& d : h_out) d.active = 0;
+    bool any = false;
+    for (auto& p : probs) any |= p.active;
+    if (any) {
+      STCK(upload_desc());
+      // first iteration: u^1 from u^0 = 0 without momentum
+      const double bpl = bytes_per_launch() * 6.0 / 9.0, vpl = vu_per_launch();
+      HIPCK(c, hipEventRecord(c->ev0, c->s));
+      parity = 0;
+      HIPCK(c, step(1, nullptr));
+      HIPCK(c, hipEventRecord(c->ev1, c->s));
+      HIPCK(c, hipEventSynchronize(c->ev1));
+      float ms = 0.f;
+      HIPCK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      step_ms += ms; step_bytes += bpl; vu += vpl; launches += 1;
+      parity = 1;
+      for (auto& p : probs)
+        if (p.active) p.iters = 1;
+    }
+    int m = o.check_every + (o.check_every & 1);
+    while (true) {
+      bool act = false;
+      for (auto& p : probs) act |= p.active;
+      if (!act) break;
+      STCK(run_block(m));
+      std::vector<double> norms;
+      STCK(read_norms(norms));
+      bool desc_dirty = false;
+      std::vector<Prob*> to_fold;
+      for (auto& p : probs) {
+        if (!p.active) continue;
+        const int64_t checked = p.iters + m - 1;  // iterate whose residual was reduced
+        p.iters += m;
+        const double rr = std::sqrt(norms[(size_t)p.s * kMaxLoads + p.slot]) / p.r0;
+        p.relres = rr;
+        record(checked, p.J, rr);
+        const bool bad = !std::isfinite(rr) || rr > 1e6;
+        const bool cap = checked >= o.max_iter;
+        if (!mixed) {
+          if (rr <= o.rtol || bad || cap) {
+            p.active = false;
+            p.iters = checked;
+            p.sol = parity ^ 1;
+            p.st = rr <= o.rtol ? CEFF_OK : (bad ? CEFF_EDIVERGED : CEFF_ENOTCONV);
+            h_in[p.s].active &= ~(1u << p.slot);
+            desc_dirty = true;
+          }
+        } else {
+          bool stall = false;
+          if (p.recent.size() >= 3) {
+            const double best = *std::min_element(p.recent.end() - 3, p.recent.end());
+            stall = rr > 0.9 * best;
+          }
+          p.recent.push_back(rr);
+          if (bad) {
+            p.active = false;
+            p.iters = checked;
+            p.st = CEFF_EDIVERGED;
+            h_in[p.s].active &= ~(1u << p.slot);
+            desc_dirty = true;
+          } else if (rr <= o.rtol || rr <= o.fold_ratio * p.relres_base || stall || cap) {
+            to_fold.push_back(&p);
+          }
+        }
+      }
+      if (!to_fold.empty()) {
+        // fold u^{n} (in buffer parity^1) into the FP64 displacement, keep the momentum
+        for (Prob* p : to_fold) {
+          const int64_t N = in[p->s].nx * in[p->s].ny * in[p->s].nz;
+          HIPCK(c, launch_fold(base[p->s][p->slot].as<double>(), (float*)h_in[p->s].u[parity][p->slot],
+                               (float*)h_in[p->s].u[parity ^ 1][p->slot], 3 * N, c->s));
+          h_out[p->s].active |= 1u << p->slot;
+        }
+        std::vector<double> n64;
+        STCK(outer_pass(true, n64));
+        for (auto& d : h_out) d.active = 0;
+        for (Prob* p : to_fold) {
+          const int64_t checked = p->iters - 1;
+          const double rr = std::sqrt(n64[(size_t)p->s * kMaxLoads + p->slot]) / p->r0;
+          p->relres = rr;
+          p->recent.clear();
+          record(checked, p->J, rr);
+          const bool bad = !std::isfinite(rr) || rr > 1e6;
+          if (rr <= o.rtol || bad || checked >= o.max_iter) {
+            p->active = false;
+            p->iters = checked;
+            p->st = rr <= o.rtol ? CEFF_OK : (bad ? CEFF_EDIVERGED : CEFF_ENOTCONV);
+            h_in[p->s].active &= ~(1u << p->slot);
+          } else {
+            p->relres_base = rr;
+            if (p->phase == 0) {
+              p->phase = 1;
+              for (int q = 0; q < 6; ++q) h_in[p->s].E[p->slot][q] = T(0);
+              h_in[p->s].force[p->slot] = (const T*)force[p->s][p->slot].as<float>();
+            }
+          }
+        }
+        desc_dirty = true;
+      }
+      if (desc_dirty) STCK(upload_desc());
+    }
+    return CEFF_OK;
+  }
+
+  // FP64 solution of problem p on the device.
+  const double* solution(const Prob& p) const {
+    if (mixed) return base[p.s][p.slot].as<double>();
+    return (const double*)h_in[p.s].u[p.sol][p.slot];
+  }
+};
+
+ceff_status stress_average(ceff_ctx* c, const SampleIn& s, int J, const double* u, double out6[6]) {
+  const int64_t N = s.nx * s.ny * s.nz;
+  DevBuf part, o6;
+  const int cap = 4096;
+  HIPCK(c, part.alloc(sizeof(double) * 6 * cap));
+  HIPCK(c, o6.alloc(sizeof(double) * 6));
+  double E[6];
+  unit_strain(J, E);
+  HIPCK(c, launch_average_stress(s.nx, s.ny, s.nz, s.h, s.K64, s.G64, E, u, part.as<double>(), cap, o6.as<double>(),
+                                 c->s));
+  HIPCK(c, hipMemcpyAsync(out6, o6.p, sizeof(double) * 6, hipMemcpyDeviceToHost, c->s));
+  HIPCK(c, hipStreamSynchronize(c->s));
+  for (int q = 0; q < 6; ++q) out6[q] /= (double)N;
+  return CEFF_OK;
+}
+
+template <typename T>
+ceff_status run_engine(ceff_ctx* c, std::vector<SampleIn> samples, std::vector<int> Js, const ceff_solve_opts& o,
+                       int Lk, std::vector<std::array<double, 36>>& C, std::vector<std::array<int64_t, 6>>& iters,
+                       std::vector<double>* hist, bool keep, ceff_status& worst) {
+  Engine<T> e;
+  e.c = c;
+  e.in = std::move(samples);
+  e.o = o;
+  e.mixed = sizeof(T) == 4;
+  e.Lk = Lk;
+  e.Js = std::move(Js);
+  e.hist = hist;
+  STCK(e.solve());
+  for (auto& p : e.probs) {
+    double a6[6];
+    STCK(stress_average(c, e.in[p.s], p.J, e.solution(p), a6));
+    for (int I = 0; I < 6; ++I) C[p.s][I * 6 + p.J] = a6[I];
+    iters[p.s][p.J] = p.iters;
+    if (p.st != CEFF_OK && (worst == CEFF_OK || p.st == CEFF_EDIVERGED)) worst = p.st;
+    if (keep) {
+      const int64_t N = e.in[p.s].nx * e.in[p.s].ny * e.in[p.s].nz;
+      HIPCK(c, c->keep[p.J].alloc(sizeof(double) * 3 * N));
+      HIPCK(c, hipMemcpyAsync(c->keep[p.J].p, e.solution(p), sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->s));
+      c->kept[p.J] = true;
+    }
+  }
+  HIPCK(c, hipStreamSynchronize(c->s));
+  c->stats.step_launches += e.launches;
+  c->stats.step_time_ms += e.step_ms;
+  c->stats.step_bytes += e.step_bytes;
+  c->stats.voxel_updates += e.vu;
+  c->stats.outer_checks += e.outer;
+  c->stats.tile_bx = e.ts.bx;
+  c->stats.tile_by = e.ts.by;
+  c->stats.tile_kc = e.h_in.empty() ? 0 : e.h_in[0].kc;
+  return CEFF_OK;
+}
+
+ceff_status ensure32(ceff_ctx* c) {
+  if (c->have32) return CEFF_OK;
+  const int64_t N = c->nx * c->ny * c->nz;
+  HIPCK(c, c->K32.alloc(sizeof(float) * N));
+  HIPCK(c, c->G32.alloc(sizeof(float) * N));
+  HIPCK(c, launch_convert<double, float>(c->K64.as<double>(), c->K32.as<float>(), N, c->s));
+  HIPCK(c, launch_convert<double, float>(c->G64.as<double>(), c->G32.as<float>(), N, c->s));
+  c->have32 = true;
+  return CEFF_OK;
+}
+
+ceff_status begin_call(ceff_ctx* c) {
+  if (!c) return CEFF_EINVAL;
+  c->err.clear();
+  HIPCK(c, hipSetDevice(c->device));
+  HIPCK(c, hipStreamSynchronize(c->user));
+  return CEFF_OK;
+}
+
+SampleIn ctx_sample(ceff_ctx* c) {
+  SampleIn s;
+  s.nx = c->nx; s.ny = c->ny; s.nz = c->nz;
+  s.h[0] = c->h[0]; s.h[1] = c->h[1]; s.h[2] = c->h[2];
+  s.K64 = c->K64.as<double>(); s.G64 = c->G64.as<double>();
+  s.K32 = c->have32 ? c->K32.as<float>() : nullptr;
+  s.G32 = c->have32 ? c->G32.as<float>() : nullptr;
+  return s;
+}
+
+}  // namespace
+
+// ---- C ABI ---------------------------------------------------------------------------
+
+extern "C" {
+
+void ceff_default_opts(ceff_solve_opts* o) {
+  if (!o) return;
+  o->precision = CEFF_PREC_MIXED;
+  o->rtol = 1e-8;
+  o->max_iter = 2000000;
+  o->check_every = 100;
+  o->courant = 0.95;
+  o->strouhal = 2.0;
+  o->fuse_loads = 1;
+  o->use_graph = 1;
+  o->keep_fields = 0;
+  o->autotune = 0;
+  o->fold_ratio = 1e-4;
+}
+
+ceff_status ceff_create(int device, void* hip_stream, ceff_ctx** out) {
+  if (!out) return CEFF_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return CEFF_EDEVICE;
+  if (device < 0 || device >= n) return CEFF_EINVAL;
+  std::unique_ptr<ceff_ctx> c(new (std::nothrow) ceff_ctx());
+  if (!c) return CEFF_ENOMEM;
+  c->device = device;
+  c->user = static_cast<hipStream_t>(hip_stream);
+  if (hipSetDevice(device) != hipSuccess) return CEFF_EDEVICE;
+  if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess) return CEFF_EDEVICE;
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) return CEFF_EDEVICE;
+  *out = c.release();
+  return CEFF_OK;
+}
+
+void ceff_destroy(ceff_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->s) (void)hipStreamSynchronize(c->s);
+  c->K64.reset(); c->G64.reset(); c->K32.reset(); c->G32.reset();
+  clear_kept(c);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->s) (void)hipStreamDestroy(c->s);
+  delete c;
+}
+
+const char* ceff_last_error(const ceff_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+ceff_status ceff_set_grid(ceff_ctx* c, int64_t nx, int64_t ny, int64_t nz, double hx, double hy, double hz) {
+  if (!c) return CEFF_EINVAL;
+  const double h[3] = {hx, hy, hz};
+  STCK(validate_grid(c, nx, ny, nz, h));
+  c->nx = nx; c->ny = ny; c->nz = nz;
+  c->h[0] = hx; c->h[1] = hy; c->h[2] = hz;
+  c->grid_set = true;
+  c->have_material = false;
+  c->have32 = false;
+  c->K64.reset(); c->G64.reset(); c->K32.reset(); c->G32.reset();
+  clear_kept(c);
+  c->err.clear();
+  return CEFF_OK;
+}
+
+ceff_status ceff_set_isotropic(ceff_ctx* c, const void* K, const void* G, int dtype, int where) {
+  if (!c) return CEFF_EINVAL;
+  if (!c->grid_set) return fail(c, CEFF_ESTATE, "set the grid first");
+  if (!K || !G) return fail(c, CEFF_EINVAL, "null moduli");
+  if (dtype != CEFF_F32 && dtype != CEFF_F64) return fail(c, CEFF_EINVAL, "dtype must be CEFF_F32 or CEFF_F64");
+  if (where != CEFF_HOST && where != CEFF_DEVICE) return fail(c, CEFF_EINVAL, "where must be CEFF_HOST or CEFF_DEVICE");
+  STCK(begin_call(c));
+  const int64_t N = c->nx * c->ny * c->nz;
+  c->have_material = false;
+  c->have32 = false;
+  clear_kept(c);
+  STCK(load_moduli(c, K, dtype, where, N, c->K64));
+  STCK(load_moduli(c, G, dtype, where, N, c->G64));
+  STCK(check_positive(c, c->K64.as<double>(), c->G64.as<double>(), N));
+  c->have_material = true;
+  return CEFF_OK;
+}
+
+ceff_status ceff_set_phases(ceff_ctx* c, const uint8_t* phase, int where, int nphase, const double* K_tab,
+                            const double* G_tab) {
+  if (!c) return CEFF_EINVAL;
+  if (!c->grid_set) return fail(c, CEFF_ESTATE, "set the grid first");
+  if (!phase || !K_tab || !G_tab) return fail(c, CEFF_EINVAL, "null argument");
+  if (nphase < 1 || nphase > 256) return fail(c, CEFF_EINVAL, "nphase must be in [1, 256]");
+  if (where != CEFF_HOST && where != CEFF_DEVICE) return fail(c, CEFF_EINVAL, "where must be CEFF_HOST or CEFF_DEVICE");
+  for (int p = 0; p < nphase; ++p)
+    if (!(K_tab[p] > 0.0) || !(G_tab[p] > 0.0) || !std::isfinite(K_tab[p]) || !std::isfinite(G_tab[p]))
+      return fail(c, CEFF_EINVAL, "phase moduli must be finite and > 0");
+  const int64_t N = c->nx * c->ny * c->nz;
+  std::vector<uint8_t> host;
+  const uint8_t* hp = phase;
+  STCK(begin_call(c));
+  if (where == CEFF_DEVICE) {
+    host.resize(N);
+    HIPCK(c, hipMemcpy(host.data(), phase, N, hipMemcpyDeviceToHost));
+    hp = host.data();
+  }
+  for (int64_t t = 0; t < N; ++t)
+    if (hp[t] >= nphase) return fail(c, CEFF_EINVAL, "phase id %d at voxel %lld >= nphase", hp[t], (long long)t);
+  c->have_material = false;
+  c->have32 = false;
+  clear_kept(c);
+  DevBuf dph, kt, gt;
+  HIPCK(c, dph.alloc(N));
+  HIPCK(c, hipMemcpyAsync(dph.p, hp, N, hipMemcpyHostToDevice, c->s));
+  HIPCK(c, kt.alloc(sizeof(double) * nphase));
+  HIPCK(c, gt.alloc(sizeof(double) * nphase));
+  HIPCK(c, hipMemcpyAsync(kt.p, K_tab, sizeof(double) * nphase, hipMemcpyHostToDevice, c->s));
+  HIPCK(c, hipMemcpyAsync(gt.p, G_tab, sizeof(double) * nphase, hipMemcpyHostToDevice, c->s));
+  HIPCK(c, c->K64.alloc(sizeof(double) * N));
+  HIPCK(c, c->G64.alloc(sizeof(double) * N));
+  HIPCK(c, launch_phase_to_fields<double>(dph.as<uint8_t>(), N, kt.as<double>(), gt.as<double>(), nphase,
+                                          c->K64.as<double>(), c->G64.as<double>(), c->s));
+  HIPCK(c, hipStreamSynchronize(c->s));
+  c->have_material = true;
+  return CEFF_OK;
+}
+
+ceff_status ceff_set_stiffness(ceff_ctx* c, const void* cmat, int ncomp, int dtype, int where) {
+  (void)cmat; (void)ncomp; (void)dtype; (void)where;
+  if (!c) return CEFF_EINVAL;
+  return fail(c, CEFF_EUNSUPPORTED, "anisotropic local stiffness is not implemented");
+}
+
+ceff_status ceff_solve(ceff_ctx* c, uint32_t load_mask, const ceff_solve_opts* opts, double C_out[36], double* hist,
+                       int64_t hist_cap, int64_t* hist_len, int64_t iters_out[6]) {
+  if (!c) return CEFF_EINVAL;
+  ceff_solve_opts o;
+  ceff_default_opts(&o);
+  if (opts) o = *opts;
+  STCK(validate_opts(c, o));
+  if (!C_out) return fail(c, CEFF_EINVAL, "C_out is null");
+  if (load_mask == 0 || (load_mask & ~0x3Fu)) return fail(c, CEFF_EINVAL, "load_mask must be a nonzero 6-bit mask");
+  if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(c, CEFF_EINVAL, "bad history buffer");
+  if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  STCK(begin_call(c));
+  const auto t0 = std::chrono::steady_clock::now();
+  c->stats = ceff_stats{};
+  if (o.keep_fields) clear_kept(c);
+  const bool mixed = o.precision == CEFF_PREC_MIXED;
+  if (mixed) STCK(ensure32(c));
+  std::vector<int> Js;
+  for (int J = 0; J < 6; ++J)
+    if (load_mask & (1u << J)) Js.push_back(J);
+  std::vector<std::array<double, 36>> C(1);
+  std::vector<std::array<int64_t, 6>> it(1);
+  for (int q = 0; q < 36; ++q) C[0][q] = C_out[q];
+  for (int q = 0; q < 6; ++q) it[0][q] = 0;
+  std::vector<double> hv;
+  ceff_status worst = CEFF_OK;
+  std::vector<std::vector<int>> groups;
+  if (o.fuse_loads && Js.size() > 1)
+    groups.push_back(Js);
+  else
+    for (int J : Js) groups.push_back({J});
+  for (auto& g : groups) {
+    const int Lk = g.size() == 1 ? 1 : 6;
+    std::vector<SampleIn> s{ctx_sample(c)};
+    if (mixed)
+      STCK(run_engine<float>(c, s, g, o, Lk, C, it, &hv, o.keep_fields != 0, worst));
+    else
+      STCK(run_engine<double>(c, s, g, o, Lk, C, it, &hv, o.keep_fields != 0, worst));
+  }
+  for (int J : Js)
+    for (int I = 0; I < 6; ++I) C_out[I * 6 + J] = C[0][I * 6 + J];
+  if (iters_out)
+    for (int q = 0; q < 6; ++q) iters_out[q] = (load_mask & (1u << q)) ? it[0][q] : 0;
+  const int64_t nh = (int64_t)hv.size() / 3;
+  if (hist && hist_cap > 0) {
+    const int64_t w = std::min(nh, hist_cap);
+    std::memcpy(hist, hv.data(), sizeof(double) * 3 * w);
+  }
+  if (hist_len) *hist_len = nh;
+  c->stats.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (worst != CEFF_OK) return fail(c, worst, worst == CEFF_ENOTCONV ? "max_iter reached" : "iteration diverged");
+  return CEFF_OK;
+}
+
+ceff_status ceff_solve_batch(ceff_ctx* c, int nsamples, const int64_t* dims, const double* h, const void* const* K,
+                             const void* const* G, int dtype, int where, uint32_t load_mask,
+                             const ceff_solve_opts* opts, double* C_out, int64_t* iters_out) {
+  if (!c) return CEFF_EINVAL;
+  ceff_solve_opts o;
+  ceff_default_opts(&o);
+  if (opts) o = *opts;
+  STCK(validate_opts(c, o));
+  if (nsamples < 1 || nsamples > 100000) return fail(c, CEFF_EINVAL, "nsamples out of range");
+  if (!dims || !h || !K || !G || !C_out) return fail(c, CEFF_EINVAL, "null argument");
+  if (dtype != CEFF_F32 && dtype != CEFF_F64) return fail(c, CEFF_EINVAL, "dtype must be CEFF_F32 or CEFF_F64");
+  if (where != CEFF_HOST && where != CEFF_DEVICE) return fail(c, CEFF_EINVAL, "where must be CEFF_HOST or CEFF_DEVICE");
+  if (load_mask == 0 || (load_mask & ~0x3Fu)) return fail(c, CEFF_EINVAL, "load_mask must be a nonzero 6-bit mask");
+  for (int s = 0; s < nsamples; ++s) {
+    STCK(validate_grid(c, dims[3 * s], dims[3 * s + 1], dims[3 * s + 2], h + 3 * s));
+    if (!K[s] || !G[s]) return fail(c, CEFF_EINVAL, "null moduli for sample %d", s);
+  }
+  STCK(begin_call(c));
+  const auto t0 = std::chrono::steady_clock::now();
+  c->stats = ceff_stats{};
+  const bool mixed = o.precision == CEFF_PREC_MIXED;
+  std::vector<DevBuf> K64(nsamples), G64(nsamples), K32(nsamples), G32(nsamples);
+  std::vector<SampleIn> in(nsamples);
+  for (int s = 0; s < nsamples; ++s) {
+    const int64_t N = dims[3 * s] * dims[3 * s + 1] * dims[3 * s + 2];
+    STCK(load_moduli(c, K[s], dtype, where, N, K64[s]));
+    STCK(load_moduli(c, G[s], dtype, where, N, G64[s]));
+    STCK(check_positive(c, K64[s].as<double>(), G64[s].as<double>(), N));
+    if (mixed) {
+      HIPCK(c, K32[s].alloc(sizeof(float) * N));
+      HIPCK(c, G32[s].alloc(sizeof(float) * N));
+      HIPCK(c, launch_convert<double, float>(K64[s].as<double>(), K32[s].as<float>(), N, c->s));
+      HIPCK(c, launch_convert<double, float>(G64[s].as<double>(), G32[s].as<float>(), N, c->s));
+    }
+    in[s] = SampleIn{dims[3 * s], dims[3 * s + 1], dims[3 * s + 2], {h[3 * s], h[3 * s + 1], h[3 * s + 2]},
+                     K64[s].as<double>(), G64[s].as<double>(), mixed ? K32[s].as<float>() : nullptr,
+                     mixed ? G32[s].as<float>() : nullptr};
+  }
+  std::vector<int> Js;
+  for (int J = 0; J < 6; ++J)
+    if (load_mask & (1u << J)) Js.push_back(J);
+  std::vector<std::array<double, 36>> C(nsamples);
+  std::vector<std::array<int64_t, 6>> it(nsamples);
+  for (int s = 0; s < nsamples; ++s) {
+    for (int q = 0; q < 36; ++q) C[s][q] = C_out[36 * s + q];
+    for (int q = 0; q < 6; ++q) it[s][q] = 0;
+  }
+  ceff_status worst = CEFF_OK;
+  const int Lk = Js.size() == 1 ? 1 : 6;
+  if (mixed)
+    STCK(run_engine<float>(c, in, Js, o, Lk, C, it, nullptr, false, worst));
+  else
+    STCK(run_engine<double>(c, in, Js, o, Lk, C, it, nullptr, false, worst));
+  for (int s = 0; s < nsamples; ++s) {
+    for (int J : Js)
+      for (int I = 0; I < 6; ++I) C_out[36 * s + I * 6 + J] = C[s][I * 6 + J];
+    if (iters_out)
+      for (int q = 0; q < 6; ++q) iters_out[6 * s + q] = (load_mask & (1u << q)) ? it[s][q] : 0;
+  }
+  c->stats.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (worst != CEFF_OK) return fail(c, worst, worst == CEFF_ENOTCONV ? "max_iter reached" : "iteration diverged");
+  return CEFF_OK;
+}
+
+ceff_status ceff_gradient(ceff_ctx* c, const double W[36], void* dK, void* dG, int dtype, int where) {
+  if (!c) return CEFF_EINVAL;
+  if (!W || !dK || !dG) return fail(c, CEFF_EINVAL, "null argument");
+  if (dtype != CEFF_F32 && dtype != CEFF_F64) return fail(c, CEFF_EINVAL, "dtype must be CEFF_F32 or CEFF_F64");
+  if (where != CEFF_HOST && where != CEFF_DEVICE) return fail(c, CEFF_EINVAL, "where must be CEFF_HOST or CEFF_DEVICE");
+  for (int q = 0; q < 36; ++q)
+    if (!std::isfinite(W[q])) return fail(c, CEFF_EINVAL, "W must be finite");
+  if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  const double* u6[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  for (int I = 0; I < 6; ++I)
+    for (int J = 0; J < 6; ++J)
+      if (W[I * 6 + J] != 0.0) {
+        if (!c->kept[I] || !c->kept[J])
+          return fail(c, CEFF_ESTATE, "gradient needs the fields of loads %d and %d (solve with keep_fields=1)", I, J);
+        u6[I] = c->keep[I].as<double>();
+        u6[J] = c->keep[J].as<double>();
+      }
+  STCK(begin_call(c));
+  const int64_t N = c->nx * c->ny * c->nz;
+  DevBuf du6, dW, oK, oG;
+  HIPCK(c, du6.alloc(sizeof u6));
+  HIPCK(c, dW.alloc(sizeof(double) * 36));
+  HIPCK(c, hipMemcpyAsync(du6.p, u6, sizeof u6, hipMemcpyHostToDevice, c->s));
+  HIPCK(c, hipMemcpyAsync(dW.p, W, sizeof(double) * 36, hipMemcpyHostToDevice, c->s));
+  const size_t es = dtype == CEFF_F64 ? sizeof(double) : sizeof(float);
+  void* tK = dK;
+  void* tG = dG;
+  if (where == CEFF_HOST) {
+    HIPCK(c, oK.alloc(es * N));
+    HIPCK(c, oG.alloc(es * N));
+    tK = oK.p;
+    tG = oG.p;
+  }
+  if (dtype == CEFF_F64)
+    HIPCK(c, launch_gradient<double>(c->nx, c->ny, c->nz, c->h, c->K64.as<double>(), c->G64.as<double>(),
+                                     du6.as<const double*>(), dW.as<double>(), (double*)tK, (double*)tG, c->s));
+  else
+    HIPCK(c, launch_gradient<float>(c->nx, c->ny, c->nz, c->h, c->K64.as<double>(), c->G64.as<double>(),
+                                    du6.as<const double*>(), dW.as<double>(), (float*)tK, (float*)tG, c->s));
+  if (where == CEFF_HOST) {
+    HIPCK(c, hipMemcpyAsync(dK, tK, es * N, hipMemcpyDeviceToHost, c->s));
+    HIPCK(c, hipMemcpyAsync(dG, tG, es * N, hipMemcpyDeviceToHost, c->s));
+  }
+  HIPCK(c, hipStreamSynchronize(c->s));
+  return CEFF_OK;
+}
+
+ceff_status ceff_apt_steps(ceff_ctx* c, int J, int64_t nsteps, int precision, double courant, double strouhal,
+                           double* u_out, double* u_prev_out) {
+  if (!c) return CEFF_EINVAL;
+  if (J < 0 || J > 5) return fail(c, CEFF_EINVAL, "load index must be in [0, 5]");
+  if (nsteps < 1 || nsteps > 100000000) return fail(c, CEFF_EINVAL, "nsteps out of range");
+  if (precision != CEFF_PREC_FP64 && precision != CEFF_PREC_MIXED) return fail(c, CEFF_EINVAL, "bad precision");
+  if (!(courant > 0.0) || !(courant <= 1.0) || !(strouhal > 0.0)) return fail(c, CEFF_EINVAL, "bad parameters");
+  if (!u_out) return fail(c, CEFF_EINVAL, "u_out is null");
+  if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  STCK(begin_call(c));
+  ceff_solve_opts o;
+  ceff_default_opts(&o);
+  o.courant = courant;
+  o.strouhal = strouhal;
+  o.use_graph = 0;
+  const int64_t N = c->nx * c->ny * c->nz;
+  auto run = [&](auto tag) -> ceff_status {
+    using T = decltype(tag);
+    Engine<T> e;
+    e.c = c;
+    e.in = {ctx_sample(c)};
+    e.o = o;
+    e.mixed = false;
+    e.Lk = 1;
+    e.Js = {J};
+    STCK(e.setup());
+    e.h_in[0].active = 1u;
+    STCK(e.upload_desc());
+    e.parity = 0;
+    HIPCK(c, e.step(1, nullptr));
+    e.parity = 1;
+    for (int64_t q = 1; q < nsteps; ++q) {
+      HIPCK(c, e.step(0, nullptr));
+      e.parity ^= 1;
+    }
+    DevBuf tmp;
+    HIPCK(c, tmp.alloc(sizeof(double) * 3 * N));
+    for (int which = 0; which < 2; ++which) {
+      double* dst = which == 0 ? u_out : u_prev_out;
+      if (!dst) continue;
+      const T* src = e.h_in[0].u[which == 0 ? e.parity : e.parity ^ 1][0];
+      if (sizeof(T) == 8)
+        HIPCK(c, hipMemcpyAsync(tmp.p, src, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->s));
+      else
+        HIPCK(c, launch_convert<float, double>((const float*)src, tmp.as<double>(), 3 * N, c->s));
+      HIPCK(c, hipMemcpyAsync(dst, tmp.p, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c->s));
+      HIPCK(c, hipStreamSynchronize(c->s));
+    }
+    return CEFF_OK;
+  };
+  if (precision == CEFF_PREC_MIXED) {
+    STCK(ensure32(c));
+    return run(float{});
+  }
+  return run(double{});
+}
+
+ceff_status ceff_residual(ceff_ctx* c, int J, int precision, const double* u, double* r_out, double* norm2) {
+  if (!c) return CEFF_EINVAL;
+  if (J < 0 || J > 5) return fail(c, CEFF_EINVAL, "load index must be in [0, 5]");
+  if (precision != CEFF_PREC_FP64 && precision != CEFF_PREC_MIXED) return fail(c, CEFF_EINVAL, "bad precision");
+  if (!u) return fail(c, CEFF_EINVAL, "u is null");
+  if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  STCK(begin_call(c));
+  const int64_t N = c->nx * c->ny * c->nz;
+  ceff_solve_opts o;
+  ceff_default_opts(&o);
+  auto run = [&](auto tag) -> ceff_status {
+    using T = decltype(tag);
+    Engine<T> e;
+    e.c = c;
+    e.in = {ctx_sample(c)};
+    e.o = o;
+    e.mixed = false;
+    e.Lk = 1;
+    e.Js = {J};
+    STCK(e.setup());
+    DevBuf d64, r, rp, part, nrm;
+    HIPCK(c, d64.alloc(sizeof(double) * 3 * N));
+    HIPCK(c, hipMemcpyAsync(d64.p, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice, c->s));
+    if (sizeof(T) == 8)
+      HIPCK(c, hipMemcpyAsync(e.h_in[0].u[0][0], d64.p, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->s));
+    else
+      HIPCK(c, launch_convert<double, float>(d64.as<double>(), (float*)e.h_in[0].u[0][0], 3 * N, c->s));
+    e.h_in[0].active = 1u;
+    STCK(e.upload_desc());
+    HIPCK(c, r.alloc(sizeof(T) * 3 * N));
+    T* rptr[1] = {r.as<T>()};
+    HIPCK(c, rp.alloc(sizeof rptr));
+    HIPCK(c, hipMemcpyAsync(rp.p, rptr, sizeof rptr, hipMemcpyHostToDevice, c->s));
+    HIPCK(c, launch_residual<T, T, 1>(e.d_in.template as<SampleDesc<T>>(), e.d_work.template as<WorkItem>(),
+                                      (int)e.work.size(), e.ts, 0, rp.as<T*>(), e.d_partials.template as<double>(),
+                                      c->s));
+    HIPCK(c, launch_finalize_norms(e.d_ranges.template as<int>(), 1, e.d_partials.template as<double>(),
+                                   e.d_norms.template as<double>(), c->s));
+    double nn[kMaxLoads];
+    HIPCK(c, hipMemcpyAsync(nn, e.d_norms.p, sizeof nn, hipMemcpyDeviceToHost, c->s));
+    if (r_out) {
+      if (sizeof(T) == 8)
+        HIPCK(c, hipMemcpyAsync(d64.p, r.p, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->s));
+      else
+        HIPCK(c, launch_convert<float, double>((const float*)r.p, d64.as<double>(), 3 * N, c->s));
+      HIPCK(c, hipMemcpyAsync(r_out, d64.p, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c->s));
+    }
+    HIPCK(c, hipStreamSynchronize(c->s));
+    if (norm2) *norm2 = nn[0];
+    return CEFF_OK;
+  };
+  if (precision == CEFF_PREC_MIXED) {
+    STCK(ensure32(c));
+    return run(float{});
+  }
+  return run(double{});
+}
+
+ceff_status ceff_average_stress(ceff_ctx* c, int J, const double* u, double out6[6]) {
+  if (!c) return CEFF_EINVAL;
+  if (J < 0 || J > 5) return fail(c, CEFF_EINVAL, "load index must be in [0, 5]");
+  if (!u || !out6) return fail(c, CEFF_EINVAL, "null argument");
+  if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  STCK(begin_call(c));
+  const int64_t N = c->nx * c->ny * c->nz;
+  DevBuf d;
+  HIPCK(c, d.alloc(sizeof(double) * 3 * N));
+  HIPCK(c, hipMemcpyAsync(d.p, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice, c->s));
+  return stress_average(c, ctx_sample(c), J, d.as<double>(), out6);
+}
+
+ceff_status ceff_get_stats(const ceff_ctx* c, ceff_stats* out) {
+  if (!c || !out) return CEFF_EINVAL;
+  *out = c->stats;
+  return CEFF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal declarations shared by the HIP kernels and the host driver.
+// Not part of the public C ABI (that is include/ceff.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ceff {
+
+constexpr int kMaxLoads = 6;
+
+// One voxel sample as the kernels see it (device-resident table, one entry per
+// sample).  Vector fields are component-major: f[c*N + i + nx*(j + ny*k)].
+template <typename T>
+struct SampleDesc {
+  int64_t nx, ny, nz, N;
+  T rhx, rhy, rhz;            // 1/h per axis
+  T mom;                      // heavy-ball momentum a = 1/(1+c)
+  T sfac;                     // step numerator: u += (sfac / H_face) * r
+  T sfac_first;               // step numerator of the very first iteration (no momentum yet)
+  const T* K;                 // bulk modulus per cell (N)
+  const T* G;                 // shear modulus per cell (N)
+  T* u[2][kMaxLoads];         // two rotating displacement buffers per load (3N each)
+  const T* force[kMaxLoads];  // optional constant body force per load (3N) or nullptr
+  T E[kMaxLoads][6];          // macroscopic tensor strain per load: xx yy zz yz xz xy
+  unsigned active;            // bit l: load l is iterated
+  int work_begin, work_end;   // this sample's work items [begin, end)
+  int tiles_x, tiles_y, chunks_z, kc;  // tiling of this sample
+};
+
+// One block's worth of work: a (tile_x, tile_y, z-chunk) of one sample.
+struct WorkItem {
+  int sample;
+  int tx, ty, kz;
+};
+
+struct TileShape {
+  int bx, by;  // block extent including the one-cell ghost ring (threads = bx*by)
+  int kc;      // z-planes per chunk (0 = choose automatically)
+};
+
+// ---- launch wrappers (ceff_kernels.hip) ----------------------------------------
+
+// One heavy-ball iteration for every active (sample, load).  parity selects which
+// of the two buffers holds u^n (read) and which holds u^{n-1} (read, then
+// overwritten by u^{n+1}).  first != 0 runs the start-up step (no momentum).
+// If partials != nullptr the squared residual of u^n is accumulated per work item
+// and load into partials[w*kMaxLoads + l] (FP64).
+template <typename T, int L>
+hipError_t launch_step(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
+                       int parity, int first, double* partials, hipStream_t s);
+
+// Residual only: r = div(C:(E + grad u^parity)) + force, written as float or T to
+// rout[l] (3N per load, may be nullptr), norms as above.  No update.
+template <typename T, typename R, int L>
+hipError_t launch_residual(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
+                           int parity, R* const* rout, double* partials, hipStream_t s);
+
+// Sum partials of each (sample, load) in fixed order: out[s*kMaxLoads + l].
+hipError_t launch_finalize_norms(const int* d_ranges /* 2 per sample */, int nsamples, const double* partials,
+                                 double* out, hipStream_t s);
+
+// FP64 volume averages of the six stresses of u (3N) under strain E: writes
+// block partials (6 per block) then the final 6 sums (not yet divided by N).
+hipError_t launch_average_stress(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K,
+                                 const double* G, const double E[6], const double* u, double* partials,
+                                 int nblocks_cap, double* out6, hipStream_t s);
+
+// Gradient of sum W_IJ C_IJ with respect to per-voxel K and G from six FP64
+// displacement fields.
+template <typename R>
+hipError_t launch_gradient(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K, const double* G,
+                           const double* const* u6, const double* W36, R* dK, R* dG, hipStream_t s);
+
+// Elementwise helpers.
+template <typename T>
+hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
+template <typename A, typename B>
+hipError_t launch_convert(const A* src, B* dst, int64_t n, hipStream_t s);
+// base += (double)prev; cur -= prev; prev = 0   (fold an FP32 iterate into the FP64 base)
+hipError_t launch_fold(double* base, float* cur, float* prev, int64_t n, hipStream_t s);
+// dst += src (FP64)
+hipError_t launch_axpy1(double* dst, const double* src, int64_t n, hipStream_t s);
+// K, G from a phase image and per-phase tables
+template <typename T>
+hipError_t launch_phase_to_fields(const uint8_t* phase, int64_t n, const double* Ktab, const double* Gtab, int nphase,
+                                  T* K, T* G, hipStream_t s);
+// Per-block flags (1 = some K or G not finite and > 0) into bad[0 .. *nblocks)
+// (bad must hold 65536 ints).
+template <typename T>
+hipError_t launch_check_moduli(const T* K, const T* G, int64_t n, int* bad, int* nblocks, hipStream_t s);
+
+}  // namespace ceff

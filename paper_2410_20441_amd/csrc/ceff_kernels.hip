@@ -1,0 +1,587 @@
+// HIP kernels for gfx950 (MI355X): periodic staggered-grid elasticity on a voxel
+// grid, iterated with the accelerated pseudo-transient (APT) method of the
+// paper ("Numerical solution strategy").
+//
+// The paper updates pressure p, deviator tau and velocity v.  With unit
+// physical time step and pseudo moduli equal to the local moduli (K~ = K,
+// G~ = G), the pressure and deviator relaxations share one factor 1/(1+c),
+// so the stress is an exponential average of Hooke's stress of the current
+// iterate, and eliminating it gives an equivalent two-level recurrence on the
+// displacement alone:
+//
+//     u^{n+1} = u^n + a (u^n - u^{n-1}) + (s / H_f) div( C : (E + grad u^n) ),
+//     a = 1/(1+c),  s = c/(1+c) * ell*Lx/St,  c = ell*St/Lx,
+//
+// with the first step u^1 = (ell*Lx/St / H_f) div(C:E).  This is what runs
+// here: it is the same iterate sequence (to rounding) with 2 displacement
+// buffers instead of 9 stress/velocity fields in ping-pong pairs, so each
+// voxel-update reads u^n (with its halo) and u^{n-1} and writes u^{n+1} in
+// place of u^{n-1}: 9 words of state traffic instead of 18.
+//
+// Step kernel layout: a block covers a (bx-2) x (by-2) tile of one z-range
+// plus a one-cell ring of ghost threads, and marches up the z-range one plane
+// at a time.  Every thread loads its own column's u and moduli; the in-plane
+// neighbours come through LDS; the z neighbours stay in registers.  Stresses
+// are computed once per node by the thread that owns the node (ghost threads
+// compute the halo nodes the tile needs).  Several loads share one launch: the
+// moduli and the derived edge/face coefficients are read once per plane for
+// all of them.  The residual norm is fused into the sweep on check iterations.
+#include "ceff_internal.h"
+
+namespace ceff {
+
+namespace {
+
+__device__ __forceinline__ int64_t wrap_idx(int64_t a, int64_t n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+
+template <typename T>
+__device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+
+// Sum of v over the block; the result is valid on thread 0.  Fixed order
+// (wave shuffle tree, then waves in index order) so it is deterministic.
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += red[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+// MODE 0: heavy-ball update; MODE 1: write the residual to rout.
+template <typename T, int L, int MODE, typename R>
+__global__ void __launch_bounds__(512) step_kernel(const SampleDesc<T>* __restrict__ samples,
+                                                    const WorkItem* __restrict__ work, int nwork, int bx, int by,
+                                                    int parity, int first, double* __restrict__ partials,
+                                                    R* const* __restrict__ rout) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const int nt = blockDim.x;  // multiple of 64, >= bx*by
+  T* sG0 = reinterpret_cast<T*>(smem_raw);
+  T* sG1 = sG0 + nt;
+  T* sH = sG1 + nt;
+  T* sUx = sH + nt;
+  T* sUy = sUx + nt;
+  T* sUz = sUy + nt;
+  T* sSxx = sUz + nt;
+  T* sSyy = sSxx + nt;
+  T* sSxy = sSyy + nt;
+  T* sSxz = sSxy + nt;
+  T* sSyz = sSxz + nt;
+
+  const int tid = threadIdx.x;
+  const int tx = tid % bx, ty = tid / bx;
+  const int TX = bx - 2, TY = by - 2;
+  // LDS neighbours, clamped inside the block (values at clamped ghost
+  // positions are never consumed by interior threads)
+  const int xm = tid > 0 && tx > 0 ? tid - 1 : tid;
+  const int xp = tx < bx - 1 && tid + 1 < nt ? tid + 1 : tid;
+  const int ym = ty > 0 ? tid - bx : tid;
+  const int yp = ty < by - 1 && tid + bx < nt ? tid + bx : tid;
+  const int xmym = ty > 0 ? xm - bx : xm;
+
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const WorkItem wi = work[w];
+    const SampleDesc<T>& sd = samples[wi.sample];
+    const unsigned act = sd.active & ((1u << L) - 1u);
+    if (act == 0u) continue;  // uniform over the block
+    const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N, plane = nx * ny;
+    const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
+    const T mom = first ? T(0) : sd.mom;
+    const T sfac = first ? sd.sfac_first : sd.sfac;
+    const int64_t gi = (int64_t)wi.tx * TX + tx - 1, gj = (int64_t)wi.ty * TY + ty - 1;
+    const int64_t col = wrap_idx(gi, nx) + nx * wrap_idx(gj, ny);
+    const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
+    const int64_t k0 = (int64_t)wi.kz * sd.kc;
+    const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
+
+    const T* __restrict__ Kf = sd.K;
+    const T* __restrict__ Gf = sd.G;
+    const T* ucur[L];
+    T* uold[L];
+    const T* frc[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      ucur[l] = sd.u[parity][l];
+      uold[l] = sd.u[parity ^ 1][l];
+      frc[l] = sd.force[l];
+    }
+
+    // registers carried up the z-march, per load
+    T ux[L], uy[L], uz[L], szz_p[L], sxz_c[L], syz_c[L];
+    double nsum[L];
+    {
+      const int64_t kw = k0 - 1 < 0 ? k0 - 1 + nz : k0 - 1;
+      const int64_t o = col + plane * kw;
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        if (act & (1u << l)) {
+          ux[l] = ucur[l][o];
+          uy[l] = ucur[l][N + o];
+          uz[l] = ucur[l][2 * N + o];
+        } else {
+          ux[l] = uy[l] = uz[l] = T(0);
+        }
+        szz_p[l] = sxz_c[l] = syz_c[l] = T(0);
+        nsum[l] = 0.0;
+      }
+    }
+    T Kc = Kf[col + plane * (k0 - 1 < 0 ? k0 - 1 + nz : k0 - 1)];
+    T Gc = Gf[col + plane * (k0 - 1 < 0 ? k0 - 1 + nz : k0 - 1)];
+    T Hprev = T(1);
+    sG0[tid] = Gc;
+
+    for (int64_t k = k0 - 1; k < k1; ++k) {
+      const int rel = (int)(k - (k0 - 1));
+      const int64_t kw = k < 0 ? k + nz : k;
+      const int64_t kn = k + 1 >= nz ? k + 1 - nz : k + 1;
+      const int64_t oc = col + plane * kw, on = col + plane * kn;
+      const bool face = k >= k0 && interior;
+
+      // global loads for plane k+1 (and u^{n-1} / force at plane k)
+      const T Kn = Kf[on], Gn = Gf[on];
+      T unx[L], uny[L], unz[L], uo0[L], uo1[L], uo2[L], f0[L], f1[L], f2[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        unx[l] = uny[l] = unz[l] = uo0[l] = uo1[l] = uo2[l] = f0[l] = f1[l] = f2[l] = T(0);
+        if (act & (1u << l)) {
+          unx[l] = ucur[l][on];
+          uny[l] = ucur[l][N + on];
+          unz[l] = ucur[l][2 * N + on];
+          if (face) {
+            if (MODE == 0 && !first) {
+              uo0[l] = uold[l][oc];
+              uo1[l] = uold[l][N + oc];
+              uo2[l] = uold[l][2 * N + oc];
+            }
+            if (frc[l] != nullptr) {
+              f0[l] = frc[l][oc];
+              f1[l] = frc[l][N + oc];
+              f2[l] = frc[l][2 * N + oc];
+            }
+          }
+        }
+      }
+
+      T* gk = (rel & 1) ? sG1 : sG0;   // plane k
+      T* gn = (rel & 1) ? sG0 : sG1;   // plane k+1
+      gn[tid] = Gn;
+      const T Hk = Kc + T(4.0 / 3.0) * Gc;
+      sH[tid] = Hk;
+
+      // per-plane coefficients shared by all loads: edge shear moduli (harmonic
+      // mean of the four cells around the edge, times two), Lame lambda, 2G
+      // and the face step factors; computed after the first barrier
+      T G2xy = T(0), G2xz = T(0), G2yz = T(0), sfx = T(0), sfy = T(0), sfz = T(0);
+      const T lam = Kc - T(2.0 / 3.0) * Gc;
+      const T twoG = T(2) * Gc;
+      bool coef = false;
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        if (!(act & (1u << l))) continue;
+        sUx[tid] = ux[l];
+        sUy[tid] = uy[l];
+        sUz[tid] = unz[l];
+        __syncthreads();
+        if (!coef) {
+          G2xy = T(8) / (T(1) / gk[xmym] + T(1) / gk[ym] + T(1) / gk[xm] + T(1) / gk[tid]);
+          G2xz = T(8) / (T(1) / gk[xm] + T(1) / gk[tid] + T(1) / gn[xm] + T(1) / gn[tid]);
+          G2yz = T(8) / (T(1) / gk[ym] + T(1) / gk[tid] + T(1) / gn[ym] + T(1) / gn[tid]);
+          sfx = sfac / tmax(sH[xm], Hk);
+          sfy = sfac / tmax(sH[ym], Hk);
+          sfz = sfac / tmax(Hprev, Hk);
+          coef = true;
+        }
+        const T* E = sd.E[l];
+        // stresses owned by this thread: cell (k), xy-edge (k), xz/yz-edges (k+1)
+        const T exx = E[0] + (sUx[xp] - ux[l]) * rhx;
+        const T eyy = E[1] + (sUy[yp] - uy[l]) * rhy;
+        const T ezz = E[2] + (unz[l] - uz[l]) * rhz;
+        const T th = exx + eyy + ezz;
+        const T sxx = lam * th + twoG * exx;
+        const T syy = lam * th + twoG * eyy;
+        const T szz = lam * th + twoG * ezz;
+        const T sxy = G2xy * (E[5] + T(0.5) * ((ux[l] - sUx[ym]) * rhy + (uy[l] - sUy[xm]) * rhx));
+        const T sxz_n = G2xz * (E[4] + T(0.5) * ((unx[l] - ux[l]) * rhz + (unz[l] - sUz[xm]) * rhx));
+        const T syz_n = G2yz * (E[3] + T(0.5) * ((uny[l] - uy[l]) * rhz + (unz[l] - sUz[ym]) * rhy));
+        sSxx[tid] = sxx;
+        sSyy[tid] = syy;
+        sSxy[tid] = sxy;
+        sSxz[tid] = sxz_c[l];
+        sSyz[tid] = syz_c[l];
+        __syncthreads();
+        if (face) {
+          T rx = (sxx - sSxx[xm]) * rhx + (sSxy[yp] - sxy) * rhy + (sxz_n - sxz_c[l]) * rhz;
+          T ry = (sSxy[xp] - sxy) * rhx + (syy - sSyy[ym]) * rhy + (syz_n - syz_c[l]) * rhz;
+          T rz = (sSxz[xp] - sxz_c[l]) * rhx + (sSyz[yp] - syz_c[l]) * rhy + (szz - szz_p[l]) * rhz;
+          rx += f0[l];
+          ry += f1[l];
+          rz += f2[l];
+          if (partials != nullptr)
+            nsum[l] += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
+          if (MODE == 0) {
+            uold[l][oc] = ux[l] + mom * (ux[l] - uo0[l]) + sfx * rx;
+            uold[l][N + oc] = uy[l] + mom * (uy[l] - uo1[l]) + sfy * ry;
+            uold[l][2 * N + oc] = uz[l] + mom * (uz[l] - uo2[l]) + sfz * rz;
+          } else {
+            R* ro = rout != nullptr ? rout[l] : nullptr;
+            if (ro != nullptr) {
+              ro[oc] = (R)rx;
+              ro[N + oc] = (R)ry;
+              ro[2 * N + oc] = (R)rz;
+            }
+          }
+        }
+        szz_p[l] = szz;
+        sxz_c[l] = sxz_n;
+        syz_c[l] = syz_n;
+        ux[l] = unx[l];
+        uy[l] = uny[l];
+        uz[l] = unz[l];
+      }
+      Kc = Kn;
+      Gc = Gn;
+      Hprev = Hk;
+    }
+
+    if (partials != nullptr) {
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        if (!(act & (1u << l))) continue;
+        const double s = block_sum(nsum[l], red);
+        if (tid == 0) partials[(int64_t)w * kMaxLoads + l] = s;
+      }
+    }
+    __syncthreads();  // LDS is reused by the next work item
+  }
+}
+
+__global__ void finalize_norms_kernel(const int* __restrict__ ranges, const double* __restrict__ partials,
+                                      double* __restrict__ out) {
+  __shared__ double red[16];
+  const int s = blockIdx.x / kMaxLoads, l = blockIdx.x % kMaxLoads;
+  const int b = ranges[2 * s], e = ranges[2 * s + 1];
+  double v = 0.0;
+  for (int w = b + threadIdx.x; w < e; w += blockDim.x) v += partials[(int64_t)w * kMaxLoads + l];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+// ---- FP64 volume averages ----------------------------------------------------
+
+__global__ void average_partials_kernel(int64_t nx, int64_t ny, int64_t nz, double rhx, double rhy, double rhz,
+                                        const double* __restrict__ K, const double* __restrict__ G, double E0,
+                                        double E1, double E2, double E3, double E4, double E5,
+                                        const double* __restrict__ u, double* __restrict__ partials) {
+  __shared__ double red[16];
+  const int64_t N = nx * ny * nz;
+  const double* ux = u;
+  const double* uy = u + N;
+  const double* uz = u + 2 * N;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    const int64_t ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
+    const int64_t jp = j + 1 == ny ? 0 : j + 1, jm = j == 0 ? ny - 1 : j - 1;
+    const int64_t kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
+    auto at = [&](int64_t a, int64_t b, int64_t d) { return a + nx * (b + ny * d); };
+    const double exx = E0 + (ux[at(ip, j, k)] - ux[c]) * rhx;
+    const double eyy = E1 + (uy[at(i, jp, k)] - uy[c]) * rhy;
+    const double ezz = E2 + (uz[at(i, j, kp)] - uz[c]) * rhz;
+    const double th = exx + eyy + ezz;
+    const double lam = K[c] - 2.0 / 3.0 * G[c];
+    acc[0] += lam * th + 2.0 * G[c] * exx;
+    acc[1] += lam * th + 2.0 * G[c] * eyy;
+    acc[2] += lam * th + 2.0 * G[c] * ezz;
+    const double gc = 1.0 / G[c];
+    const double gyz = 8.0 / (gc + 1.0 / G[at(i, jm, k)] + 1.0 / G[at(i, j, km)] + 1.0 / G[at(i, jm, km)]);
+    const double gxz = 8.0 / (gc + 1.0 / G[at(im, j, k)] + 1.0 / G[at(i, j, km)] + 1.0 / G[at(im, j, km)]);
+    const double gxy = 8.0 / (gc + 1.0 / G[at(im, j, k)] + 1.0 / G[at(i, jm, k)] + 1.0 / G[at(im, jm, k)]);
+    acc[3] += gyz * (E3 + 0.5 * ((uy[c] - uy[at(i, j, km)]) * rhz + (uz[c] - uz[at(i, jm, k)]) * rhy));
+    acc[4] += gxz * (E4 + 0.5 * ((ux[c] - ux[at(i, j, km)]) * rhz + (uz[c] - uz[at(im, j, k)]) * rhx));
+    acc[5] += gxy * (E5 + 0.5 * ((ux[c] - ux[at(i, jm, k)]) * rhy + (uy[c] - uy[at(im, j, k)]) * rhx));
+  }
+  for (int q = 0; q < 6; ++q) {
+    const double s = block_sum(acc[q], red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * 6 + q] = s;
+  }
+}
+
+__global__ void average_finalize_kernel(const double* __restrict__ partials, int nblocks, double* __restrict__ out6) {
+  __shared__ double red[16];
+  const int q = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partials[(int64_t)b * 6 + q];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) out6[q] = v;
+}
+
+// ---- gradient of sum W_IJ C_IJ ------------------------------------------------
+
+template <typename R>
+__global__ void gradient_kernel(int64_t nx, int64_t ny, int64_t nz, double rhx, double rhy, double rhz,
+                                const double* __restrict__ K, const double* __restrict__ G,
+                                const double* const* __restrict__ u6, const double* __restrict__ W,
+                                R* __restrict__ dK, R* __restrict__ dG) {
+  const int64_t N = nx * ny * nz;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  (void)K;
+  const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+  auto wr = [](int64_t a, int64_t n) { return a >= n ? a - n : (a < 0 ? a + n : a); };
+  auto at = [&](int64_t a, int64_t b, int64_t d) { return wr(a, nx) + nx * (wr(b, ny) + ny * wr(d, nz)); };
+  // the twelve edges touching cell c: (orientation, di, dj, dk); orientation
+  // 0 = yz, 1 = xz, 2 = xy (Voigt 4, 5, 6)
+  const int eo[12][4] = {{2, 0, 0, 0}, {2, 1, 0, 0}, {2, 0, 1, 0}, {2, 1, 1, 0}, {1, 0, 0, 0}, {1, 1, 0, 0},
+                         {1, 0, 0, 1}, {1, 1, 0, 1}, {0, 0, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}, {0, 0, 1, 1}};
+  double qe[12];
+  int64_t ei[12];
+  for (int e = 0; e < 12; ++e) {
+    const int64_t a = i + eo[e][1], b = j + eo[e][2], d = k + eo[e][3];
+    double s;
+    if (eo[e][0] == 0)
+      s = 1.0 / G[at(a, b, d)] + 1.0 / G[at(a, b - 1, d)] + 1.0 / G[at(a, b, d - 1)] + 1.0 / G[at(a, b - 1, d - 1)];
+    else if (eo[e][0] == 1)
+      s = 1.0 / G[at(a, b, d)] + 1.0 / G[at(a - 1, b, d)] + 1.0 / G[at(a, b, d - 1)] + 1.0 / G[at(a - 1, b, d - 1)];
+    else
+      s = 1.0 / G[at(a, b, d)] + 1.0 / G[at(a - 1, b, d)] + 1.0 / G[at(a, b - 1, d)] + 1.0 / G[at(a - 1, b - 1, d)];
+    const double Ge = 4.0 / s;
+    qe[e] = (Ge / G[c]) * (Ge / G[c]);
+    ei[e] = at(a, b, d);
+  }
+  double th[6], dv[6][3], es[6][12];
+  for (int J = 0; J < 6; ++J) {
+    const double* u = u6[J];
+    if (u == nullptr) continue;
+    const double* ux = u;
+    const double* uy = u + N;
+    const double* uz = u + 2 * N;
+    const double Ev[6] = {J == 0 ? 1.0 : 0.0, J == 1 ? 1.0 : 0.0, J == 2 ? 1.0 : 0.0,
+                          J == 3 ? 0.5 : 0.0, J == 4 ? 0.5 : 0.0, J == 5 ? 0.5 : 0.0};
+    const double exx = Ev[0] + (ux[at(i + 1, j, k)] - ux[c]) * rhx;
+    const double eyy = Ev[1] + (uy[at(i, j + 1, k)] - uy[c]) * rhy;
+    const double ezz = Ev[2] + (uz[at(i, j, k + 1)] - uz[c]) * rhz;
+    th[J] = exx + eyy + ezz;
+    dv[J][0] = exx - th[J] / 3.0;
+    dv[J][1] = eyy - th[J] / 3.0;
+    dv[J][2] = ezz - th[J] / 3.0;
+    for (int e = 0; e < 12; ++e) {
+      const int64_t a = i + eo[e][1], b = j + eo[e][2], d = k + eo[e][3];
+      const int64_t o = ei[e];
+      double eps;
+      if (eo[e][0] == 0)
+        eps = Ev[3] + 0.5 * ((uy[o] - uy[at(a, b, d - 1)]) * rhz + (uz[o] - uz[at(a, b - 1, d)]) * rhy);
+      else if (eo[e][0] == 1)
+        eps = Ev[4] + 0.5 * ((ux[o] - ux[at(a, b, d - 1)]) * rhz + (uz[o] - uz[at(a - 1, b, d)]) * rhx);
+      else
+        eps = Ev[5] + 0.5 * ((ux[o] - ux[at(a, b - 1, d)]) * rhy + (uy[o] - uy[at(a - 1, b, d)]) * rhx);
+      es[J][e] = eps;
+    }
+  }
+  double gk = 0.0, gg = 0.0;
+  for (int I = 0; I < 6; ++I) {
+    if (u6[I] == nullptr) continue;
+    for (int J = 0; J < 6; ++J) {
+      const double w = W[I * 6 + J];
+      if (w == 0.0 || u6[J] == nullptr) continue;
+      gk += w * th[I] * th[J];
+      double dev = dv[I][0] * dv[J][0] + dv[I][1] * dv[J][1] + dv[I][2] * dv[J][2];
+      double ed = 0.0;
+      for (int e = 0; e < 12; ++e) ed += qe[e] * es[I][e] * es[J][e];
+      gg += w * (2.0 * dev + ed);
+    }
+  }
+  dK[c] = (R)(gk / (double)N);
+  dG[c] = (R)(gg / (double)N);
+}
+
+// ---- elementwise helpers ---------------------------------------------------------
+
+template <typename T>
+__global__ void fill_kernel(T* p, int64_t n, T v) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+template <typename A, typename B>
+__global__ void convert_kernel(const A* __restrict__ src, B* __restrict__ dst, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = (B)src[t];
+}
+
+__global__ void fold_kernel(double* __restrict__ base, float* __restrict__ cur, float* __restrict__ prev, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const float p = prev[t];
+    base[t] += (double)p;
+    cur[t] = cur[t] - p;
+    prev[t] = 0.0f;
+  }
+}
+
+__global__ void axpy1_kernel(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] += src[t];
+}
+
+template <typename T>
+__global__ void phase_kernel(const uint8_t* __restrict__ ph, int64_t n, const double* __restrict__ Kt,
+                             const double* __restrict__ Gt, int nphase, T* __restrict__ K, T* __restrict__ G) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    int p = ph[t];
+    if (p >= nphase) p = nphase - 1;  // validated on the host before launch
+    K[t] = (T)Kt[p];
+    G[t] = (T)Gt[p];
+  }
+}
+
+// per-block count of moduli that are not finite and positive
+template <typename T>
+__global__ void check_moduli_kernel(const T* __restrict__ K, const T* __restrict__ G, int64_t n, int* bad) {
+  __shared__ double red[16];
+  double cnt = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const T a = K[t], b = G[t];
+    if (!(a > T(0)) || !(b > T(0)) || !(a < T(1e300)) || !(b < T(1e300))) cnt += 1.0;
+  }
+  cnt = block_sum(cnt, red);
+  if (threadIdx.x == 0) bad[blockIdx.x] = cnt > 0.0 ? 1 : 0;
+}
+
+inline int grid_for(int64_t n, int block = 256) {
+  int64_t g = (n + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+// ---- launch wrappers -------------------------------------------------------------
+
+template <typename T, int L>
+hipError_t launch_step(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts, int parity,
+                       int first, double* partials, hipStream_t s) {
+  const int nt = ((ts.bx * ts.by + 63) / 64) * 64;
+  const size_t lds = (size_t)11 * nt * sizeof(T);
+  hipLaunchKernelGGL((step_kernel<T, L, 0, T>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork, ts.bx,
+                     ts.by, parity, first, partials, (T* const*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T, typename R, int L>
+hipError_t launch_residual(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
+                           int parity, R* const* rout, double* partials, hipStream_t s) {
+  const int nt = ((ts.bx * ts.by + 63) / 64) * 64;
+  const size_t lds = (size_t)11 * nt * sizeof(T);
+  hipLaunchKernelGGL((step_kernel<T, L, 1, R>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork, ts.bx,
+                     ts.by, parity, 0, partials, rout);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_norms(const int* d_ranges, int nsamples, const double* partials, double* out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(finalize_norms_kernel, dim3(nsamples * kMaxLoads), dim3(256), 0, s, d_ranges, partials, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_average_stress(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K,
+                                 const double* G, const double E[6], const double* u, double* partials,
+                                 int nblocks_cap, double* out6, hipStream_t s) {
+  int nb = grid_for(nx * ny * nz, 256);
+  if (nb > nblocks_cap) nb = nblocks_cap;
+  hipLaunchKernelGGL(average_partials_kernel, dim3(nb), dim3(256), 0, s, nx, ny, nz, 1.0 / h[0], 1.0 / h[1],
+                     1.0 / h[2], K, G, E[0], E[1], E[2], E[3], E[4], E[5], u, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(average_finalize_kernel, dim3(6), dim3(256), 0, s, partials, nb, out6);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_gradient(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K, const double* G,
+                           const double* const* u6, const double* W36, R* dK, R* dG, hipStream_t s) {
+  const int64_t N = nx * ny * nz;
+  hipLaunchKernelGGL((gradient_kernel<R>), dim3((unsigned)((N + 127) / 128)), dim3(128), 0, s, nx, ny, nz,
+                     1.0 / h[0], 1.0 / h[1], 1.0 / h[2], K, G, u6, W36, dK, dG);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s) {
+  hipLaunchKernelGGL((fill_kernel<T>), dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+template <typename A, typename B>
+hipError_t launch_convert(const A* src, B* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((convert_kernel<A, B>), dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold(double* base, float* cur, float* prev, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fold_kernel, dim3(grid_for(n)), dim3(256), 0, s, base, cur, prev, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy1(double* dst, const double* src, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(axpy1_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_phase_to_fields(const uint8_t* phase, int64_t n, const double* Ktab, const double* Gtab, int nphase,
+                                  T* K, T* G, hipStream_t s) {
+  hipLaunchKernelGGL((phase_kernel<T>), dim3(grid_for(n)), dim3(256), 0, s, phase, n, Ktab, Gtab, nphase, K, G);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_check_moduli(const T* K, const T* G, int64_t n, int* bad, int* nblocks, hipStream_t s) {
+  const int g = grid_for(n);
+  *nblocks = g;
+  hipLaunchKernelGGL((check_moduli_kernel<T>), dim3(g), dim3(256), 0, s, K, G, n, bad);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+#define CEFF_INST_STEP(T, L)                                                                                       \
+  template hipError_t launch_step<T, L>(const SampleDesc<T>*, const WorkItem*, int, TileShape, int, int, double*, \
+                                        hipStream_t);
+CEFF_INST_STEP(float, 1)
+CEFF_INST_STEP(float, 6)
+CEFF_INST_STEP(double, 1)
+CEFF_INST_STEP(double, 6)
+#define CEFF_INST_RES(T, R, L)                                                                              \
+  template hipError_t launch_residual<T, R, L>(const SampleDesc<T>*, const WorkItem*, int, TileShape, int, \
+                                               R* const*, double*, hipStream_t);
+CEFF_INST_RES(double, float, 1)
+CEFF_INST_RES(double, float, 6)
+CEFF_INST_RES(double, double, 1)
+CEFF_INST_RES(double, double, 6)
+CEFF_INST_RES(float, float, 1)
+CEFF_INST_RES(float, float, 6)
+template hipError_t launch_gradient<float>(int64_t, int64_t, int64_t, const double*, const double*, const double*,
+                                           const double* const*, const double*, float*, float*, hipStream_t);
+template hipError_t launch_gradient<double>(int64_t, int64_t, int64_t, const double*, const double*, const double*,
+                                            const double* const*, const double*, double*, double*, hipStream_t);
+template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
+template hipError_t launch_fill<double>(double*, int64_t, double, hipStream_t);
+template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template hipError_t launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+template hipError_t launch_phase_to_fields<double>(const uint8_t*, int64_t, const double*, const double*, int,
+                                                   double*, double*, hipStream_t);
+template hipError_t launch_phase_to_fields<float>(const uint8_t*, int64_t, const double*, const double*, int, float*,
+                                                  float*, hipStream_t);
+template hipError_t launch_check_moduli<double>(const double*, const double*, int64_t, int*, int*, hipStream_t);
+template hipError_t launch_check_moduli<float>(const float*, const float*, int64_t, int*, int*, hipStream_t);
+
+}  // namespace ceff

@@ -1,0 +1,67 @@
+"""The C ABI library loads and exports every entry point declared in
+include/ceff.h; calls that need no device fail cleanly (CPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "ceff.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ceff_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for n in ("ceff_create", "ceff_destroy", "ceff_set_grid", "ceff_set_isotropic", "ceff_set_phases",
+              "ceff_solve", "ceff_solve_batch", "ceff_gradient", "ceff_apt_steps", "ceff_residual",
+              "ceff_average_stress", "ceff_get_stats", "ceff_last_error", "ceff_default_opts"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2410_20441_amd import _lib
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    for n in declared_symbols():
+        assert hasattr(L, n), n
+    assert set(declared_symbols()) == set(_lib.SIGNATURES)
+
+
+def test_binding_has_same_names():
+    import paper_2410_20441_amd as p
+    for n in declared_symbols():
+        assert callable(getattr(p, n)), n
+
+
+def test_defaults():
+    import paper_2410_20441_amd as p
+    o = p.ceff_default_opts()
+    assert o.precision == p.CEFF_PREC_MIXED and o.rtol == 1e-8 and o.check_every == 100
+    assert 0 < o.courant <= 1 and o.strouhal > 0 and o.fuse_loads == 1
+
+
+def test_null_context_is_rejected():
+    from paper_2410_20441_amd import _lib
+    L = _lib.load()
+    assert L.ceff_set_grid(None, 4, 4, 4, 1.0, 1.0, 1.0) == _lib.CEFF_EINVAL
+    assert L.ceff_solve(None, 1, None, None, None, 0, None, None) == _lib.CEFF_EINVAL
+    assert L.ceff_gradient(None, None, None, None, 0, 0) == _lib.CEFF_EINVAL
+    assert L.ceff_get_stats(None, None) == _lib.CEFF_EINVAL
+    assert L.ceff_last_error(None) == b"null context"
+    L.ceff_destroy(None)
+    assert L.ceff_create(0, None, None) == _lib.CEFF_EINVAL
+
+
+def test_create_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    from paper_2410_20441_amd import _lib
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    assert L.ceff_create(0, None, ctypes.byref(h)) == _lib.CEFF_EDEVICE
+    assert not h.value

@@ -1,0 +1,207 @@
+"""End-to-end parity of C* from the HIP path with the CPU oracle (GPU)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import oracle
+import synth
+from gpu_common import announce, matrix_rel, need_gpu
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def sphere32():
+    m = synth.workload_sphere32()
+    K, G = m.fields()
+    C, info = oracle.ceff(K, G, rtol=1e-11)
+    return K, G, C
+
+
+@pytest.mark.parametrize("precision,fuse", [("fp64", False), ("fp64", True), ("mixed", True), ("mixed", False)])
+def test_sphere32_matches_oracle(sphere32, precision, fuse):
+    p = need_gpu()
+    K, G, Co = sphere32
+    announce("sphere32", precision, fuse)
+    C, info = p.solve(K, G, precision=precision, fuse_loads=fuse, rtol=1e-8)
+    assert info["status"] == 0
+    assert matrix_rel(C, Co) <= 1e-6, matrix_rel(C, Co)
+    assert np.all(info["iters"] > 0)
+
+
+@pytest.mark.parametrize("shape,seed", [((13, 11, 9), 1), ((70, 6, 7), 2), ((5, 17, 30), 3)])
+def test_random_fields_match_oracle(shape, seed):
+    p = need_gpu()
+    K, G = synth.random_fields(shape, seed, lo=(2.0, 1.0), hi=(90.0, 45.0))
+    Co, _ = oracle.ceff(K, G, rtol=1e-12)
+    for prec in ("fp64", "mixed"):
+        announce("random", shape, prec)
+        C, info = p.solve(K, G, precision=prec, rtol=1e-9)
+        assert matrix_rel(C, Co) <= 1e-6
+
+
+def test_anisotropic_spacing_matches_oracle():
+    p = need_gpu()
+    K, G = synth.random_fields((9, 12, 10), 4, lo=(5.0, 2.0), hi=(80.0, 40.0))
+    h = (1.0, 0.6, 1.7)
+    Co, _ = oracle.ceff(K, G, h=h, rtol=1e-12)
+    C, _ = p.solve(K, G, h=h, precision="fp64", rtol=1e-9)
+    assert matrix_rel(C, Co) <= 1e-6
+
+
+def test_homogeneous_is_exact_without_iterations():
+    p = need_gpu()
+    K = np.full((6, 7, 8), 70.0); G = np.full((6, 7, 8), 32.0)
+    for prec in ("fp64", "mixed"):
+        C, info = p.solve(K, G, precision=prec)
+        np.testing.assert_allclose(C, cf.c_iso(70.0, 32.0), rtol=1e-14, atol=1e-12)
+        assert np.all(info["iters"] == 0)
+
+
+def test_paper_layered_model_full_size():
+    """Model 1 geometry at its full 191^3 size, six loads fused, mixed precision:
+    Backus exactly (periodic), the analytic column to the printed digits."""
+    p = need_gpu()
+    g = json.load(open(os.path.join(GOLD, "table2_layered.json")))
+    geo = g["geometry"]
+    st, so = g["layers"]["stiff"], g["layers"]["soft"]
+    m = synth.laminate_z(191, 191, 191, geo["stiff_layers"], geo["layer_thickness"],
+                         stiff=(st["K"], st["G"]), soft=(so["K"], so["G"]))
+    announce("laminate 191^3")
+    ctx = p.Context()
+    ctx.set_phases(m.phase, m.K_tab, m.G_tab)
+    C, info = ctx.solve(precision="mixed", rtol=1e-8)
+    ctx.close()
+    f = m.info["f_stiff"]
+    Cb = cf.backus_z([f, 1 - f], [st["K"], so["K"]], [st["G"], so["G"]])
+    assert matrix_rel(C, Cb) <= 1e-6
+    idx = {"C11": (0, 0), "C22": (1, 1), "C33": (2, 2), "C44": (3, 3), "C55": (4, 4), "C66": (5, 5),
+           "C12": (0, 1), "C13": (0, 2), "C23": (1, 2)}
+    for name, val in g["analytic_GPa"].items():
+        assert round(C[idx[name]], 3) == pytest.approx(val, abs=1e-12), name
+
+
+def test_hill_identity_full_size():
+    """191^3 sphere pack with one shear modulus: Hill's exact bulk response."""
+    p = need_gpu()
+    m = synth.workload_spheres191()
+    K, G = m.fields()
+    G[:] = 32.0
+    announce("hill 191^3")
+    C, info = p.solve(K, G, loads=range(3), precision="mixed", rtol=1e-8)
+    assert C[:3, :3].sum() / 9.0 == pytest.approx(cf.hill_uniform_shear(K, G), rel=1e-6)
+
+
+def test_graph_and_direct_launches_agree():
+    p = need_gpu()
+    K, G = synth.random_fields((20, 18, 16), 11, lo=(2.0, 1.0), hi=(90.0, 45.0))
+    Ca, ia = p.solve(K, G, precision="fp64", use_graph=True, rtol=1e-9)
+    Cb, ib = p.solve(K, G, precision="fp64", use_graph=False, rtol=1e-9)
+    assert np.array_equal(Ca, Cb)
+    assert np.array_equal(ia["iters"], ib["iters"])
+
+
+def test_batch_matches_per_sample_oracle():
+    p = need_gpu()
+    shapes = [(12, 12, 12), (10, 14, 9), (16, 8, 11), (7, 7, 20)]
+    samples = [synth.random_fields(s, 20 + i, lo=(2.0, 1.0), hi=(90.0, 45.0)) for i, s in enumerate(shapes)]
+    for prec in ("fp64", "mixed"):
+        announce("batch", prec)
+        C, it, info = p.solve_batch(samples, precision=prec, rtol=1e-9)
+        for s, (K, G) in enumerate(samples):
+            Co, _ = oracle.ceff(K, G, rtol=1e-12)
+            assert matrix_rel(C[s], Co) <= 1e-6, (prec, s)
+        assert np.all(it > 0)
+
+
+def test_batch_mixed_phases_and_sizes():
+    p = need_gpu()
+    ms = [synth.gaussian_field_three_phase(n, 0xC4 + i) for i, n in enumerate((16, 20))]
+    samples = [m.fields() for m in ms]
+    C, it, info = p.solve_batch(samples, precision="mixed", rtol=1e-8)
+    for s, (K, G) in enumerate(samples):
+        Co, _ = oracle.ceff(K, G, rtol=1e-11)
+        assert matrix_rel(C[s], Co) <= 1e-6
+
+
+def test_gradient_matches_oracle():
+    p = need_gpu()
+    m = synth.workload_grad16()
+    K, G = m.fields()
+    Co, info, fields = oracle.ceff(K, G, rtol=1e-12, return_fields=True)
+    W = np.zeros((6, 6)); W[0, 0] = 1.0; W[3, 3] = 0.5; W += np.eye(6) * 0.25
+    dKo, dGo = oracle.gradient(K, G, fields, W)
+    with p.Context() as c:
+        c.set_material(K, G)
+        C, _ = c.solve(precision="fp64", rtol=1e-11, keep_fields=True)
+        dK, dG = c.gradient(W, out_dtype="float64")
+    assert np.max(np.abs(dK - dKo)) <= 1e-6 * np.abs(dKo).max()
+    assert np.max(np.abs(dG - dGo)) <= 1e-6 * np.abs(dGo).max()
+    # Euler homogeneity of degree one
+    J = float(np.sum(W * C))
+    assert float(np.sum(K * dK + G * dG)) == pytest.approx(J, rel=1e-7)
+
+
+def test_autograd_function():
+    p = need_gpu()
+    import torch
+    K, G = synth.random_fields((10, 9, 8), 31, lo=(5.0, 2.0), hi=(80.0, 40.0))
+    Kt = torch.tensor(K, device="cuda", requires_grad=True)
+    Gt = torch.tensor(G, device="cuda", requires_grad=True)
+    C = p.EffectiveStiffness.apply(Kt, Gt, {"precision": "fp64", "rtol": 1e-11})
+    (C[0, 0] + C[3, 3]).backward()
+    Co, info, fields = oracle.ceff(K, G, rtol=1e-12, return_fields=True)
+    W = np.zeros((6, 6)); W[0, 0] = 1; W[3, 3] = 1
+    dKo, dGo = oracle.gradient(K, G, fields, W)
+    assert np.max(np.abs(Kt.grad.cpu().numpy() - dKo)) <= 1e-6 * np.abs(dKo).max()
+    assert np.max(np.abs(Gt.grad.cpu().numpy() - dGo)) <= 1e-6 * np.abs(dGo).max()
+
+
+def test_error_paths():
+    p = need_gpu()
+    import ctypes
+    from paper_2410_20441_amd import _lib
+    L = _lib.load()
+    c = p.Context()
+    h = c.h
+    o = p.make_opts()
+    C = np.zeros(36)
+    dp = C.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.ceff_solve(h, 0x3F, ctypes.byref(o), dp, None, 0, None, None) == _lib.CEFF_ESTATE
+    assert L.ceff_set_grid(h, 1, 4, 4, 1.0, 1.0, 1.0) == _lib.CEFF_EINVAL
+    assert L.ceff_set_grid(h, 4, 4, 4, 1.0, -1.0, 1.0) == _lib.CEFF_EINVAL
+    assert L.ceff_set_grid(h, 4, 4, 4, 1.0, 1.0, 1.0) == 0
+    bad = np.full(64, 70.0); bad[5] = np.nan
+    good = np.full(64, 32.0)
+    assert L.ceff_set_isotropic(h, bad.ctypes.data, good.ctypes.data, 1, 0) == _lib.CEFF_EINVAL
+    neg = np.full(64, 32.0); neg[3] = -1.0
+    assert L.ceff_set_isotropic(h, good.ctypes.data, neg.ctypes.data, 1, 0) == _lib.CEFF_EINVAL
+    ph = np.zeros(64, np.uint8); ph[7] = 3
+    kt = np.array([70.0, 2.2]); gt = np.array([32.0, 1e-3])
+    dkt = kt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)); dgt = gt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.ceff_set_phases(h, ph.ctypes.data, 0, 2, dkt, dgt) == _lib.CEFF_EINVAL
+    assert L.ceff_set_stiffness(h, None, 21, 1, 0) == _lib.CEFF_EUNSUPPORTED
+    K, G = synth.random_fields((4, 4, 4), 1)
+    assert L.ceff_set_isotropic(h, K.ctypes.data, G.ctypes.data, 1, 0) == 0
+    for field, val in (("courant", 1.5), ("rtol", -1.0), ("check_every", 0), ("strouhal", 0.0),
+                       ("precision", 7), ("max_iter", 0)):
+        o2 = p.make_opts()
+        setattr(o2, field, val)
+        assert L.ceff_solve(h, 0x3F, ctypes.byref(o2), dp, None, 0, None, None) == _lib.CEFF_EINVAL, field
+    assert L.ceff_solve(h, 0, ctypes.byref(o), dp, None, 0, None, None) == _lib.CEFF_EINVAL
+    assert L.ceff_solve(h, 0x40, ctypes.byref(o), dp, None, 0, None, None) == _lib.CEFF_EINVAL
+    W = np.eye(6)
+    dK = np.zeros(64); dG = np.zeros(64)
+    assert L.ceff_gradient(h, W.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), dK.ctypes.data, dG.ctypes.data,
+                           1, 0) == _lib.CEFF_ESTATE
+    # max_iter forces non-convergence; C is still filled
+    o3 = p.make_opts(precision="fp64", max_iter=2, check_every=2)
+    st = L.ceff_solve(h, 0x1, ctypes.byref(o3), dp, None, 0, None, None)
+    assert st == _lib.CEFF_ENOTCONV
+    assert np.all(np.isfinite(C.reshape(6, 6)[:, 0]))
+    assert "max_iter" in p.ceff_last_error(h)
+    c.close()
