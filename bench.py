@@ -36,6 +36,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle APT iterations timed for the CPU baseline")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=400000)
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for counter collection: allow stopping at --max-iter")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy a buffer of this many MiB three times (a plain copy kernel of known size "
+                         "against which HBM byte counters are scaled)")
     return ap.parse_args()
 
 
@@ -57,10 +63,21 @@ def main():
     N = m.phase.size
     print(f"# workload {m.info}", file=sys.stderr, flush=True)
 
+    if a.calibrate_copy:
+        nb = a.calibrate_copy * (1 << 20)
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        print(f"# copy calibration: {nb} bytes read and {nb} bytes written per copy kernel", file=sys.stderr,
+              flush=True)
+        del src, dst
+
     ctx = ceff.Context(0)
     ctx.set_phases(m.phase, m.K_tab, m.G_tab)
     opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, fuse_loads=True,
-                use_graph=True, autotune=a.autotune, max_iter=400000)
+                use_graph=True, autotune=a.autotune, max_iter=a.max_iter, allow_unconverged=a.profile_run)
 
     for w in range(a.warmup):
         C, info = ctx.solve(**opts)
@@ -80,9 +97,10 @@ def main():
         tot["step_bytes"] += st["step_bytes"]
         tot["launches"] += st["step_launches"]
         Cs.append(C)
-        print(f"# step {k}: iters {info['iters'].tolist()} solve {st['solve_ms']:.1f} ms, kernel "
-              f"{st['step_time_ms'] / max(st['step_launches'], 1):.4f} ms/launch, tile {st['tile_bx']}x"
-              f"{st['tile_by']}x{st['tile_kc']}", file=sys.stderr, flush=True)
+        print(f"# step {k}: status {info['status']} iters {info['iters'].tolist()} solve {st['solve_ms']:.1f} ms, "
+              f"kernel {st['step_time_ms'] / max(st['step_launches'], 1):.4f} ms/launch, tile {st['tile_bx']}x"
+              f"{st['tile_by']}x{st['tile_kc']} group {st['tile_group']} prefetch {st['tile_prefetch']}",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t0
     C = Cs[-1]
@@ -110,7 +128,7 @@ def main():
         "iterations_per_solve": tot["iters"] / a.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "step_kernel<float,6> (heavy-ball APT iteration)",
+                     "kernel": "step_kernel<float,L,0> (heavy-ball APT iteration, L loads per block)",
                      "avg_launch_ms": tot["step_ms"] / max(tot["launches"], 1),
                      "bytes_per_launch": tot["step_bytes"] / max(tot["launches"], 1)},
         "C_eff_GPa": np.round(C, 6).tolist(),
@@ -119,6 +137,8 @@ def main():
     if not a.no_fp64_baseline:
         t1 = time.perf_counter()
         C64, info64 = ctx.solve(**dict(opts, precision="fp64", fuse_loads=False))
+        if info64["status"] != 0:
+            print(f"# fp64 single-load status {info64['status']}", file=sys.stderr, flush=True)
         t64 = time.perf_counter() - t1
         st64 = info64["stats"]
         out["fp64_single_load"] = {

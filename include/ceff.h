@@ -82,6 +82,8 @@ typedef struct {
   int64_t outer_checks;    /* FP64 residual evaluations */
   double solve_ms;         /* host wall time of the solve call */
   int tile_bx, tile_by, tile_kc;  /* tile shape used (block extent incl. ghosts, z-chunk) */
+  int tile_group;          /* loads per block */
+  int tile_prefetch;       /* 1 if the next plane is prefetched into registers */
 } ceff_stats;
 
 /* Fill *o with the defaults: MIXED, rtol 1e-8, max_iter 2e6, check_every 100,

@@ -32,7 +32,8 @@ class ceff_stats(ctypes.Structure):
     _fields_ = [("step_launches", ctypes.c_int64), ("step_time_ms", ctypes.c_double),
                 ("step_bytes", ctypes.c_double), ("voxel_updates", ctypes.c_double),
                 ("outer_checks", ctypes.c_int64), ("solve_ms", ctypes.c_double),
-                ("tile_bx", ctypes.c_int), ("tile_by", ctypes.c_int), ("tile_kc", ctypes.c_int)]
+                ("tile_bx", ctypes.c_int), ("tile_by", ctypes.c_int), ("tile_kc", ctypes.c_int),
+                ("tile_group", ctypes.c_int), ("tile_prefetch", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p
@@ -65,9 +66,17 @@ _lib = None
 
 
 def load():
-    """Load libceff.so (built in-tree by paper_2410_20441_amd/build.py)."""
+    """Load libceff.so (built in-tree by paper_2410_20441_amd/build.py).
+
+    torch is imported first: torch ships its own HIP runtime with the same
+    soname as the system one, and whichever is loaded first serves the whole
+    process; loading torch's first keeps one runtime for both."""
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
                               f"g.build()'` (hipcc, gfx950); there is no fallback path")

@@ -221,15 +221,22 @@ TileShape default_tile(int64_t nx, int64_t ny, bool fp64) {
   TileShape t;
   (void)fp64;
   // CEFF_TILE="bx,by[,kc]" overrides the shape (tests check results do not depend on it)
+  // CEFF_TILE="bx,by[,kc[,group[,prefetch]]]" overrides the launch shape
   if (const char* env = std::getenv("CEFF_TILE")) {
-    int bx = 0, by = 0, kc = 0;
-    const int n = std::sscanf(env, "%d,%d,%d", &bx, &by, &kc);
-    if (n >= 2 && bx >= 3 && by >= 3 && ((bx * by + 63) / 64) * 64 <= 512) return TileShape{bx, by, n == 3 ? kc : 0};
+    int bx = 0, by = 0, kc = 0, grp = 6, pf = 1, ord = 1;
+    const int n = std::sscanf(env, "%d,%d,%d,%d,%d,%d", &bx, &by, &kc, &grp, &pf, &ord);
+    if (n >= 2 && bx >= 3 && by >= 3 && ((bx * by + 63) / 64) * 64 <= 512 &&
+        (grp == 1 || grp == 2 || grp == 3 || grp == 6))
+      return TileShape{bx, by, n >= 3 ? kc : 0, grp, pf ? 1 : 0, ord ? 1 : 0};
   }
-  t.bx = nx + 2 <= 66 ? (int)nx + 2 : 66;
-  t.by = 6;  // 66 x 6 ghosted block: 64 x 4 interior, 448 threads (<= the kernel's 512 bound)
-  if (ny + 2 < t.by) t.by = (int)ny + 2;
+  // 34 x 14 ghosted block (32 x 12 interior, 476 of 512 threads), two loads per
+  // block, XCD bands: the fastest shape of the 191^3 sweeps (see the tuner)
+  t.bx = nx + 2 <= 34 ? (int)nx + 2 : 34;
+  t.by = ny + 2 <= 14 ? (int)ny + 2 : 14;
   t.kc = 0;
+  t.group = 2;
+  t.pf = 0;
+  t.order = 1;
   return t;
 }
 
@@ -239,17 +246,17 @@ struct Engine {
   std::vector<SampleIn> in;
   ceff_solve_opts o;
   bool mixed;
-  int Lk;                       // compiled load count of the kernels (1 or 6)
+  int Lk;                       // 1: one load (slot 0); otherwise slot J holds load J
   std::vector<int> Js;          // requested loads
   TileShape ts{};
   // device
   std::vector<std::array<DevBuf, 2 * kMaxLoads>> ubuf;  // per sample: u[b][slot] at index b*6+slot
   std::vector<std::array<DevBuf, kMaxLoads>> base, force;
-  DevBuf d_in, d_out, d_work, d_partials, d_norms, d_ranges, d_rout;
+  DevBuf d_in, d_out, d_work, d_work_o, d_partials, d_norms, d_ranges, d_ranges_o, d_rout;
   std::vector<SampleDesc<T>> h_in;
   std::vector<SampleDesc<double>> h_out;
-  std::vector<WorkItem> work;
-  std::vector<int> ranges;
+  std::vector<WorkItem> work, work_o;  // iteration launches / FP64 residual launches
+  std::vector<int> ranges, ranges_o;
   std::vector<Prob> probs;
   int parity = 0;
   hipGraphExec_t gexec = nullptr;
@@ -265,13 +272,32 @@ struct Engine {
     if (graph) (void)hipGraphDestroy(graph);
   }
 
-  int slot_of(int J) const { return Lk == 1 ? 0 : J; }
+  bool single() const { return Js.size() == 1; }
+  int slot_of(int J) const { return single() ? 0 : J; }
+  int group() const { return single() ? 1 : (ts.group > 0 ? ts.group : kMaxLoads); }
 
-  ceff_status build_work(TileShape t, std::vector<WorkItem>& w, std::vector<int>& rg, std::vector<int>& kcs) {
+  // Work list of one launch.  Each (tile, z-chunk) of a sample is split into
+  // load groups of `group` slots; the groups of one tile are placed 8 items apart
+  // so that the round-robin dispatch of blocks over the 8 XCDs puts them on the
+  // same XCD (they then share that XCD's L2 for the moduli).  Every sample's
+  // items stay contiguous (padded with sample = -1) so norms reduce per sample.
+  ceff_status build_work(TileShape t, int group, std::vector<WorkItem>& w, std::vector<int>& rg,
+                         std::vector<int>& kcs) {
     w.clear();
     rg.clear();
     kcs.clear();
-    // split z into chunks so that the whole launch has a few thousand work items
+    std::vector<int> slots0;  // first slot of each group that holds a requested load
+    if (single()) {
+      slots0.push_back(0);
+    } else {
+      for (int g0 = 0; g0 < kMaxLoads; g0 += group) {
+        bool any = false;
+        for (int J : Js)
+          if (J >= g0 && J < g0 + group) any = true;
+        if (any) slots0.push_back(g0);
+      }
+    }
+    const int G = (int)slots0.size();
     int64_t total_xy = 0;
     for (auto& s : in) total_xy += ((s.nx + t.bx - 3) / (t.bx - 2)) * ((s.ny + t.by - 3) / (t.by - 2));
     for (size_t si = 0; si < in.size(); ++si) {
@@ -282,7 +308,7 @@ struct Engine {
       if (t.kc > 0) {
         kc = t.kc;
       } else {
-        int64_t chunks = (2048 + total_xy - 1) / total_xy;
+        int64_t chunks = (2048 + total_xy * G - 1) / (total_xy * G);
         if (chunks > s.nz / 4) chunks = s.nz / 4;
         if (chunks < 1) chunks = 1;
         kc = (int)((s.nz + chunks - 1) / chunks);
@@ -290,10 +316,35 @@ struct Engine {
       if (kc > s.nz) kc = (int)s.nz;
       if (kc < 1) kc = 1;
       const int cz = (int)((s.nz + kc - 1) / kc);
-      rg.push_back((int)w.size());
-      for (int kz = 0; kz < cz; ++kz)
-        for (int b = 0; b < ty; ++b)
-          for (int a = 0; a < tx; ++a) w.push_back(WorkItem{(int)si, a, b, kz});
+      const int64_t ntile = (int64_t)tx * ty * cz;
+      const size_t base = w.size();
+      rg.push_back((int)base);
+      if (t.order == 1) {
+        // (kz, ty, tx, group) in lexicographic order, cut into 8 contiguous bands;
+        // band x goes to positions x, x+8, x+16, ... (XCD x under round-robin
+        // dispatch), so blocks running together on one XCD are spatial neighbours
+        // and share halo rows and moduli through that XCD's L2
+        const int64_t n = ntile * G;
+        const int64_t per = (n + 7) / 8;
+        w.resize(base + (size_t)(per * 8), WorkItem{-1, 0, 0, 0, 0});
+        for (int64_t q = 0; q < n; ++q) {
+          const int64_t tt = q / G;
+          const int g = (int)(q % G);
+          const int a = (int)(tt % tx), b = (int)((tt / tx) % ty), kz = (int)(tt / ((int64_t)tx * ty));
+          const int64_t pos = 8 * (q % per) + q / per;
+          w[base + (size_t)pos] = WorkItem{(int)si, a, b, kz, slots0[g]};
+        }
+      } else {
+        const int64_t nbatch = (ntile + 7) / 8;
+        w.resize(base + (size_t)(nbatch * 8 * G), WorkItem{-1, 0, 0, 0, 0});
+        for (int64_t tt = 0; tt < ntile; ++tt) {
+          const int a = (int)(tt % tx), b = (int)((tt / tx) % ty), kz = (int)(tt / ((int64_t)tx * ty));
+          for (int g = 0; g < G; ++g) {
+            const int64_t pos = 8 * G * (tt / 8) + 8 * g + (tt % 8);
+            w[base + (size_t)pos] = WorkItem{(int)si, a, b, kz, slots0[g]};
+          }
+        }
+      }
       rg.push_back((int)w.size());
       kcs.push_back(kc);
     }
@@ -330,11 +381,17 @@ struct Engine {
     return v;
   }
 
+  hipError_t step_on(const WorkItem* dw, int nw, TileShape t, int grp, int par, int first, double* partials) {
+    const SampleDesc<T>* d = d_in.as<SampleDesc<T>>();
+    switch (grp) {
+      case 1: return launch_step<T, 1>(d, dw, nw, t, par, first, partials, c->s);
+      case 2: return launch_step<T, 2>(d, dw, nw, t, par, first, partials, c->s);
+      case 3: return launch_step<T, 3>(d, dw, nw, t, par, first, partials, c->s);
+      default: return launch_step<T, 6>(d, dw, nw, t, par, first, partials, c->s);
+    }
+  }
   hipError_t step(int first, double* partials) {
-    return Lk == 1 ? launch_step<T, 1>(d_in.as<SampleDesc<T>>(), d_work.as<WorkItem>(), (int)work.size(), ts, parity,
-                                       first, partials, c->s)
-                   : launch_step<T, 6>(d_in.as<SampleDesc<T>>(), d_work.as<WorkItem>(), (int)work.size(), ts, parity,
-                                       first, partials, c->s);
+    return step_on(d_work.as<WorkItem>(), (int)work.size(), ts, group(), parity, first, partials);
   }
 
   // FP64 residual of the outer (FP64) displacement with the macroscopic strain;
@@ -342,15 +399,15 @@ struct Engine {
   hipError_t outer_residual(bool write_force) {
     hipError_t e;
     float* const* rout = write_force ? d_rout.as<float*>() : nullptr;
-    if (Lk == 1)
-      e = launch_residual<double, float, 1>(d_out.as<SampleDesc<double>>(), d_work.as<WorkItem>(), (int)work.size(),
-                                            ts, 0, rout, d_partials.as<double>(), c->s);
+    if (single())
+      e = launch_residual<double, float, 1>(d_out.as<SampleDesc<double>>(), d_work_o.as<WorkItem>(),
+                                            (int)work_o.size(), ts, 0, rout, d_partials.as<double>(), c->s);
     else
-      e = launch_residual<double, float, 6>(d_out.as<SampleDesc<double>>(), d_work.as<WorkItem>(), (int)work.size(),
-                                            ts, 0, rout, d_partials.as<double>(), c->s);
+      e = launch_residual<double, float, 6>(d_out.as<SampleDesc<double>>(), d_work_o.as<WorkItem>(),
+                                            (int)work_o.size(), ts, 0, rout, d_partials.as<double>(), c->s);
     if (e != hipSuccess) return e;
-    return launch_finalize_norms(d_ranges.as<int>(), (int)in.size(), d_partials.as<double>(), d_norms.as<double>(),
-                                 c->s);
+    return launch_finalize_norms(d_ranges_o.as<int>(), (int)in.size(), d_partials.as<double>(),
+                                 d_norms.as<double>(), c->s);
   }
 
   ceff_status read_norms(std::vector<double>& out) {
@@ -362,31 +419,41 @@ struct Engine {
     return CEFF_OK;
   }
 
+  // Pick the launch shape: block extent, loads per block and prefetch.  With
+  // autotune, time each candidate over a few iterations on this problem (the
+  // iterates do not depend on the shape; only speed does) and cache the best.
   ceff_status tune() {
-    const auto key = std::make_tuple((int)sizeof(T), Lk, in[0].nx, in[0].ny, in[0].nz);
-    auto it = c->tuned.find(key);
+    const bool fp64 = sizeof(T) == 8;
+    const auto key = std::make_tuple((int)sizeof(T), (int)Js.size(), in[0].nx, in[0].ny, in[0].nz);
     if (std::getenv("CEFF_TILE")) {
-      ts = default_tile(in[0].nx, in[0].ny, sizeof(T) == 8);
+      ts = default_tile(in[0].nx, in[0].ny, fp64);
       return CEFF_OK;
     }
+    auto it = c->tuned.find(key);
     if (it != c->tuned.end()) {
       ts = it->second;
       return CEFF_OK;
     }
-    if (!o.autotune) {
-      ts = default_tile(in[0].nx, in[0].ny, sizeof(T) == 8);
-      return CEFF_OK;
-    }
+    ts = default_tile(in[0].nx, in[0].ny, fp64);
+    if (!o.autotune) return CEFF_OK;
     std::vector<TileShape> cand;
-    const int bxs[] = {34, 66, 130};
-    const int bys[] = {4, 6, 8, 10, 14};
+    const int bxs[] = {34, 66};
+    const int bys[] = {6, 10, 14};
+    const int groups_fused[] = {6, 3, 2, 1};
+    const int groups_single[] = {1};
+    const int* groups = single() ? groups_single : groups_fused;
+    const int ng = single() ? 1 : 4;
     for (int bx : bxs)
       for (int by : bys) {
-        if (((bx * by + 63) / 64) * 64 > 512 || bx * by < 128) continue;
-        cand.push_back(TileShape{bx, by, 0});
+        const int nt = ((bx * by + 63) / 64) * 64;
+        if (nt > 512 || bx * by < 128 || bx > in[0].nx + 2 + 64 || by > in[0].ny + 2 + 8) continue;
+        if ((size_t)11 * nt * sizeof(T) > 64 * 1024) continue;
+        for (int gi = 0; gi < ng; ++gi)
+          for (int pf = 0; pf < 2; ++pf)
+            for (int kc : {0, 12, 32}) cand.push_back(TileShape{bx, by, kc, groups[gi], pf, 1});
       }
     float best = 1e30f;
-    TileShape bt = default_tile(in[0].nx, in[0].ny, sizeof(T) == 8);
+    TileShape bt = ts;
     std::vector<unsigned> saved(in.size());
     for (size_t si = 0; si < in.size(); ++si) {
       saved[si] = h_in[si].active;
@@ -395,7 +462,8 @@ struct Engine {
     for (const TileShape& t : cand) {
       std::vector<WorkItem> w;
       std::vector<int> rg, kcs;
-      STCK(build_work(t, w, rg, kcs));
+      const int grp = single() ? 1 : t.group;
+      STCK(build_work(t, grp, w, rg, kcs));
       DevBuf dw;
       HIPCK(c, dw.alloc(sizeof(WorkItem) * w.size()));
       HIPCK(c, hipMemcpyAsync(dw.p, w.data(), sizeof(WorkItem) * w.size(), hipMemcpyHostToDevice, c->s));
@@ -403,10 +471,7 @@ struct Engine {
       STCK(upload_desc());
       auto run = [&](int n) -> hipError_t {
         for (int q = 0; q < n; ++q) {
-          hipError_t e = Lk == 1 ? launch_step<T, 1>(d_in.as<SampleDesc<T>>(), dw.as<WorkItem>(), (int)w.size(), t,
-                                                     q & 1, 0, nullptr, c->s)
-                                 : launch_step<T, 6>(d_in.as<SampleDesc<T>>(), dw.as<WorkItem>(), (int)w.size(), t,
-                                                     q & 1, 0, nullptr, c->s);
+          hipError_t e = step_on(dw.as<WorkItem>(), (int)w.size(), t, grp, q & 1, 0, nullptr);
           if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -418,6 +483,9 @@ struct Engine {
       HIPCK(c, hipEventSynchronize(c->ev1));
       float ms = 0.f;
       HIPCK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      if (std::getenv("CEFF_TUNE_VERBOSE"))
+        std::fprintf(stderr, "tune bx=%d by=%d kc=%d group=%d pf=%d order=%d: %.4f ms/launch\n", t.bx, t.by, t.kc,
+                     grp, t.pf, t.order, ms / 6);
       if (ms < best) {
         best = ms;
         bt = t;
@@ -481,20 +549,31 @@ struct Engine {
     HIPCK(c, d_in.alloc(sizeof(SampleDesc<T>) * ns));
     HIPCK(c, d_out.alloc(sizeof(SampleDesc<double>) * ns));
     STCK(tune());
-    std::vector<int> kcs;
-    STCK(build_work(ts, work, ranges, kcs));
+    std::vector<int> kcs, kcs_o;
+    STCK(build_work(ts, group(), work, ranges, kcs));
+    TileShape to = ts;
+    to.kc = 0;
+    STCK(build_work(to, single() ? 1 : kMaxLoads, work_o, ranges_o, kcs_o));
     for (int si = 0; si < ns; ++si) {
       h_in[si].kc = kcs[si];
-      h_out[si].kc = kcs[si];
-      h_in[si].work_begin = h_out[si].work_begin = ranges[2 * si];
-      h_in[si].work_end = h_out[si].work_end = ranges[2 * si + 1];
+      h_out[si].kc = kcs_o[si];
+      h_in[si].work_begin = ranges[2 * si];
+      h_in[si].work_end = ranges[2 * si + 1];
+      h_out[si].work_begin = ranges_o[2 * si];
+      h_out[si].work_end = ranges_o[2 * si + 1];
     }
     HIPCK(c, d_work.alloc(sizeof(WorkItem) * work.size()));
     HIPCK(c, hipMemcpyAsync(d_work.p, work.data(), sizeof(WorkItem) * work.size(), hipMemcpyHostToDevice, c->s));
-    HIPCK(c, d_partials.alloc(sizeof(double) * kMaxLoads * work.size()));
+    HIPCK(c, d_work_o.alloc(sizeof(WorkItem) * work_o.size()));
+    HIPCK(c, hipMemcpyAsync(d_work_o.p, work_o.data(), sizeof(WorkItem) * work_o.size(), hipMemcpyHostToDevice,
+                            c->s));
+    HIPCK(c, d_partials.alloc(sizeof(double) * kMaxLoads * std::max(work.size(), work_o.size())));
     HIPCK(c, d_norms.alloc(sizeof(double) * kMaxLoads * ns));
     HIPCK(c, d_ranges.alloc(sizeof(int) * ranges.size()));
     HIPCK(c, hipMemcpyAsync(d_ranges.p, ranges.data(), sizeof(int) * ranges.size(), hipMemcpyHostToDevice, c->s));
+    HIPCK(c, d_ranges_o.alloc(sizeof(int) * ranges_o.size()));
+    HIPCK(c, hipMemcpyAsync(d_ranges_o.p, ranges_o.data(), sizeof(int) * ranges_o.size(), hipMemcpyHostToDevice,
+                            c->s));
     // per-slot float residual outputs for the outer check (only slot arrays of sample 0 are
     // addressed through rout; batches write forces per sample through the same slot pointers
     // when the batch has one sample, otherwise through per-sample passes below)
@@ -791,6 +870,8 @@ ceff_status run_engine(ceff_ctx* c, std::vector<SampleIn> samples, std::vector<i
   c->stats.tile_bx = e.ts.bx;
   c->stats.tile_by = e.ts.by;
   c->stats.tile_kc = e.h_in.empty() ? 0 : e.h_in[0].kc;
+  c->stats.tile_group = e.group();
+  c->stats.tile_prefetch = e.ts.pf;
   return CEFF_OK;
 }
 

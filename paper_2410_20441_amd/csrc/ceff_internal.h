@@ -27,15 +27,20 @@ struct SampleDesc {
   int tiles_x, tiles_y, chunks_z, kc;  // tiling of this sample
 };
 
-// One block's worth of work: a (tile_x, tile_y, z-chunk) of one sample.
+// One block's worth of work: a (tile_x, tile_y, z-chunk) of one sample and the
+// load slots [slot0, slot0 + L) of it.  sample < 0 marks padding.
 struct WorkItem {
   int sample;
   int tx, ty, kz;
+  int slot0;
 };
 
 struct TileShape {
   int bx, by;  // block extent including the one-cell ghost ring (threads = bx*by)
   int kc;      // z-planes per chunk (0 = choose automatically)
+  int group;   // loads per block: 1, 2, 3 or 6 (0 = all requested loads in one block)
+  int pf;      // 1 = prefetch the next plane into registers
+  int order;   // 0: load groups of a tile 8 items apart; 1: each XCD takes a contiguous band
 };
 
 // ---- launch wrappers (ceff_kernels.hip) ----------------------------------------

@@ -32,6 +32,19 @@ namespace ceff {
 
 namespace {
 
+// Pointers read from descriptor tables are generic; without this cast the
+// compiler emits FLAT accesses, which also count against the LDS wait counter,
+// so every LDS barrier would wait for all outstanding global loads.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const GLOBAL_AS T* gconst(const T* p) {
+  return (const GLOBAL_AS T*)p;
+}
+template <typename T>
+__device__ __forceinline__ GLOBAL_AS T* gmut(T* p) {
+  return (GLOBAL_AS T*)p;
+}
+
 __device__ __forceinline__ int64_t wrap_idx(int64_t a, int64_t n) {
   a %= n;
   return a < 0 ? a + n : a;
@@ -58,11 +71,33 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // MODE 0: heavy-ball update; MODE 1: write the residual to rout.
-template <typename T, int L, int MODE, typename R>
-__global__ void __launch_bounds__(512) step_kernel(const SampleDesc<T>* __restrict__ samples,
-                                                    const WorkItem* __restrict__ work, int nwork, int bx, int by,
-                                                    int parity, int first, double* __restrict__ partials,
-                                                    R* const* __restrict__ rout) {
+// L: loads handled by one block (slots [slot0, slot0+L) of its work item).
+// PF: prefetch the next plane's global data into registers while the current
+// plane is processed.
+template <typename T>
+__device__ __forceinline__ T recip(T x) {
+  return T(1) / x;
+}
+// FP32 sweeps use the hardware reciprocal (1 ulp); FP64 keeps exact division
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
+// Minimum waves per SIMD the compiler must allow (it caps registers to fit):
+// the FP32 kernels with up to two loads per block, and the FP64 one-load
+// kernel, are held to 128 VGPRs so that two 512-thread blocks share a CU.
+template <typename T, int L>
+struct MinWaves {
+  static constexpr int value = (sizeof(T) == 4 && L <= 2) || (sizeof(T) == 8 && L == 1) ? 4 : 1;
+};
+
+template <typename T, int L, int MODE, typename R, bool PF>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWaves<T, L>::value)))
+step_kernel(const SampleDesc<T>* __restrict__ samples,
+                                                   const WorkItem* __restrict__ work, int nwork, int bx, int by,
+                                                   int parity, int first, double* __restrict__ partials,
+                                                   R* const* __restrict__ rout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const int nt = blockDim.x;  // multiple of 64, >= bx*by
@@ -91,9 +126,17 @@ __global__ void __launch_bounds__(512) step_kernel(const SampleDesc<T>* __restri
 
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const WorkItem wi = work[w];
+    if (wi.sample < 0) {  // padding of the XCD-aware order
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
     const SampleDesc<T>& sd = samples[wi.sample];
-    const unsigned act = sd.active & ((1u << L) - 1u);
-    if (act == 0u) continue;  // uniform over the block
+    const int s0 = wi.slot0;
+    const unsigned act = (sd.active >> s0) & ((1u << L) - 1u);
+    if (act == 0u) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;  // uniform over the block
+    }
     const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N, plane = nx * ny;
     const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
     const T mom = first ? T(0) : sd.mom;
@@ -104,16 +147,18 @@ __global__ void __launch_bounds__(512) step_kernel(const SampleDesc<T>* __restri
     const int64_t k0 = (int64_t)wi.kz * sd.kc;
     const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
 
-    const T* __restrict__ Kf = sd.K;
-    const T* __restrict__ Gf = sd.G;
-    const T* ucur[L];
-    T* uold[L];
-    const T* frc[L];
+    const GLOBAL_AS T* __restrict__ Kf = gconst(sd.K);
+    const GLOBAL_AS T* __restrict__ Gf = gconst(sd.G);
+    const GLOBAL_AS T* ucur[L];
+    GLOBAL_AS T* uold[L];
+    const GLOBAL_AS T* frc[L];
+    bool hasf[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-      ucur[l] = sd.u[parity][l];
-      uold[l] = sd.u[parity ^ 1][l];
-      frc[l] = sd.force[l];
+      ucur[l] = gconst(sd.u[parity][s0 + l]);
+      uold[l] = gmut(sd.u[parity ^ 1][s0 + l]);
+      hasf[l] = sd.force[s0 + l] != nullptr;
+      frc[l] = gconst(sd.force[s0 + l]);
     }
 
     // registers carried up the z-march, per load
@@ -140,36 +185,59 @@ __global__ void __launch_bounds__(512) step_kernel(const SampleDesc<T>* __restri
     T Hprev = T(1);
     sG0[tid] = Gc;
 
-    for (int64_t k = k0 - 1; k < k1; ++k) {
-      const int rel = (int)(k - (k0 - 1));
+    // global data consumed while processing plane k: moduli and u^n at plane
+    // k+1, u^{n-1} and the body force at plane k
+    T Kn, Gn, unx[L], uny[L], unz[L], uo0[L], uo1[L], uo2[L], f0[L], f1[L], f2[L];
+    T pK, pG, pux[L], puy[L], puz[L], po0[L], po1[L], po2[L], pf0[L], pf1[L], pf2[L];
+    auto fetch = [&](int64_t k, T& K_, T& G_, T* ax, T* ay, T* az, T* b0, T* b1, T* b2, T* c0, T* c1, T* c2) {
       const int64_t kw = k < 0 ? k + nz : k;
       const int64_t kn = k + 1 >= nz ? k + 1 - nz : k + 1;
       const int64_t oc = col + plane * kw, on = col + plane * kn;
       const bool face = k >= k0 && interior;
-
-      // global loads for plane k+1 (and u^{n-1} / force at plane k)
-      const T Kn = Kf[on], Gn = Gf[on];
-      T unx[L], uny[L], unz[L], uo0[L], uo1[L], uo2[L], f0[L], f1[L], f2[L];
+      K_ = Kf[on];
+      G_ = Gf[on];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
-        unx[l] = uny[l] = unz[l] = uo0[l] = uo1[l] = uo2[l] = f0[l] = f1[l] = f2[l] = T(0);
+        ax[l] = ay[l] = az[l] = b0[l] = b1[l] = b2[l] = c0[l] = c1[l] = c2[l] = T(0);
         if (act & (1u << l)) {
-          unx[l] = ucur[l][on];
-          uny[l] = ucur[l][N + on];
-          unz[l] = ucur[l][2 * N + on];
+          ax[l] = ucur[l][on];
+          ay[l] = ucur[l][N + on];
+          az[l] = ucur[l][2 * N + on];
           if (face) {
             if (MODE == 0 && !first) {
-              uo0[l] = uold[l][oc];
-              uo1[l] = uold[l][N + oc];
-              uo2[l] = uold[l][2 * N + oc];
+              b0[l] = uold[l][oc];
+              b1[l] = uold[l][N + oc];
+              b2[l] = uold[l][2 * N + oc];
             }
-            if (frc[l] != nullptr) {
-              f0[l] = frc[l][oc];
-              f1[l] = frc[l][N + oc];
-              f2[l] = frc[l][2 * N + oc];
+            if (hasf[l]) {
+              c0[l] = frc[l][oc];
+              c1[l] = frc[l][N + oc];
+              c2[l] = frc[l][2 * N + oc];
             }
           }
         }
+      }
+    };
+    if (PF) fetch(k0 - 1, pK, pG, pux, puy, puz, po0, po1, po2, pf0, pf1, pf2);
+
+    for (int64_t k = k0 - 1; k < k1; ++k) {
+      const int rel = (int)(k - (k0 - 1));
+      const int64_t kw = k < 0 ? k + nz : k;
+      const int64_t oc = col + plane * kw;
+      const bool face = k >= k0 && interior;
+
+      if (PF) {
+        Kn = pK;
+        Gn = pG;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          unx[l] = pux[l]; uny[l] = puy[l]; unz[l] = puz[l];
+          uo0[l] = po0[l]; uo1[l] = po1[l]; uo2[l] = po2[l];
+          f0[l] = pf0[l]; f1[l] = pf1[l]; f2[l] = pf2[l];
+        }
+        if (k + 1 < k1) fetch(k + 1, pK, pG, pux, puy, puz, po0, po1, po2, pf0, pf1, pf2);
+      } else {
+        fetch(k, Kn, Gn, unx, uny, unz, uo0, uo1, uo2, f0, f1, f2);
       }
 
       T* gk = (rel & 1) ? sG1 : sG0;   // plane k
@@ -193,15 +261,17 @@ __global__ void __launch_bounds__(512) step_kernel(const SampleDesc<T>* __restri
         sUz[tid] = unz[l];
         __syncthreads();
         if (!coef) {
-          G2xy = T(8) / (T(1) / gk[xmym] + T(1) / gk[ym] + T(1) / gk[xm] + T(1) / gk[tid]);
-          G2xz = T(8) / (T(1) / gk[xm] + T(1) / gk[tid] + T(1) / gn[xm] + T(1) / gn[tid]);
-          G2yz = T(8) / (T(1) / gk[ym] + T(1) / gk[tid] + T(1) / gn[ym] + T(1) / gn[tid]);
-          sfx = sfac / tmax(sH[xm], Hk);
-          sfy = sfac / tmax(sH[ym], Hk);
-          sfz = sfac / tmax(Hprev, Hk);
+          const T ik = recip(gk[tid]), ikx = recip(gk[xm]), iky = recip(gk[ym]);
+          const T in = recip(gn[tid]), inx = recip(gn[xm]), iny = recip(gn[ym]);
+          G2xy = T(8) * recip(recip(gk[xmym]) + iky + ikx + ik);
+          G2xz = T(8) * recip(ikx + ik + inx + in);
+          G2yz = T(8) * recip(iky + ik + iny + in);
+          sfx = sfac * recip(tmax(sH[xm], Hk));
+          sfy = sfac * recip(tmax(sH[ym], Hk));
+          sfz = sfac * recip(tmax(Hprev, Hk));
           coef = true;
         }
-        const T* E = sd.E[l];
+        const T* E = sd.E[s0 + l];
         // stresses owned by this thread: cell (k), xy-edge (k), xz/yz-edges (k+1)
         const T exx = E[0] + (sUx[xp] - ux[l]) * rhx;
         const T eyy = E[1] + (sUy[yp] - uy[l]) * rhy;
@@ -233,7 +303,7 @@ __global__ void __launch_bounds__(512) step_kernel(const SampleDesc<T>* __restri
             uold[l][N + oc] = uy[l] + mom * (uy[l] - uo1[l]) + sfy * ry;
             uold[l][2 * N + oc] = uz[l] + mom * (uz[l] - uo2[l]) + sfz * rz;
           } else {
-            R* ro = rout != nullptr ? rout[l] : nullptr;
+            GLOBAL_AS R* ro = rout != nullptr ? gmut(rout[s0 + l]) : nullptr;
             if (ro != nullptr) {
               ro[oc] = (R)rx;
               ro[N + oc] = (R)ry;
@@ -254,12 +324,15 @@ __global__ void __launch_bounds__(512) step_kernel(const SampleDesc<T>* __restri
     }
 
     if (partials != nullptr) {
+      // every work item writes all six slots (zero for loads it does not own)
+      double tot[kMaxLoads] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
       for (int l = 0; l < L; ++l) {
         if (!(act & (1u << l))) continue;
-        const double s = block_sum(nsum[l], red);
-        if (tid == 0) partials[(int64_t)w * kMaxLoads + l] = s;
+        tot[s0 + l] = block_sum(nsum[l], red);
       }
+      if (tid == 0)
+        for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = tot[q];
     }
     __syncthreads();  // LDS is reused by the next work item
   }
@@ -360,11 +433,11 @@ __global__ void gradient_kernel(int64_t nx, int64_t ny, int64_t nz, double rhx, 
   }
   double th[6], dv[6][3], es[6][12];
   for (int J = 0; J < 6; ++J) {
-    const double* u = u6[J];
-    if (u == nullptr) continue;
-    const double* ux = u;
-    const double* uy = u + N;
-    const double* uz = u + 2 * N;
+    if (u6[J] == nullptr) continue;
+    const GLOBAL_AS double* u = gconst(u6[J]);
+    const GLOBAL_AS double* ux = u;
+    const GLOBAL_AS double* uy = u + N;
+    const GLOBAL_AS double* uz = u + 2 * N;
     const double Ev[6] = {J == 0 ? 1.0 : 0.0, J == 1 ? 1.0 : 0.0, J == 2 ? 1.0 : 0.0,
                           J == 3 ? 0.5 : 0.0, J == 4 ? 0.5 : 0.0, J == 5 ? 0.5 : 0.0};
     const double exx = Ev[0] + (ux[at(i + 1, j, k)] - ux[c]) * rhx;
@@ -472,8 +545,12 @@ hipError_t launch_step(const SampleDesc<T>* d_samples, const WorkItem* d_work, i
                        int first, double* partials, hipStream_t s) {
   const int nt = ((ts.bx * ts.by + 63) / 64) * 64;
   const size_t lds = (size_t)11 * nt * sizeof(T);
-  hipLaunchKernelGGL((step_kernel<T, L, 0, T>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork, ts.bx,
-                     ts.by, parity, first, partials, (T* const*)nullptr);
+  if (ts.pf)
+    hipLaunchKernelGGL((step_kernel<T, L, 0, T, true>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork,
+                       ts.bx, ts.by, parity, first, partials, (T* const*)nullptr);
+  else
+    hipLaunchKernelGGL((step_kernel<T, L, 0, T, false>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork,
+                       ts.bx, ts.by, parity, first, partials, (T* const*)nullptr);
   return hipGetLastError();
 }
 
@@ -482,8 +559,8 @@ hipError_t launch_residual(const SampleDesc<T>* d_samples, const WorkItem* d_wor
                            int parity, R* const* rout, double* partials, hipStream_t s) {
   const int nt = ((ts.bx * ts.by + 63) / 64) * 64;
   const size_t lds = (size_t)11 * nt * sizeof(T);
-  hipLaunchKernelGGL((step_kernel<T, L, 1, R>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork, ts.bx,
-                     ts.by, parity, 0, partials, rout);
+  hipLaunchKernelGGL((step_kernel<T, L, 1, R, false>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork,
+                     ts.bx, ts.by, parity, 0, partials, rout);
   return hipGetLastError();
 }
 
@@ -557,8 +634,12 @@ hipError_t launch_check_moduli(const T* K, const T* G, int64_t n, int* bad, int*
   template hipError_t launch_step<T, L>(const SampleDesc<T>*, const WorkItem*, int, TileShape, int, int, double*, \
                                         hipStream_t);
 CEFF_INST_STEP(float, 1)
+CEFF_INST_STEP(float, 2)
+CEFF_INST_STEP(float, 3)
 CEFF_INST_STEP(float, 6)
 CEFF_INST_STEP(double, 1)
+CEFF_INST_STEP(double, 2)
+CEFF_INST_STEP(double, 3)
 CEFF_INST_STEP(double, 6)
 #define CEFF_INST_RES(T, R, L)                                                                              \
   template hipError_t launch_residual<T, R, L>(const SampleDesc<T>*, const WorkItem*, int, TileShape, int, \

@@ -59,17 +59,33 @@ class SplitMix64:
             if x < limit:
                 return lo + (x % span)
 
+    def u64_array(self, n: int) -> np.ndarray:
+        """The next n outputs at once (splitmix64 is counter based: output k
+        mixes state + k * gamma), identical to n calls of next_u64."""
+        k = np.arange(1, n + 1, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            z = np.uint64(self.state) + k * np.uint64(0x9E3779B97F4A7C15)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            z = z ^ (z >> np.uint64(31))
+        self.state = (self.state + n * 0x9E3779B97F4A7C15) & MASK64
+        return z
+
+    def uniform_array(self, n: int) -> np.ndarray:
+        return (self.u64_array(n) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
     def normals(self, n: int) -> np.ndarray:
-        """n standard normal variates by the Box-Muller transform."""
-        out = np.empty(n)
-        for t in range(0, n, 2):
-            u1 = 1.0 - self.uniform()  # (0, 1]
-            u2 = self.uniform()
-            rad = math.sqrt(-2.0 * math.log(u1))
-            out[t] = rad * math.cos(2.0 * math.pi * u2)
-            if t + 1 < n:
-                out[t + 1] = rad * math.sin(2.0 * math.pi * u2)
-        return out
+        """n standard normal variates by the Box-Muller transform (uniforms drawn
+        in pairs: u1 in (0, 1], u2 in [0, 1))."""
+        m = (n + 1) // 2
+        u = self.uniform_array(2 * m)
+        u1 = 1.0 - u[0::2]
+        u2 = u[1::2]
+        rad = np.sqrt(-2.0 * np.log(u1))
+        out = np.empty(2 * m)
+        out[0::2] = rad * np.cos(2.0 * math.pi * u2)
+        out[1::2] = rad * np.sin(2.0 * math.pi * u2)
+        return out[:n]
 
     def unit_vector(self) -> np.ndarray:
         """Uniform direction on the unit sphere (z uniform in [-1,1], phi uniform)."""

@@ -205,3 +205,18 @@ def test_error_paths():
     assert np.all(np.isfinite(C.reshape(6, 6)[:, 0]))
     assert "max_iter" in p.ceff_last_error(h)
     c.close()
+
+
+@pytest.mark.parametrize("tile", ["66,6,0,6,1", "66,6,0,3,0", "34,10,0,2,1", "34,14,5,1,1", "18,18,3,6,0"])
+def test_fused_solve_independent_of_launch_shape(monkeypatch, tile):
+    """Block extent, loads per block, z-chunk and prefetch change only the speed."""
+    p = need_gpu()
+    K, G = synth.random_fields((23, 19, 17), 41, lo=(2.0, 1.0), hi=(90.0, 45.0))
+    monkeypatch.delenv("CEFF_TILE", raising=False)
+    Cref, iref = p.solve(K, G, precision="mixed", rtol=1e-9)
+    monkeypatch.setenv("CEFF_TILE", tile)
+    announce("launch shape", tile)
+    C, info = p.solve(K, G, precision="mixed", rtol=1e-9)
+    assert info["stats"]["tile_group"] == int(tile.split(",")[3])
+    assert np.array_equal(info["iters"], iref["iters"])
+    assert np.max(np.abs(C - Cref)) <= 1e-12 * np.abs(Cref).max()
