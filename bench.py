@@ -22,6 +22,44 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the iteration kernel measured with rocprofv3 FETCH_SIZE /
+# WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_hbm_counters.md),
+# valid only for the kernel source they were taken on.
+MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "c601667b6af5da36", "bytes_per_launch": 1.931058e+09,
+                    "launch": "step_kernel_b<float,2>, macroscopic-strain phase (no body force)"}
+
+
+def kernel_source_hash():
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "paper_2410_20441_amd", "csrc", "ceff_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stream_ceiling(torch, dev, mib=1024):
+    """Bandwidth of plain torch copy (1 read, 1 write) and add (2 reads, 1 write)
+    kernels on mib-MiB buffers: the practical streaming ceiling of the device."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device=dev)
+    b = torch.ones(n, device=dev)
+    c = torch.empty(n, device=dev)
+    out = {}
+    for name, f, nbytes in (("copy_GB_s", lambda: c.copy_(a), 8 * n), ("add_GB_s", lambda: torch.add(a, b, out=c),
+                                                                        12 * n)):
+        for _ in range(3):
+            f()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            f()
+        e1.record()
+        torch.cuda.synchronize(dev)
+        out[name] = nbytes / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -39,6 +77,10 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=400000)
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for counter collection: allow stopping at --max-iter")
+    ap.add_argument("--workload", default="spheres191",
+                    choices=["spheres191", "batch48", "cracks479", "sizing703"],
+                    help="spheres191 (default bench line); batch48: 48 uneven three-phase samples in one solve; "
+                         "cracks479: 479^3 cracked solid; sizing703: 703^3 sphere pack (memory sizing run)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a buffer of this many MiB three times (a plain copy kernel of known size "
                          "against which HBM byte counters are scaled)")
@@ -59,6 +101,8 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if a.workload != "spheres191":
+        return other_workload(a, torch, synth, ceff, dev)
     m = synth.workload_spheres191(n=a.n)
     N = m.phase.size
     print(f"# workload {m.info}", file=sys.stderr, flush=True)
@@ -87,6 +131,7 @@ def main():
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     tot = {"vu": 0.0, "iters": 0, "step_ms": 0.0, "step_bytes": 0.0, "launches": 0}
+    groups = set()
     Cs = []
     for k in range(a.steps):
         C, info = ctx.solve(**opts)
@@ -96,6 +141,7 @@ def main():
         tot["step_ms"] += st["step_time_ms"]
         tot["step_bytes"] += st["step_bytes"]
         tot["launches"] += st["step_launches"]
+        groups.add((st["tile_group"], st["tile_prefetch"]))
         Cs.append(C)
         print(f"# step {k}: status {info['status']} iters {info['iters'].tolist()} solve {st['solve_ms']:.1f} ms, "
               f"kernel {st['step_time_ms'] / max(st['step_launches'], 1):.4f} ms/launch, tile {st['tile_bx']}x"
@@ -105,6 +151,9 @@ def main():
     wall = time.perf_counter() - t0
     C = Cs[-1]
     achieved = tot["step_bytes"] / (tot["step_ms"] * 1e-3) / 1e9
+    traffic = None
+    if kernel_source_hash() == MEASURED_TRAFFIC["ceff_kernels_sha256_prefix"] and groups == {(2, 3)}:
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
 
     out = {
         "metric": "GVoxel-updates/s (six-load effective stiffness solve, 191^3)",
@@ -127,12 +176,14 @@ def main():
         "time_to_ceff_s": wall / a.steps,
         "iterations_per_solve": tot["iters"] / a.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "step_kernel<float,L,0> (heavy-ball APT iteration, L loads per block)",
                      "avg_launch_ms": tot["step_ms"] / max(tot["launches"], 1),
                      "bytes_per_launch": tot["step_bytes"] / max(tot["launches"], 1)},
         "C_eff_GPa": np.round(C, 6).tolist(),
     }
+
+    out["stream_ceiling"] = stream_ceiling(torch, dev)
 
     if not a.no_fp64_baseline:
         t1 = time.perf_counter()
@@ -164,6 +215,53 @@ def main():
                                "sample": f"{a.cpu_steps} APT iterations of one load on the same {a.n}^3 grid "
                                          f"(oracle, paper-form variables), {tc:.1f} s"}
     print(json.dumps(out), flush=True)
+
+
+def other_workload(a, torch, synth, ceff, dev):
+    """Measurement runs of the other workloads (one solve each, not the bench line)."""
+    opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, max_iter=a.max_iter,
+                allow_unconverged=a.profile_run, autotune=a.autotune)
+    t0 = time.perf_counter()
+    if a.workload == "batch48":
+        ms = synth.workload_batch()
+        samples = [tuple(torch.from_numpy(x).to(dev) for x in m.fields(np.float32)) for m in ms]
+        N = sum(m.phase.size for m in ms)
+        print(f"# batch of {len(ms)}: sizes {[m.phase.shape[0] for m in ms]}, {N} voxels, generated in "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize(dev)
+        t1 = time.perf_counter()
+        C, it, info = ceff.solve_batch(samples, **opts)
+        torch.cuda.synchronize(dev)
+        wall = time.perf_counter() - t1
+        vu = float(sum(ms[s].phase.size * it[s].sum() for s in range(len(ms))))
+        st = info["stats"]
+        res = {"workload": "batch48", "voxels": N, "samples": len(ms), "status": info["status"],
+               "time_s": wall, "gvu_s": vu / wall / 1e9, "max_iterations": int(it.max()),
+               "kernel_GB_s": st["step_bytes"] / (st["step_time_ms"] * 1e-3) / 1e9,
+               "avg_launch_ms": st["step_time_ms"] / max(st["step_launches"], 1), "launches": st["step_launches"]}
+    else:
+        if a.workload == "cracks479":
+            m = synth.workload_cracks()
+        else:
+            m = synth.random_spheres(703, 0.10, 0xC2)
+        N = m.phase.size
+        print(f"# {a.workload}: {m.info}, generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+        ctx = ceff.Context(0)
+        ctx.set_phases(m.phase, m.K_tab, m.G_tab)
+        torch.cuda.synchronize(dev)
+        t1 = time.perf_counter()
+        C, info = ctx.solve(**opts)
+        wall = time.perf_counter() - t1
+        st = info["stats"]
+        free, total = torch.cuda.mem_get_info(dev)
+        ctx.close()
+        res = {"workload": a.workload, "voxels": N, "info": m.info, "status": info["status"], "time_s": wall,
+               "iterations": info["iters"].tolist(), "gvu_s": N * float(info["iters"].sum()) / wall / 1e9,
+               "kernel_GB_s": st["step_bytes"] / (st["step_time_ms"] * 1e-3) / 1e9,
+               "avg_launch_ms": st["step_time_ms"] / max(st["step_launches"], 1),
+               "C_eff_GPa": np.round(C, 5).tolist()}
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -219,24 +219,26 @@ struct Prob {
 
 TileShape default_tile(int64_t nx, int64_t ny, bool fp64) {
   TileShape t;
-  (void)fp64;
   // CEFF_TILE="bx,by[,kc]" overrides the shape (tests check results do not depend on it)
   // CEFF_TILE="bx,by[,kc[,group[,prefetch]]]" overrides the launch shape
   if (const char* env = std::getenv("CEFF_TILE")) {
-    int bx = 0, by = 0, kc = 0, grp = 6, pf = 1, ord = 1;
-    const int n = std::sscanf(env, "%d,%d,%d,%d,%d,%d", &bx, &by, &kc, &grp, &pf, &ord);
+    int bx = 0, by = 0, kc = 0, grp = 6, pf = 1, ord = 1, occ = 0;
+    const int n = std::sscanf(env, "%d,%d,%d,%d,%d,%d,%d", &bx, &by, &kc, &grp, &pf, &ord, &occ);
     if (n >= 2 && bx >= 3 && by >= 3 && ((bx * by + 63) / 64) * 64 <= 512 &&
         (grp == 1 || grp == 2 || grp == 3 || grp == 6))
-      return TileShape{bx, by, n >= 3 ? kc : 0, grp, pf ? 1 : 0, ord ? 1 : 0};
+      return TileShape{bx, by, n >= 3 ? kc : 0, grp, pf >= 0 && pf <= 3 ? pf : 0, ord ? 1 : 0, occ ? 1 : 0};
   }
-  // 34 x 14 ghosted block (32 x 12 interior, 476 of 512 threads), two loads per
-  // block, XCD bands: the fastest shape of the 191^3 sweeps (see the tuner)
+  // 34 x 14 ghosted block (32 x 12 interior, 476 of 512 threads), XCD bands.
+  // FP32: two loads per block staged between one barrier pair per plane;
+  // FP64: one load, unrolled march, 12-plane chunks.  These were the fastest
+  // shapes of the 191^3 sweeps (see the tuner).
   t.bx = nx + 2 <= 34 ? (int)nx + 2 : 34;
   t.by = ny + 2 <= 14 ? (int)ny + 2 : 14;
-  t.kc = 0;
+  t.kc = fp64 ? 12 : 0;
   t.group = 2;
-  t.pf = 0;
+  t.pf = fp64 ? 2 : 3;
   t.order = 1;
+  t.occ = 0;
   return t;
 }
 
@@ -449,8 +451,13 @@ struct Engine {
         if (nt > 512 || bx * by < 128 || bx > in[0].nx + 2 + 64 || by > in[0].ny + 2 + 8) continue;
         if ((size_t)11 * nt * sizeof(T) > 64 * 1024) continue;
         for (int gi = 0; gi < ng; ++gi)
-          for (int pf = 0; pf < 2; ++pf)
-            for (int kc : {0, 12, 32}) cand.push_back(TileShape{bx, by, kc, groups[gi], pf, 1});
+          for (int pf = 1; pf < 4; ++pf)
+            for (int kc : {0, 12})
+              for (int occ = 0; occ < 1; ++occ) {
+                const int grp = single() ? 1 : groups[gi];
+                if (pf == 3 && (size_t)(3 + 8 * grp) * nt * sizeof(T) > 64 * 1024) continue;
+                cand.push_back(TileShape{bx, by, kc, groups[gi], pf, 1, occ});
+              }
       }
     float best = 1e30f;
     TileShape bt = ts;
@@ -484,8 +491,8 @@ struct Engine {
       float ms = 0.f;
       HIPCK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
       if (std::getenv("CEFF_TUNE_VERBOSE"))
-        std::fprintf(stderr, "tune bx=%d by=%d kc=%d group=%d pf=%d order=%d: %.4f ms/launch\n", t.bx, t.by, t.kc,
-                     grp, t.pf, t.order, ms / 6);
+        std::fprintf(stderr, "tune bx=%d by=%d kc=%d group=%d pf=%d order=%d occ=%d: %.4f ms/launch\n", t.bx, t.by,
+                     t.kc, grp, t.pf, t.order, t.occ, ms / 6);
       if (ms < best) {
         best = ms;
         bt = t;

@@ -39,8 +39,10 @@ struct TileShape {
   int bx, by;  // block extent including the one-cell ghost ring (threads = bx*by)
   int kc;      // z-planes per chunk (0 = choose automatically)
   int group;   // loads per block: 1, 2, 3 or 6 (0 = all requested loads in one block)
-  int pf;      // 1 = prefetch the next plane into registers
+  int pf;      // 0: plain z-march; 1: prefetch the next plane into registers; 2: z-march unrolled by two;
+               // 3: unrolled, all loads of the group between one pair of barriers per plane
   int order;   // 0: load groups of a tile 8 items apart; 1: each XCD takes a contiguous band
+  int occ;     // 1: build that targets more waves per SIMD (fewer registers)
 };
 
 // ---- launch wrappers (ceff_kernels.hip) ----------------------------------------

@@ -28,6 +28,8 @@
 // all of them.  The residual norm is fused into the sweep on check iterations.
 #include "ceff_internal.h"
 
+#include <type_traits>
+
 namespace ceff {
 
 namespace {
@@ -87,13 +89,17 @@ __device__ __forceinline__ float recip<float>(float x) {
 // Minimum waves per SIMD the compiler must allow (it caps registers to fit):
 // the FP32 kernels with up to two loads per block, and the FP64 one-load
 // kernel, are held to 128 VGPRs so that two 512-thread blocks share a CU.
-template <typename T, int L>
+// HI selects the high-occupancy build (more waves per SIMD, fewer registers,
+// possibly some spills); the tuner measures both.
+template <typename T, int L, bool HI>
 struct MinWaves {
-  static constexpr int value = (sizeof(T) == 4 && L <= 2) || (sizeof(T) == 8 && L == 1) ? 4 : 1;
+  static constexpr int hi = sizeof(T) == 4 ? (L == 1 ? 8 : (L == 2 ? 6 : (L == 3 ? 4 : 1))) : (L == 1 ? 5 : 1);
+  static constexpr int lo = (sizeof(T) == 4 && L <= 2) || (sizeof(T) == 8 && L == 1) ? 4 : 1;
+  static constexpr int value = HI ? hi : lo;
 };
 
-template <typename T, int L, int MODE, typename R, bool PF>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWaves<T, L>::value)))
+template <typename T, int L, int MODE, typename R, bool PF, bool HI>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWaves<T, L, HI>::value)))
 step_kernel(const SampleDesc<T>* __restrict__ samples,
                                                    const WorkItem* __restrict__ work, int nwork, int bx, int by,
                                                    int parity, int first, double* __restrict__ partials,
@@ -338,6 +344,428 @@ step_kernel(const SampleDesc<T>* __restrict__ samples,
   }
 }
 
+// Same iteration as step_kernel (MODE 0, no prefetch), with the z-march
+// unrolled by two: the register sets of "this plane" and "next plane" swap
+// roles at compile time instead of being copied at the end of every plane.
+template <typename T, int L, bool HI>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWaves<T, L, HI>::value)))
+step_kernel_u2(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
+               int by, int parity, int first, double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const int nt = blockDim.x;
+  T* sG[2] = {reinterpret_cast<T*>(smem_raw), reinterpret_cast<T*>(smem_raw) + nt};
+  T* sH = sG[1] + nt;
+  T* sUx = sH + nt;
+  T* sUy = sUx + nt;
+  T* sUz = sUy + nt;
+  T* sSxx = sUz + nt;
+  T* sSyy = sSxx + nt;
+  T* sSxy = sSyy + nt;
+  T* sSxz = sSxy + nt;
+  T* sSyz = sSxz + nt;
+
+  const int tid = threadIdx.x;
+  const int tx = tid % bx, ty = tid / bx;
+  const int TX = bx - 2, TY = by - 2;
+  const int xm = tid > 0 && tx > 0 ? tid - 1 : tid;
+  const int xp = tx < bx - 1 && tid + 1 < nt ? tid + 1 : tid;
+  const int ym = ty > 0 ? tid - bx : tid;
+  const int yp = ty < by - 1 && tid + bx < nt ? tid + bx : tid;
+  const int xmym = ty > 0 ? xm - bx : xm;
+
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const WorkItem wi = work[w];
+    if (wi.sample < 0) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const SampleDesc<T>& sd = samples[wi.sample];
+    const int s0 = wi.slot0;
+    const unsigned act = (sd.active >> s0) & ((1u << L) - 1u);
+    if (act == 0u) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N, plane = nx * ny;
+    const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
+    const T mom = first ? T(0) : sd.mom;
+    const T sfac = first ? sd.sfac_first : sd.sfac;
+    const int64_t gi = (int64_t)wi.tx * TX + tx - 1, gj = (int64_t)wi.ty * TY + ty - 1;
+    const int64_t col = wrap_idx(gi, nx) + nx * wrap_idx(gj, ny);
+    const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
+    const int64_t k0 = (int64_t)wi.kz * sd.kc;
+    const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
+
+    const GLOBAL_AS T* __restrict__ Kf = gconst(sd.K);
+    const GLOBAL_AS T* __restrict__ Gf = gconst(sd.G);
+    const GLOBAL_AS T* ucur[L];
+    GLOBAL_AS T* uold[L];
+    const GLOBAL_AS T* frc[L];
+    bool hasf[L];
+    T E[L][6];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      ucur[l] = gconst(sd.u[parity][s0 + l]);
+      uold[l] = gmut(sd.u[parity ^ 1][s0 + l]);
+      hasf[l] = sd.force[s0 + l] != nullptr;
+      frc[l] = gconst(sd.force[s0 + l]);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) E[l][q] = sd.E[s0 + l][q];
+    }
+
+    // two register sets, indexed by plane parity
+    T Ux[2][L], Uy[2][L], Uz[2][L], Szz[2][L], Sxz[2][L], Syz[2][L], Kc[2], Gc[2], Hh[2];
+    double nsum[L];
+    {
+      const int64_t kw = k0 - 1 < 0 ? k0 - 1 + nz : k0 - 1;
+      const int64_t o = col + plane * kw;
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        Ux[0][l] = Uy[0][l] = Uz[0][l] = T(0);
+        if (act & (1u << l)) {
+          Ux[0][l] = ucur[l][o];
+          Uy[0][l] = ucur[l][N + o];
+          Uz[0][l] = ucur[l][2 * N + o];
+        }
+        Szz[1][l] = Sxz[1][l] = Syz[1][l] = T(0);
+        nsum[l] = 0.0;
+      }
+      Kc[0] = Kf[o];
+      Gc[0] = Gf[o];
+      Hh[1] = T(1);
+      sG[0][tid] = Gc[0];
+    }
+
+    auto plane_step = [&](int64_t k, auto Pc) {
+      constexpr int P = decltype(Pc)::value;
+      constexpr int Q = 1 - P;
+      const int64_t kw = k < 0 ? k + nz : k;
+      const int64_t kn = k + 1 >= nz ? k + 1 - nz : k + 1;
+      const int64_t oc = col + plane * kw, on = col + plane * kn;
+      const bool face = k >= k0 && interior;
+      // plane k+1 into the other register set; u^{n-1} and force at plane k
+      Kc[Q] = Kf[on];
+      Gc[Q] = Gf[on];
+      T uo0[L], uo1[L], uo2[L], f0[L], f1[L], f2[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        Ux[Q][l] = Uy[Q][l] = Uz[Q][l] = uo0[l] = uo1[l] = uo2[l] = f0[l] = f1[l] = f2[l] = T(0);
+        if (act & (1u << l)) {
+          Ux[Q][l] = ucur[l][on];
+          Uy[Q][l] = ucur[l][N + on];
+          Uz[Q][l] = ucur[l][2 * N + on];
+          if (face) {
+            if (!first) {
+              uo0[l] = uold[l][oc];
+              uo1[l] = uold[l][N + oc];
+              uo2[l] = uold[l][2 * N + oc];
+            }
+            if (hasf[l]) {
+              f0[l] = frc[l][oc];
+              f1[l] = frc[l][N + oc];
+              f2[l] = frc[l][2 * N + oc];
+            }
+          }
+        }
+      }
+      T* gk = sG[P];
+      T* gn = sG[Q];
+      gn[tid] = Gc[Q];
+      Hh[P] = Kc[P] + T(4.0 / 3.0) * Gc[P];
+      sH[tid] = Hh[P];
+      const T lam = Kc[P] - T(2.0 / 3.0) * Gc[P];
+      const T twoG = T(2) * Gc[P];
+      T G2xy = T(0), G2xz = T(0), G2yz = T(0), sfx = T(0), sfy = T(0), sfz = T(0);
+      bool coef = false;
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        if (!(act & (1u << l))) continue;
+        sUx[tid] = Ux[P][l];
+        sUy[tid] = Uy[P][l];
+        sUz[tid] = Uz[Q][l];
+        __syncthreads();
+        if (!coef) {
+          const T ik = recip(gk[tid]), ikx = recip(gk[xm]), iky = recip(gk[ym]);
+          const T in = recip(gn[tid]), inx = recip(gn[xm]), iny = recip(gn[ym]);
+          G2xy = T(8) * recip(recip(gk[xmym]) + iky + ikx + ik);
+          G2xz = T(8) * recip(ikx + ik + inx + in);
+          G2yz = T(8) * recip(iky + ik + iny + in);
+          sfx = sfac * recip(tmax(sH[xm], Hh[P]));
+          sfy = sfac * recip(tmax(sH[ym], Hh[P]));
+          sfz = sfac * recip(tmax(Hh[Q], Hh[P]));
+          coef = true;
+        }
+        const T ux = Ux[P][l], uy = Uy[P][l], uz = Uz[P][l];
+        const T unx = Ux[Q][l], uny = Uy[Q][l], unz = Uz[Q][l];
+        const T exx = E[l][0] + (sUx[xp] - ux) * rhx;
+        const T eyy = E[l][1] + (sUy[yp] - uy) * rhy;
+        const T ezz = E[l][2] + (unz - uz) * rhz;
+        const T th = exx + eyy + ezz;
+        const T sxx = lam * th + twoG * exx;
+        const T syy = lam * th + twoG * eyy;
+        const T szz = lam * th + twoG * ezz;
+        const T sxy = G2xy * (E[l][5] + T(0.5) * ((ux - sUx[ym]) * rhy + (uy - sUy[xm]) * rhx));
+        const T sxz_n = G2xz * (E[l][4] + T(0.5) * ((unx - ux) * rhz + (unz - sUz[xm]) * rhx));
+        const T syz_n = G2yz * (E[l][3] + T(0.5) * ((uny - uy) * rhz + (unz - sUz[ym]) * rhy));
+        const T sxz_c = Sxz[Q][l], syz_c = Syz[Q][l];
+        sSxx[tid] = sxx;
+        sSyy[tid] = syy;
+        sSxy[tid] = sxy;
+        sSxz[tid] = sxz_c;
+        sSyz[tid] = syz_c;
+        __syncthreads();
+        if (face) {
+          T rx = (sxx - sSxx[xm]) * rhx + (sSxy[yp] - sxy) * rhy + (sxz_n - sxz_c) * rhz;
+          T ry = (sSxy[xp] - sxy) * rhx + (syy - sSyy[ym]) * rhy + (syz_n - syz_c) * rhz;
+          T rz = (sSxz[xp] - sxz_c) * rhx + (sSyz[yp] - syz_c) * rhy + (szz - Szz[Q][l]) * rhz;
+          rx += f0[l];
+          ry += f1[l];
+          rz += f2[l];
+          if (partials != nullptr)
+            nsum[l] += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
+          uold[l][oc] = ux + mom * (ux - uo0[l]) + sfx * rx;
+          uold[l][N + oc] = uy + mom * (uy - uo1[l]) + sfy * ry;
+          uold[l][2 * N + oc] = uz + mom * (uz - uo2[l]) + sfz * rz;
+        }
+        Szz[P][l] = szz;
+        Sxz[P][l] = sxz_n;
+        Syz[P][l] = syz_n;
+      }
+    };
+
+    for (int64_t k = k0 - 1; k < k1; k += 2) {
+      plane_step(k, std::integral_constant<int, 0>{});
+      if (k + 1 < k1) plane_step(k + 1, std::integral_constant<int, 1>{});
+    }
+
+    if (partials != nullptr) {
+      double tot[kMaxLoads] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        if (!(act & (1u << l))) continue;
+        tot[s0 + l] = block_sum(nsum[l], red);
+      }
+      if (tid == 0)
+        for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = tot[q];
+    }
+    __syncthreads();
+  }
+}
+
+// Unrolled z-march with all loads of the block's group staged together: one
+// barrier after the displacements of every load are in LDS, one after their
+// stresses, so two barriers per plane whatever the group size.  LDS holds
+// 3 + 8L arrays.
+template <typename T, int L, bool HI>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWaves<T, L, HI>::value)))
+step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
+              int by, int parity, int first, double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const int nt = blockDim.x;
+  T* base = reinterpret_cast<T*>(smem_raw);
+  T* sG[2] = {base, base + nt};
+  T* sH = base + 2 * nt;
+  T* lds_l = base + 3 * nt;  // per load: ux uy uz sxx syy sxy sxz syz
+  auto S = [&](int l, int f) { return lds_l + (size_t)(8 * l + f) * nt; };
+
+  const int tid = threadIdx.x;
+  const int tx = tid % bx, ty = tid / bx;
+  const int TX = bx - 2, TY = by - 2;
+  const int xm = tid > 0 && tx > 0 ? tid - 1 : tid;
+  const int xp = tx < bx - 1 && tid + 1 < nt ? tid + 1 : tid;
+  const int ym = ty > 0 ? tid - bx : tid;
+  const int yp = ty < by - 1 && tid + bx < nt ? tid + bx : tid;
+  const int xmym = ty > 0 ? xm - bx : xm;
+
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const WorkItem wi = work[w];
+    if (wi.sample < 0) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const SampleDesc<T>& sd = samples[wi.sample];
+    const int s0 = wi.slot0;
+    const unsigned act = (sd.active >> s0) & ((1u << L) - 1u);
+    if (act == 0u) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N, plane = nx * ny;
+    const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
+    const T mom = first ? T(0) : sd.mom;
+    const T sfac = first ? sd.sfac_first : sd.sfac;
+    const int64_t gi = (int64_t)wi.tx * TX + tx - 1, gj = (int64_t)wi.ty * TY + ty - 1;
+    const int64_t col = wrap_idx(gi, nx) + nx * wrap_idx(gj, ny);
+    const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
+    const int64_t k0 = (int64_t)wi.kz * sd.kc;
+    const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
+
+    const GLOBAL_AS T* __restrict__ Kf = gconst(sd.K);
+    const GLOBAL_AS T* __restrict__ Gf = gconst(sd.G);
+    const GLOBAL_AS T* ucur[L];
+    GLOBAL_AS T* uold[L];
+    const GLOBAL_AS T* frc[L];
+    bool hasf[L];
+    T E[L][6];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      ucur[l] = gconst(sd.u[parity][s0 + l]);
+      uold[l] = gmut(sd.u[parity ^ 1][s0 + l]);
+      hasf[l] = sd.force[s0 + l] != nullptr;
+      frc[l] = gconst(sd.force[s0 + l]);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) E[l][q] = sd.E[s0 + l][q];
+    }
+
+    T Ux[2][L], Uy[2][L], Uz[2][L], Szz[2][L], Sxz[2][L], Syz[2][L], Kc[2], Gc[2], Hh[2];
+    double nsum[L];
+    {
+      const int64_t kw = k0 - 1 < 0 ? k0 - 1 + nz : k0 - 1;
+      const int64_t o = col + plane * kw;
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        Ux[0][l] = Uy[0][l] = Uz[0][l] = T(0);
+        if (act & (1u << l)) {
+          Ux[0][l] = ucur[l][o];
+          Uy[0][l] = ucur[l][N + o];
+          Uz[0][l] = ucur[l][2 * N + o];
+        }
+        Szz[1][l] = Sxz[1][l] = Syz[1][l] = T(0);
+        nsum[l] = 0.0;
+      }
+      Kc[0] = Kf[o];
+      Gc[0] = Gf[o];
+      Hh[1] = T(1);
+      sG[0][tid] = Gc[0];
+    }
+
+    auto plane_step = [&](int64_t k, auto Pc) {
+      constexpr int P = decltype(Pc)::value;
+      constexpr int Q = 1 - P;
+      const int64_t kw = k < 0 ? k + nz : k;
+      const int64_t kn = k + 1 >= nz ? k + 1 - nz : k + 1;
+      const int64_t oc = col + plane * kw, on = col + plane * kn;
+      const bool face = k >= k0 && interior;
+      Kc[Q] = Kf[on];
+      Gc[Q] = Gf[on];
+      T uo0[L], uo1[L], uo2[L], f0[L], f1[L], f2[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        Ux[Q][l] = Uy[Q][l] = Uz[Q][l] = uo0[l] = uo1[l] = uo2[l] = f0[l] = f1[l] = f2[l] = T(0);
+        if (act & (1u << l)) {
+          Ux[Q][l] = ucur[l][on];
+          Uy[Q][l] = ucur[l][N + on];
+          Uz[Q][l] = ucur[l][2 * N + on];
+          if (face) {
+            if (!first) {
+              uo0[l] = uold[l][oc];
+              uo1[l] = uold[l][N + oc];
+              uo2[l] = uold[l][2 * N + oc];
+            }
+            if (hasf[l]) {
+              f0[l] = frc[l][oc];
+              f1[l] = frc[l][N + oc];
+              f2[l] = frc[l][2 * N + oc];
+            }
+          }
+        }
+      }
+      T* gk = sG[P];
+      T* gn = sG[Q];
+      gn[tid] = Gc[Q];
+      Hh[P] = Kc[P] + T(4.0 / 3.0) * Gc[P];
+      sH[tid] = Hh[P];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        S(l, 0)[tid] = Ux[P][l];
+        S(l, 1)[tid] = Uy[P][l];
+        S(l, 2)[tid] = Uz[Q][l];
+      }
+      __syncthreads();
+      const T lam = Kc[P] - T(2.0 / 3.0) * Gc[P];
+      const T twoG = T(2) * Gc[P];
+      const T ik = recip(gk[tid]), ikx = recip(gk[xm]), iky = recip(gk[ym]);
+      const T in = recip(gn[tid]), inx = recip(gn[xm]), iny = recip(gn[ym]);
+      const T G2xy = T(8) * recip(recip(gk[xmym]) + iky + ikx + ik);
+      const T G2xz = T(8) * recip(ikx + ik + inx + in);
+      const T G2yz = T(8) * recip(iky + ik + iny + in);
+      const T sfx = sfac * recip(tmax(sH[xm], Hh[P]));
+      const T sfy = sfac * recip(tmax(sH[ym], Hh[P]));
+      const T sfz = sfac * recip(tmax(Hh[Q], Hh[P]));
+      T sxx[L], syy[L], szz[L], sxy[L], sxz_n[L], syz_n[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        const T ux = Ux[P][l], uy = Uy[P][l], uz = Uz[P][l];
+        const T unx = Ux[Q][l], uny = Uy[Q][l], unz = Uz[Q][l];
+        const T* sUx = S(l, 0);
+        const T* sUy = S(l, 1);
+        const T* sUz = S(l, 2);
+        const T exx = E[l][0] + (sUx[xp] - ux) * rhx;
+        const T eyy = E[l][1] + (sUy[yp] - uy) * rhy;
+        const T ezz = E[l][2] + (unz - uz) * rhz;
+        const T th = exx + eyy + ezz;
+        sxx[l] = lam * th + twoG * exx;
+        syy[l] = lam * th + twoG * eyy;
+        szz[l] = lam * th + twoG * ezz;
+        sxy[l] = G2xy * (E[l][5] + T(0.5) * ((ux - sUx[ym]) * rhy + (uy - sUy[xm]) * rhx));
+        sxz_n[l] = G2xz * (E[l][4] + T(0.5) * ((unx - ux) * rhz + (unz - sUz[xm]) * rhx));
+        syz_n[l] = G2yz * (E[l][3] + T(0.5) * ((uny - uy) * rhz + (unz - sUz[ym]) * rhy));
+        S(l, 3)[tid] = sxx[l];
+        S(l, 4)[tid] = syy[l];
+        S(l, 5)[tid] = sxy[l];
+        S(l, 6)[tid] = Sxz[Q][l];
+        S(l, 7)[tid] = Syz[Q][l];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        if (face && (act & (1u << l))) {
+          const T* sSxx = S(l, 3);
+          const T* sSyy = S(l, 4);
+          const T* sSxy = S(l, 5);
+          const T* sSxz = S(l, 6);
+          const T* sSyz = S(l, 7);
+          const T sxz_c = Sxz[Q][l], syz_c = Syz[Q][l];
+          T rx = (sxx[l] - sSxx[xm]) * rhx + (sSxy[yp] - sxy[l]) * rhy + (sxz_n[l] - sxz_c) * rhz;
+          T ry = (sSxy[xp] - sxy[l]) * rhx + (syy[l] - sSyy[ym]) * rhy + (syz_n[l] - syz_c) * rhz;
+          T rz = (sSxz[xp] - sxz_c) * rhx + (sSyz[yp] - syz_c) * rhy + (szz[l] - Szz[Q][l]) * rhz;
+          rx += f0[l];
+          ry += f1[l];
+          rz += f2[l];
+          if (partials != nullptr)
+            nsum[l] += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
+          const T ux = Ux[P][l], uy = Uy[P][l], uz = Uz[P][l];
+          uold[l][oc] = ux + mom * (ux - uo0[l]) + sfx * rx;
+          uold[l][N + oc] = uy + mom * (uy - uo1[l]) + sfy * ry;
+          uold[l][2 * N + oc] = uz + mom * (uz - uo2[l]) + sfz * rz;
+        }
+        Szz[P][l] = szz[l];
+        Sxz[P][l] = sxz_n[l];
+        Syz[P][l] = syz_n[l];
+      }
+    };
+
+    for (int64_t k = k0 - 1; k < k1; k += 2) {
+      plane_step(k, std::integral_constant<int, 0>{});
+      if (k + 1 < k1) plane_step(k + 1, std::integral_constant<int, 1>{});
+    }
+
+    if (partials != nullptr) {
+      double tot[kMaxLoads] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        if (!(act & (1u << l))) continue;
+        tot[s0 + l] = block_sum(nsum[l], red);
+      }
+      if (tid == 0)
+        for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = tot[q];
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void finalize_norms_kernel(const int* __restrict__ ranges, const double* __restrict__ partials,
                                       double* __restrict__ out) {
   __shared__ double red[16];
@@ -540,17 +968,32 @@ inline int grid_for(int64_t n, int block = 256) {
 
 // ---- launch wrappers -------------------------------------------------------------
 
+template <typename T, int L, bool HI>
+void launch_step_occ(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts, int parity,
+                     int first, double* partials, hipStream_t s, int nt, size_t lds) {
+  if (ts.pf == 3)
+    hipLaunchKernelGGL((step_kernel_b<T, L, HI>), dim3(nwork), dim3(nt), (size_t)(3 + 8 * L) * nt * sizeof(T), s,
+                       d_samples, d_work, nwork, ts.bx, ts.by, parity, first, partials);
+  else if (ts.pf == 2)
+    hipLaunchKernelGGL((step_kernel_u2<T, L, HI>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork, ts.bx,
+                       ts.by, parity, first, partials);
+  else if (ts.pf)
+    hipLaunchKernelGGL((step_kernel<T, L, 0, T, true, HI>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork,
+                       ts.bx, ts.by, parity, first, partials, (T* const*)nullptr);
+  else
+    hipLaunchKernelGGL((step_kernel<T, L, 0, T, false, HI>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work,
+                       nwork, ts.bx, ts.by, parity, first, partials, (T* const*)nullptr);
+}
+
 template <typename T, int L>
 hipError_t launch_step(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts, int parity,
                        int first, double* partials, hipStream_t s) {
   const int nt = ((ts.bx * ts.by + 63) / 64) * 64;
   const size_t lds = (size_t)11 * nt * sizeof(T);
-  if (ts.pf)
-    hipLaunchKernelGGL((step_kernel<T, L, 0, T, true>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork,
-                       ts.bx, ts.by, parity, first, partials, (T* const*)nullptr);
+  if (ts.occ)
+    launch_step_occ<T, L, true>(d_samples, d_work, nwork, ts, parity, first, partials, s, nt, lds);
   else
-    hipLaunchKernelGGL((step_kernel<T, L, 0, T, false>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork,
-                       ts.bx, ts.by, parity, first, partials, (T* const*)nullptr);
+    launch_step_occ<T, L, false>(d_samples, d_work, nwork, ts, parity, first, partials, s, nt, lds);
   return hipGetLastError();
 }
 
@@ -559,8 +1002,8 @@ hipError_t launch_residual(const SampleDesc<T>* d_samples, const WorkItem* d_wor
                            int parity, R* const* rout, double* partials, hipStream_t s) {
   const int nt = ((ts.bx * ts.by + 63) / 64) * 64;
   const size_t lds = (size_t)11 * nt * sizeof(T);
-  hipLaunchKernelGGL((step_kernel<T, L, 1, R, false>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork,
-                     ts.bx, ts.by, parity, 0, partials, rout);
+  hipLaunchKernelGGL((step_kernel<T, L, 1, R, false, false>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work,
+                     nwork, ts.bx, ts.by, parity, 0, partials, rout);
   return hipGetLastError();
 }
 

@@ -220,3 +220,22 @@ def test_fused_solve_independent_of_launch_shape(monkeypatch, tile):
     assert info["stats"]["tile_group"] == int(tile.split(",")[3])
     assert np.array_equal(info["iters"], iref["iters"])
     assert np.max(np.abs(C - Cref)) <= 1e-12 * np.abs(Cref).max()
+
+
+@pytest.mark.parametrize("tile", ["34,14,0,2,2", "34,14,7,6,2", "18,22,0,1,2"])
+def test_unrolled_march_matches(monkeypatch, tile):
+    p = need_gpu()
+    K, G = synth.random_fields((23, 19, 17), 41, lo=(2.0, 1.0), hi=(90.0, 45.0))
+    monkeypatch.setenv("CEFF_TILE", "34,14,0,2,0")
+    Cref, iref = p.solve(K, G, precision="mixed", rtol=1e-9)
+    monkeypatch.setenv("CEFF_TILE", tile)
+    announce("unrolled", tile)
+    C, info = p.solve(K, G, precision="mixed", rtol=1e-9)
+    assert np.array_equal(info["iters"], iref["iters"])
+    assert np.max(np.abs(C - Cref)) <= 1e-12 * np.abs(Cref).max()
+    for prec in ("fp64",):
+        Cr, ir = p.solve(K, G, precision=prec, rtol=1e-9, fuse_loads=False)
+        monkeypatch.setenv("CEFF_TILE", "34,14,0,1,0")
+        Cq, iq = p.solve(K, G, precision=prec, rtol=1e-9, fuse_loads=False)
+        assert np.array_equal(Cr, Cq)
+        monkeypatch.setenv("CEFF_TILE", tile)
