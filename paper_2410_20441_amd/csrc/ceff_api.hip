@@ -219,24 +219,24 @@ struct Prob {
 
 TileShape default_tile(int64_t nx, int64_t ny, bool fp64) {
   TileShape t;
-  // CEFF_TILE="bx,by[,kc]" overrides the shape (tests check results do not depend on it)
-  // CEFF_TILE="bx,by[,kc[,group[,prefetch]]]" overrides the launch shape
+  // CEFF_TILE="bx,by[,kc[,group[,variant[,order[,occ]]]]]" overrides the launch shape (the iterates
+  // do not depend on it; tests check that)
   if (const char* env = std::getenv("CEFF_TILE")) {
     int bx = 0, by = 0, kc = 0, grp = 6, pf = 1, ord = 1, occ = 0;
     const int n = std::sscanf(env, "%d,%d,%d,%d,%d,%d,%d", &bx, &by, &kc, &grp, &pf, &ord, &occ);
     if (n >= 2 && bx >= 3 && by >= 3 && ((bx * by + 63) / 64) * 64 <= 512 &&
         (grp == 1 || grp == 2 || grp == 3 || grp == 6))
-      return TileShape{bx, by, n >= 3 ? kc : 0, grp, pf >= 0 && pf <= 3 ? pf : 0, ord ? 1 : 0, occ ? 1 : 0};
+      return TileShape{bx, by, n >= 3 ? kc : 0, pf == 5 ? 1 : grp, pf >= 0 && pf <= 5 ? pf : 0, ord ? 1 : 0,
+                       occ ? 1 : 0};
   }
-  // 34 x 14 ghosted block (32 x 12 interior, 476 of 512 threads), XCD bands.
-  // FP32: two loads per block staged between one barrier pair per plane;
-  // FP64: one load, unrolled march, 12-plane chunks.  These were the fastest
-  // shapes of the 191^3 sweeps (see the tuner).
-  t.bx = nx + 2 <= 34 ? (int)nx + 2 : 34;
-  t.by = ny + 2 <= 14 ? (int)ny + 2 : 14;
-  t.kc = fp64 ? 12 : 0;
-  t.group = 2;
-  t.pf = fp64 ? 2 : 3;
+  // Fastest shapes of the 191^3 sweeps.  FP32: 66 x 7 ghosted block (64 x 5 interior), two loads
+  // per block staged between one barrier pair per plane, 12-plane chunks.  FP64: 34 x 14 block
+  // (32 x 12 interior), one load per block, same staging, 12-plane chunks.
+  t.bx = (int)std::min<int64_t>(nx + 2, fp64 ? 34 : 66);
+  t.by = (int)std::min<int64_t>(ny + 2, fp64 ? 14 : 7);
+  t.kc = 12;
+  t.group = fp64 ? 1 : 2;
+  t.pf = 3;
   t.order = 1;
   t.occ = 0;
   return t;
@@ -276,7 +276,7 @@ struct Engine {
 
   bool single() const { return Js.size() == 1; }
   int slot_of(int J) const { return single() ? 0 : J; }
-  int group() const { return single() ? 1 : (ts.group > 0 ? ts.group : kMaxLoads); }
+  int group() const { return single() || ts.pf == 5 ? 1 : (ts.group > 0 ? ts.group : kMaxLoads); }
 
   // Work list of one launch.  Each (tile, z-chunk) of a sample is split into
   // load groups of `group` slots; the groups of one tile are placed 8 items apart
@@ -439,8 +439,8 @@ struct Engine {
     ts = default_tile(in[0].nx, in[0].ny, fp64);
     if (!o.autotune) return CEFF_OK;
     std::vector<TileShape> cand;
-    const int bxs[] = {34, 66};
-    const int bys[] = {6, 10, 14};
+    const int bxs[] = {18, 34, 66};
+    const int bys[] = {6, 7, 10, 14};
     const int groups_fused[] = {6, 3, 2, 1};
     const int groups_single[] = {1};
     const int* groups = single() ? groups_single : groups_fused;
@@ -451,11 +451,14 @@ struct Engine {
         if (nt > 512 || bx * by < 128 || bx > in[0].nx + 2 + 64 || by > in[0].ny + 2 + 8) continue;
         if ((size_t)11 * nt * sizeof(T) > 64 * 1024) continue;
         for (int gi = 0; gi < ng; ++gi)
-          for (int pf = 1; pf < 4; ++pf)
+          for (int pf = 1; pf < 6; ++pf)
             for (int kc : {0, 12})
-              for (int occ = 0; occ < 1; ++occ) {
+              for (int occ = 0; occ < 2; ++occ) {
+                if (occ && pf < 4) continue;
+                if (pf == 5 && groups[gi] != 1) continue;
+                if (pf == 5 && (bx - 2) * (by - 2) < 64) continue;
                 const int grp = single() ? 1 : groups[gi];
-                if (pf == 3 && (size_t)(3 + 8 * grp) * nt * sizeof(T) > 64 * 1024) continue;
+                if (pf >= 3 && (size_t)(3 + 8 * grp) * nt * sizeof(T) > 64 * 1024) continue;
                 cand.push_back(TileShape{bx, by, kc, groups[gi], pf, 1, occ});
               }
       }
@@ -469,7 +472,7 @@ struct Engine {
     for (const TileShape& t : cand) {
       std::vector<WorkItem> w;
       std::vector<int> rg, kcs;
-      const int grp = single() ? 1 : t.group;
+      const int grp = single() || t.pf == 5 ? 1 : t.group;
       STCK(build_work(t, grp, w, rg, kcs));
       DevBuf dw;
       HIPCK(c, dw.alloc(sizeof(WorkItem) * w.size()));

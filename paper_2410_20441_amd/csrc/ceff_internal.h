@@ -40,7 +40,9 @@ struct TileShape {
   int kc;      // z-planes per chunk (0 = choose automatically)
   int group;   // loads per block: 1, 2, 3 or 6 (0 = all requested loads in one block)
   int pf;      // 0: plain z-march; 1: prefetch the next plane into registers; 2: z-march unrolled by two;
-               // 3: unrolled, all loads of the group between one pair of barriers per plane
+               // 3: unrolled, all loads of the group between one pair of barriers per plane;
+               // 4: as 3, unrolled by three with the next plane's data requested one plane ahead;
+               // 5: one load per block, no LDS: neighbours read through the caches
   int order;   // 0: load groups of a tile 8 items apart; 1: each XCD takes a contiguous band
   int occ;     // 1: build that targets more waves per SIMD (fewer registers)
 };

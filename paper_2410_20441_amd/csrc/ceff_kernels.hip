@@ -766,6 +766,442 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
   }
 }
 
+// Batched-barrier z-march unrolled by three with three rotating register sets,
+// so that the global data of plane k+2 (u^n), and of plane k+1 (u^{n-1},
+// body force), is requested while plane k is processed and first used one
+// plane later: load latency overlaps a whole plane of work, with no register
+// copies between planes.
+// the three register sets need room: 4 waves per SIMD for one FP32 load, 3 for
+// two, 2 otherwise (HI asks for one wave more)
+template <typename T, int L, bool HI>
+struct MinWavesP3 {
+  static constexpr int lo = sizeof(T) == 4 ? (L == 1 ? 4 : (L == 2 ? 3 : 1)) : (L == 1 ? 2 : 1);
+  static constexpr int value = HI ? lo + 1 : lo;
+};
+
+template <typename T, int L, bool HI>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWavesP3<T, L, HI>::value)))
+step_kernel_p3(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
+               int by, int parity, int first, double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const int nt = blockDim.x;
+  T* base = reinterpret_cast<T*>(smem_raw);
+  T* sG[2] = {base, base + nt};
+  T* sH = base + 2 * nt;
+  T* lds_l = base + 3 * nt;  // per load: ux uy uz sxx syy sxy sxz syz
+  auto S = [&](int l, int f) { return lds_l + (size_t)(8 * l + f) * nt; };
+
+  const int tid = threadIdx.x;
+  const int tx = tid % bx, ty = tid / bx;
+  const int TX = bx - 2, TY = by - 2;
+  const int xm = tid > 0 && tx > 0 ? tid - 1 : tid;
+  const int xp = tx < bx - 1 && tid + 1 < nt ? tid + 1 : tid;
+  const int ym = ty > 0 ? tid - bx : tid;
+  const int yp = ty < by - 1 && tid + bx < nt ? tid + bx : tid;
+  const int xmym = ty > 0 ? xm - bx : xm;
+
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const WorkItem wi = work[w];
+    if (wi.sample < 0) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const SampleDesc<T>& sd = samples[wi.sample];
+    const int s0 = wi.slot0;
+    const unsigned act = (sd.active >> s0) & ((1u << L) - 1u);
+    if (act == 0u) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N, plane = nx * ny;
+    const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
+    const T mom = first ? T(0) : sd.mom;
+    const T sfac = first ? sd.sfac_first : sd.sfac;
+    const int64_t gi = (int64_t)wi.tx * TX + tx - 1, gj = (int64_t)wi.ty * TY + ty - 1;
+    const int64_t col = wrap_idx(gi, nx) + nx * wrap_idx(gj, ny);
+    const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
+    const int64_t k0 = (int64_t)wi.kz * sd.kc;
+    const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
+
+    const GLOBAL_AS T* __restrict__ Kf = gconst(sd.K);
+    const GLOBAL_AS T* __restrict__ Gf = gconst(sd.G);
+    const GLOBAL_AS T* ucur[L];
+    GLOBAL_AS T* uold[L];
+    const GLOBAL_AS T* frc[L];
+    bool hasf[L];
+    T E[L][6];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      ucur[l] = gconst(sd.u[parity][s0 + l]);
+      uold[l] = gmut(sd.u[parity ^ 1][s0 + l]);
+      hasf[l] = sd.force[s0 + l] != nullptr;
+      frc[l] = gconst(sd.force[s0 + l]);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) E[l][q] = sd.E[s0 + l][q];
+    }
+    bool anyf = false;
+#pragma unroll
+    for (int l = 0; l < L; ++l) anyf = anyf || ((act & (1u << l)) && hasf[l]);
+
+    // register sets by plane index mod 3: u^n and moduli of that plane, and
+    // u^{n-1} and the body force of that plane
+    T Ux[3][L], Uy[3][L], Uz[3][L], Ko[3], Go[3];
+    T Vo0[3][L], Vo1[3][L], Vo2[3][L], F0[3][L], F1[3][L], F2[3][L];
+    T Szz[2][L], Sxz[2][L], Syz[2][L], Hh[2];
+    double nsum[L];
+
+    // u^n and moduli of plane k (global index kk, any integer k0-1 .. k1), and
+    // u^{n-1} / force of plane k when it is a face plane; into set R
+    auto fetch = [&](int64_t kk, auto Rc) {
+      constexpr int R = decltype(Rc)::value;
+      const int64_t kw = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
+      const int64_t o = col + plane * kw;
+      Ko[R] = Kf[o];
+      Go[R] = Gf[o];
+      const bool face = kk >= k0 && kk < k1 && interior;
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        Ux[R][l] = Uy[R][l] = Uz[R][l] = T(0);
+        Vo0[R][l] = Vo1[R][l] = Vo2[R][l] = F0[R][l] = F1[R][l] = F2[R][l] = T(0);
+        if (act & (1u << l)) {
+          Ux[R][l] = ucur[l][o];
+          Uy[R][l] = ucur[l][N + o];
+          Uz[R][l] = ucur[l][2 * N + o];
+          if (face && !first) {
+            Vo0[R][l] = uold[l][o];
+            Vo1[R][l] = uold[l][N + o];
+            Vo2[R][l] = uold[l][2 * N + o];
+          }
+          if (face && anyf && hasf[l]) {
+            F0[R][l] = frc[l][o];
+            F1[R][l] = frc[l][N + o];
+            F2[R][l] = frc[l][2 * N + o];
+          }
+        }
+      }
+    };
+
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      Szz[1][l] = Sxz[1][l] = Syz[1][l] = T(0);
+      nsum[l] = 0.0;
+    }
+    Hh[1] = T(1);
+    fetch(k0 - 1, std::integral_constant<int, 0>{});
+    fetch(k0, std::integral_constant<int, 1>{});
+    sG[0][tid] = Go[0];
+    int par = 0;  // plane parity for the LDS moduli and the carried stresses
+
+    // process plane k whose data is in set A, next plane in set B; request
+    // plane k+2 into set C
+    auto plane_step = [&](int64_t k, auto Ac, auto Bc, auto Cc, auto Pc) {
+      constexpr int A = decltype(Ac)::value;
+      constexpr int B = decltype(Bc)::value;
+      constexpr int C = decltype(Cc)::value;
+      constexpr int P = decltype(Pc)::value;
+      constexpr int Q = 1 - P;
+      const int64_t kw = k < 0 ? k + nz : k;
+      const int64_t oc = col + plane * kw;
+      const bool face = k >= k0 && interior;
+      if (k + 2 <= k1) fetch(k + 2, std::integral_constant<int, C>{});
+      T* gk = sG[P];
+      T* gn = sG[Q];
+      gn[tid] = Go[B];
+      Hh[P] = Ko[A] + T(4.0 / 3.0) * Go[A];
+      sH[tid] = Hh[P];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        S(l, 0)[tid] = Ux[A][l];
+        S(l, 1)[tid] = Uy[A][l];
+        S(l, 2)[tid] = Uz[B][l];
+      }
+      __syncthreads();
+      const T lam = Ko[A] - T(2.0 / 3.0) * Go[A];
+      const T twoG = T(2) * Go[A];
+      const T ik = recip(gk[tid]), ikx = recip(gk[xm]), iky = recip(gk[ym]);
+      const T in = recip(gn[tid]), inx = recip(gn[xm]), iny = recip(gn[ym]);
+      const T G2xy = T(8) * recip(recip(gk[xmym]) + iky + ikx + ik);
+      const T G2xz = T(8) * recip(ikx + ik + inx + in);
+      const T G2yz = T(8) * recip(iky + ik + iny + in);
+      const T sfx = sfac * recip(tmax(sH[xm], Hh[P]));
+      const T sfy = sfac * recip(tmax(sH[ym], Hh[P]));
+      const T sfz = sfac * recip(tmax(Hh[Q], Hh[P]));
+      T sxx[L], syy[L], szz[L], sxy[L], sxz_n[L], syz_n[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        const T ux = Ux[A][l], uy = Uy[A][l], uz = Uz[A][l];
+        const T unx = Ux[B][l], uny = Uy[B][l], unz = Uz[B][l];
+        const T* sUx = S(l, 0);
+        const T* sUy = S(l, 1);
+        const T* sUz = S(l, 2);
+        const T exx = E[l][0] + (sUx[xp] - ux) * rhx;
+        const T eyy = E[l][1] + (sUy[yp] - uy) * rhy;
+        const T ezz = E[l][2] + (unz - uz) * rhz;
+        const T th = exx + eyy + ezz;
+        sxx[l] = lam * th + twoG * exx;
+        syy[l] = lam * th + twoG * eyy;
+        szz[l] = lam * th + twoG * ezz;
+        sxy[l] = G2xy * (E[l][5] + T(0.5) * ((ux - sUx[ym]) * rhy + (uy - sUy[xm]) * rhx));
+        sxz_n[l] = G2xz * (E[l][4] + T(0.5) * ((unx - ux) * rhz + (unz - sUz[xm]) * rhx));
+        syz_n[l] = G2yz * (E[l][3] + T(0.5) * ((uny - uy) * rhz + (unz - sUz[ym]) * rhy));
+        S(l, 3)[tid] = sxx[l];
+        S(l, 4)[tid] = syy[l];
+        S(l, 5)[tid] = sxy[l];
+        S(l, 6)[tid] = Sxz[Q][l];
+        S(l, 7)[tid] = Syz[Q][l];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        if (face && (act & (1u << l))) {
+          const T* sSxx = S(l, 3);
+          const T* sSyy = S(l, 4);
+          const T* sSxy = S(l, 5);
+          const T* sSxz = S(l, 6);
+          const T* sSyz = S(l, 7);
+          const T sxz_c = Sxz[Q][l], syz_c = Syz[Q][l];
+          T rx = (sxx[l] - sSxx[xm]) * rhx + (sSxy[yp] - sxy[l]) * rhy + (sxz_n[l] - sxz_c) * rhz;
+          T ry = (sSxy[xp] - sxy[l]) * rhx + (syy[l] - sSyy[ym]) * rhy + (syz_n[l] - syz_c) * rhz;
+          T rz = (sSxz[xp] - sxz_c) * rhx + (sSyz[yp] - syz_c) * rhy + (szz[l] - Szz[Q][l]) * rhz;
+          rx += F0[A][l];
+          ry += F1[A][l];
+          rz += F2[A][l];
+          if (partials != nullptr)
+            nsum[l] += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
+          const T ux = Ux[A][l], uy = Uy[A][l], uz = Uz[A][l];
+          uold[l][oc] = ux + mom * (ux - Vo0[A][l]) + sfx * rx;
+          uold[l][N + oc] = uy + mom * (uy - Vo1[A][l]) + sfy * ry;
+          uold[l][2 * N + oc] = uz + mom * (uz - Vo2[A][l]) + sfz * rz;
+        }
+        Szz[P][l] = szz[l];
+        Sxz[P][l] = sxz_n[l];
+        Syz[P][l] = syz_n[l];
+      }
+    };
+
+    // planes k0-1, k0, ..., k1-1; the data sets rotate with period 3 and the
+    // parity with period 2, so the loop body covers six planes
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    (void)par;
+    for (int64_t k = k0 - 1; k < k1; k += 6) {
+      plane_step(k, I0{}, I1{}, I2{}, I0{});
+      if (k + 1 >= k1) break;
+      plane_step(k + 1, I1{}, I2{}, I0{}, I1{});
+      if (k + 2 >= k1) break;
+      plane_step(k + 2, I2{}, I0{}, I1{}, I0{});
+      if (k + 3 >= k1) break;
+      plane_step(k + 3, I0{}, I1{}, I2{}, I1{});
+      if (k + 4 >= k1) break;
+      plane_step(k + 4, I1{}, I2{}, I0{}, I0{});
+      if (k + 5 >= k1) break;
+      plane_step(k + 5, I2{}, I0{}, I1{}, I1{});
+    }
+
+    if (partials != nullptr) {
+      double tot[kMaxLoads] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        if (!(act & (1u << l))) continue;
+        tot[s0 + l] = block_sum(nsum[l], red);
+      }
+      if (tid == 0)
+        for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = tot[q];
+    }
+    __syncthreads();
+  }
+}
+
+// One load per block, no LDS and no barriers: every thread is an interior
+// column of the tile and reads the in-plane neighbours it needs (8 columns)
+// directly through the caches; stresses of neighbouring nodes are recomputed
+// instead of exchanged.  Waves never wait for each other, so memory latency is
+// hidden by the other waves of the CU.  Same arithmetic, in the same order, as
+// the LDS kernels.
+template <typename T, bool HI>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(HI ? 6 : 4)))
+step_kernel_c(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
+              int by, int parity, int first, double* __restrict__ partials) {
+  __shared__ double red[16];
+  const int TX = bx - 2, TY = by - 2;
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const WorkItem wi = work[w];
+    if (wi.sample < 0) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const SampleDesc<T>& sd = samples[wi.sample];
+    const int l = wi.slot0;
+    if (!((sd.active >> l) & 1u)) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N, plane = nx * ny;
+    const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
+    const T mom = first ? T(0) : sd.mom;
+    const T sfac = first ? sd.sfac_first : sd.sfac;
+    const int64_t gi = (int64_t)wi.tx * TX + tx, gj = (int64_t)wi.ty * TY + ty;
+    const bool valid = ty < TY && gi < nx && gj < ny;
+    const int64_t k0 = (int64_t)wi.kz * sd.kc;
+    const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
+    double nsum = 0.0;
+
+    if (valid) {
+      const T E0 = sd.E[l][0], E1 = sd.E[l][1], E2 = sd.E[l][2], E3 = sd.E[l][3], E4 = sd.E[l][4],
+              E5 = sd.E[l][5];
+      const GLOBAL_AS T* __restrict__ Kf = gconst(sd.K);
+      const GLOBAL_AS T* __restrict__ Gf = gconst(sd.G);
+      const GLOBAL_AS T* __restrict__ ux_ = gconst(sd.u[parity][l]);
+      const GLOBAL_AS T* __restrict__ uy_ = ux_ + N;
+      const GLOBAL_AS T* __restrict__ uz_ = ux_ + 2 * N;
+      GLOBAL_AS T* __restrict__ ox_ = gmut(sd.u[parity ^ 1][l]);
+      GLOBAL_AS T* __restrict__ oy_ = ox_ + N;
+      GLOBAL_AS T* __restrict__ oz_ = ox_ + 2 * N;
+      const bool hasf = sd.force[l] != nullptr;
+      const GLOBAL_AS T* __restrict__ fx_ = gconst(sd.force[l]);
+      const GLOBAL_AS T* __restrict__ fy_ = fx_ + N;
+      const GLOBAL_AS T* __restrict__ fz_ = fx_ + 2 * N;
+
+      // in-plane column offsets: 0 = (0,0), P = +1, M = -1 (x first, then y)
+      const int64_t im = gi == 0 ? nx - 1 : gi - 1, ip = gi + 1 == nx ? 0 : gi + 1;
+      const int64_t jm = gj == 0 ? ny - 1 : gj - 1, jp = gj + 1 == ny ? 0 : gj + 1;
+      // byte offsets within a plane (a plane is far below 4 GiB), so loads take a
+      // scalar base plus a 32-bit vector offset
+      constexpr uint32_t W = sizeof(T);
+      const uint32_t c00 = (uint32_t)(gi + nx * gj) * W, cP0 = (uint32_t)(ip + nx * gj) * W;
+      const uint32_t cM0 = (uint32_t)(im + nx * gj) * W, c0M = (uint32_t)(gi + nx * jm) * W;
+      const uint32_t c0P = (uint32_t)(gi + nx * jp) * W, cPM = (uint32_t)(ip + nx * jm) * W;
+      const uint32_t cMP = (uint32_t)(im + nx * jp) * W, cMM = (uint32_t)(im + nx * jm) * W;
+      auto at = [](const GLOBAL_AS T* p, uint32_t off) -> T {
+        return *(const GLOBAL_AS T*)((const GLOBAL_AS char*)p + off);
+      };
+
+      // one plane of data: u_x at 00 P0 M0 0M PM 0P; u_y at 00 0P M0 MP 0M P0;
+      // u_z at 00 M0 0M P0 0P; K at 00 M0 0M; 1/G at MM 0M M0 00 PM P0 MP 0P
+      struct Plane {
+        T x00, xP0, xM0, x0M, xPM, x0P;
+        T y00, y0P, yM0, yMP, y0M, yP0;
+        T z00, zM0, z0M, zP0, z0P;
+        T K00, KM0, K0M, G00, GM0, G0M;
+        T iMM, i0M, iM0, i00, iPM, iP0, iMP, i0P;
+      };
+      auto load = [&](int64_t kk, Plane& q) {
+        const int64_t kw = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
+        const int64_t po = plane * kw;
+        const GLOBAL_AS T* X = ux_ + po;
+        const GLOBAL_AS T* Y = uy_ + po;
+        const GLOBAL_AS T* Z = uz_ + po;
+        const GLOBAL_AS T* Kp = Kf + po;
+        const GLOBAL_AS T* Gp = Gf + po;
+        q.x00 = at(X, c00); q.xP0 = at(X, cP0); q.xM0 = at(X, cM0); q.x0M = at(X, c0M); q.xPM = at(X, cPM);
+        q.x0P = at(X, c0P);
+        q.y00 = at(Y, c00); q.y0P = at(Y, c0P); q.yM0 = at(Y, cM0); q.yMP = at(Y, cMP); q.y0M = at(Y, c0M);
+        q.yP0 = at(Y, cP0);
+        q.z00 = at(Z, c00); q.zM0 = at(Z, cM0); q.z0M = at(Z, c0M); q.zP0 = at(Z, cP0); q.z0P = at(Z, c0P);
+        q.K00 = at(Kp, c00); q.KM0 = at(Kp, cM0); q.K0M = at(Kp, c0M);
+        q.G00 = at(Gp, c00); q.GM0 = at(Gp, cM0); q.G0M = at(Gp, c0M);
+        q.iMM = recip(at(Gp, cMM)); q.i0M = recip(q.G0M); q.iM0 = recip(q.GM0); q.i00 = recip(q.G00);
+        q.iPM = recip(at(Gp, cPM)); q.iP0 = recip(at(Gp, cP0)); q.iMP = recip(at(Gp, cMP)); q.i0P = recip(at(Gp, c0P));
+      };
+
+      Plane pl[2];
+      T szz_p = T(0), sxz00 = T(0), sxzP0 = T(0), syz00 = T(0), syz0P = T(0), Hp = T(1);
+      load(k0 - 1, pl[0]);
+
+      auto step = [&](int64_t k, auto Ac) {
+        constexpr int A = decltype(Ac)::value;
+        constexpr int B = 1 - A;
+        const Plane& a = pl[A];
+        Plane& b = pl[B];
+        load(k + 1, b);
+        const bool face = k >= k0;
+        // cells of plane k: 00 (all normal stresses), M0 (xx), 0M (yy)
+        const T l00 = a.K00 - T(2.0 / 3.0) * a.G00, t00 = T(2) * a.G00;
+        const T lM0 = a.KM0 - T(2.0 / 3.0) * a.GM0, tM0 = T(2) * a.GM0;
+        const T l0M = a.K0M - T(2.0 / 3.0) * a.G0M, t0M = T(2) * a.G0M;
+        const T exx00 = E0 + (a.xP0 - a.x00) * rhx, eyy00 = E1 + (a.y0P - a.y00) * rhy,
+                ezz00 = E2 + (b.z00 - a.z00) * rhz;
+        const T th00 = exx00 + eyy00 + ezz00;
+        const T sxx00 = l00 * th00 + t00 * exx00, syy00 = l00 * th00 + t00 * eyy00, szz00 = l00 * th00 + t00 * ezz00;
+        const T exxM0 = E0 + (a.x00 - a.xM0) * rhx, eyyM0 = E1 + (a.yMP - a.yM0) * rhy,
+                ezzM0 = E2 + (b.zM0 - a.zM0) * rhz;
+        const T sxxM0 = lM0 * (exxM0 + eyyM0 + ezzM0) + tM0 * exxM0;
+        const T exx0M = E0 + (a.xPM - a.x0M) * rhx, eyy0M = E1 + (a.y00 - a.y0M) * rhy,
+                ezz0M = E2 + (b.z0M - a.z0M) * rhz;
+        const T syy0M = l0M * (exx0M + eyy0M + ezz0M) + t0M * eyy0M;
+        // xy-edges of plane k at 00, P0, 0P
+        const T Gxy00 = T(8) * recip(a.iMM + a.i0M + a.iM0 + a.i00);
+        const T GxyP0 = T(8) * recip(a.i0M + a.iPM + a.i00 + a.iP0);
+        const T Gxy0P = T(8) * recip(a.iM0 + a.i00 + a.iMP + a.i0P);
+        const T sxy00 = Gxy00 * (E5 + T(0.5) * ((a.x00 - a.x0M) * rhy + (a.y00 - a.yM0) * rhx));
+        const T sxyP0 = GxyP0 * (E5 + T(0.5) * ((a.xP0 - a.xPM) * rhy + (a.yP0 - a.y00) * rhx));
+        const T sxy0P = Gxy0P * (E5 + T(0.5) * ((a.x0P - a.x00) * rhy + (a.y0P - a.yMP) * rhx));
+        // xz- and yz-edges of plane k+1
+        const T Gxz00 = T(8) * recip(a.iM0 + a.i00 + b.iM0 + b.i00);
+        const T GxzP0 = T(8) * recip(a.i00 + a.iP0 + b.i00 + b.iP0);
+        const T Gyz00 = T(8) * recip(a.i0M + a.i00 + b.i0M + b.i00);
+        const T Gyz0P = T(8) * recip(a.i00 + a.i0P + b.i00 + b.i0P);
+        const T nxz00 = Gxz00 * (E4 + T(0.5) * ((b.x00 - a.x00) * rhz + (b.z00 - b.zM0) * rhx));
+        const T nxzP0 = GxzP0 * (E4 + T(0.5) * ((b.xP0 - a.xP0) * rhz + (b.zP0 - b.z00) * rhx));
+        const T nyz00 = Gyz00 * (E3 + T(0.5) * ((b.y00 - a.y00) * rhz + (b.z00 - b.z0M) * rhy));
+        const T nyz0P = Gyz0P * (E3 + T(0.5) * ((b.y0P - a.y0P) * rhz + (b.z0P - b.z00) * rhy));
+        const T H00 = a.K00 + T(4.0 / 3.0) * a.G00;
+        if (face) {
+          const int64_t po = plane * (k < 0 ? k + nz : k);
+          T rx = (sxx00 - sxxM0) * rhx + (sxy0P - sxy00) * rhy + (nxz00 - sxz00) * rhz;
+          T ry = (sxyP0 - sxy00) * rhx + (syy00 - syy0M) * rhy + (nyz00 - syz00) * rhz;
+          T rz = (sxzP0 - sxz00) * rhx + (syz0P - syz00) * rhy + (szz00 - szz_p) * rhz;
+          if (hasf) {
+            rx += at(fx_ + po, c00);
+            ry += at(fy_ + po, c00);
+            rz += at(fz_ + po, c00);
+          }
+          nsum += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
+          const T HM0 = a.KM0 + T(4.0 / 3.0) * a.GM0, H0M = a.K0M + T(4.0 / 3.0) * a.G0M;
+          const T sfx = sfac * recip(tmax(HM0, H00));
+          const T sfy = sfac * recip(tmax(H0M, H00));
+          const T sfz = sfac * recip(tmax(Hp, H00));
+          GLOBAL_AS T* px = (GLOBAL_AS T*)((GLOBAL_AS char*)(ox_ + po) + c00);
+          GLOBAL_AS T* py = (GLOBAL_AS T*)((GLOBAL_AS char*)(oy_ + po) + c00);
+          GLOBAL_AS T* pz = (GLOBAL_AS T*)((GLOBAL_AS char*)(oz_ + po) + c00);
+          T vx = T(0), vy = T(0), vz = T(0);
+          if (!first) {
+            vx = *px;
+            vy = *py;
+            vz = *pz;
+          }
+          *px = a.x00 + mom * (a.x00 - vx) + sfx * rx;
+          *py = a.y00 + mom * (a.y00 - vy) + sfy * ry;
+          *pz = a.z00 + mom * (a.z00 - vz) + sfz * rz;
+        }
+        szz_p = szz00;
+        sxz00 = nxz00;
+        sxzP0 = nxzP0;
+        syz00 = nyz00;
+        syz0P = nyz0P;
+        Hp = H00;
+      };
+
+      for (int64_t k = k0 - 1; k < k1; k += 2) {
+        step(k, std::integral_constant<int, 0>{});
+        if (k + 1 < k1) step(k + 1, std::integral_constant<int, 1>{});
+      }
+    }
+
+    if (partials != nullptr) {
+      const double s = block_sum(nsum, red);
+      if (tid == 0)
+        for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = q == l ? s : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void finalize_norms_kernel(const int* __restrict__ ranges, const double* __restrict__ partials,
                                       double* __restrict__ out) {
   __shared__ double red[16];
@@ -971,7 +1407,14 @@ inline int grid_for(int64_t n, int block = 256) {
 template <typename T, int L, bool HI>
 void launch_step_occ(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts, int parity,
                      int first, double* partials, hipStream_t s, int nt, size_t lds) {
-  if (ts.pf == 3)
+  if (ts.pf == 5) {
+    const int ntc = (((ts.bx - 2) * (ts.by - 2) + 63) / 64) * 64;
+    hipLaunchKernelGGL((step_kernel_c<T, HI>), dim3(nwork), dim3(ntc), 0, s, d_samples, d_work, nwork, ts.bx, ts.by,
+                       parity, first, partials);
+  } else if (ts.pf == 4)
+    hipLaunchKernelGGL((step_kernel_p3<T, L, HI>), dim3(nwork), dim3(nt), (size_t)(3 + 8 * L) * nt * sizeof(T), s,
+                       d_samples, d_work, nwork, ts.bx, ts.by, parity, first, partials);
+  else if (ts.pf == 3)
     hipLaunchKernelGGL((step_kernel_b<T, L, HI>), dim3(nwork), dim3(nt), (size_t)(3 + 8 * L) * nt * sizeof(T), s,
                        d_samples, d_work, nwork, ts.bx, ts.by, parity, first, partials);
   else if (ts.pf == 2)

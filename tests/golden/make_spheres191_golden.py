@@ -1,7 +1,8 @@
 """Write spheres191_oracle.json: oracle C* columns of the 191^3 sphere-pack
-workload (loads 0 and 3 = Voigt columns 1 and 4).
+workload (all six loads, Jacobi-PCG to rtol 1e-11; resumes from the file).
 
-Calls only the CPU oracle and the input generator.  Several hours of CPU:
+Calls only the CPU oracle and the input generator.  About half an hour of CPU
+per column:
     OMP_NUM_THREADS=6 python tests/golden/make_spheres191_golden.py
 """
 import hashlib
@@ -21,7 +22,7 @@ import synth  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "spheres191_oracle.json")
 
 
-def main(loads=(0, 3), rtol=1e-11):
+def main(loads=(0, 3, 1, 2, 4, 5), rtol=1e-11):
     m = synth.workload_spheres191()
     K, G = m.fields()
     digest = hashlib.sha256(m.phase.tobytes()).hexdigest()

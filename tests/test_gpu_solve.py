@@ -222,7 +222,7 @@ def test_fused_solve_independent_of_launch_shape(monkeypatch, tile):
     assert np.max(np.abs(C - Cref)) <= 1e-12 * np.abs(Cref).max()
 
 
-@pytest.mark.parametrize("tile", ["34,14,0,2,2", "34,14,7,6,2", "18,22,0,1,2"])
+@pytest.mark.parametrize("tile", ["34,14,0,2,2", "34,14,7,6,2", "18,22,0,1,2", "34,14,0,2,3", "34,14,0,2,4", "18,14,5,1,4", "34,7,11,3,4", "66,6,0,1,5", "34,10,7,1,5", "10,66,0,1,5"])
 def test_unrolled_march_matches(monkeypatch, tile):
     p = need_gpu()
     K, G = synth.random_fields((23, 19, 17), 41, lo=(2.0, 1.0), hi=(90.0, 45.0))
@@ -233,9 +233,10 @@ def test_unrolled_march_matches(monkeypatch, tile):
     C, info = p.solve(K, G, precision="mixed", rtol=1e-9)
     assert np.array_equal(info["iters"], iref["iters"])
     assert np.max(np.abs(C - Cref)) <= 1e-12 * np.abs(Cref).max()
-    for prec in ("fp64",):
-        Cr, ir = p.solve(K, G, precision=prec, rtol=1e-9, fuse_loads=False)
-        monkeypatch.setenv("CEFF_TILE", "34,14,0,1,0")
-        Cq, iq = p.solve(K, G, precision=prec, rtol=1e-9, fuse_loads=False)
-        assert np.array_equal(Cr, Cq)
-        monkeypatch.setenv("CEFF_TILE", tile)
+    # FP64, one load at a time: the variants are separate kernels whose compiler
+    # may contract multiply-adds differently, so agreement is to rounding
+    Cr, ir = p.solve(K, G, precision="fp64", rtol=1e-9, fuse_loads=False)
+    monkeypatch.setenv("CEFF_TILE", "34,14,0,1,0")
+    Cq, iq = p.solve(K, G, precision="fp64", rtol=1e-9, fuse_loads=False)
+    assert np.array_equal(ir["iters"], iq["iters"])
+    assert np.max(np.abs(Cr - Cq)) <= 1e-12 * np.abs(Cq).max()
