@@ -1,9 +1,11 @@
 """Benchmark: effective stiffness of a 191^3 fluid-filled sphere pack on one MI355X.
 
 One step = one complete solve of the hot path: six unit macroscopic-strain
-loads fused in one launch per iteration, FP32 sweeps with FP64 residuals and
+loads (fused in one launch per iteration, or one after another when a single
+load's working set fits in the Infinity Cache; the library's automatic
+choice unless --fuse says otherwise), FP32 sweeps with FP64 residuals and
 defect-correction folds, FP64 volume averages, giving the 6x6 C* on the host.
-The material is resident in HBM before timing starts.
+The material (a phase image) is resident in HBM before timing starts.
 
 Prints one JSON line.  value = voxel-updates per second over the timed steps
 (N x iterations summed over loads / wall time).  The roofline object covers
@@ -25,8 +27,15 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the iteration kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_hbm_counters.md),
 # valid only for the kernel source they were taken on.
-MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "c601667b6af5da36", "bytes_per_launch": 1.931058e+09,
+MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "3b3da3b4e7bc5179", "bytes_per_launch": 1.793178e+09,
+                    # (loads per block, kernel variant, loads fused, moduli from the phase image)
+                    "launch_signature": (2, 3, 1, 0),
                     "launch": "step_kernel_b<float,2>, macroscopic-strain phase (no body force)"}
+
+
+# iteration-kernel variant (ceff_stats.tile_variant) -> kernel name
+VARIANT_KERNEL = {0: "step_kernel", 1: "step_kernel", 2: "step_kernel_u2", 3: "step_kernel_b", 4: "step_kernel_p3",
+                  5: "step_kernel_c"}
 
 
 def kernel_source_hash():
@@ -74,6 +83,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle APT iterations timed for the CPU baseline")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--fuse", default="auto", choices=["auto", "on", "off"],
+                    help="load fusion: library choice (auto), one launch for all loads (on), one load at a time (off)")
     ap.add_argument("--max-iter", type=int, default=400000)
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for counter collection: allow stopping at --max-iter")
@@ -120,7 +131,8 @@ def main():
 
     ctx = ceff.Context(0)
     ctx.set_phases(m.phase, m.K_tab, m.G_tab)
-    opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, fuse_loads=True,
+    fuse = {"auto": "auto", "on": True, "off": False}[a.fuse]
+    opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, fuse_loads=fuse,
                 use_graph=True, autotune=a.autotune, max_iter=a.max_iter, allow_unconverged=a.profile_run)
 
     for w in range(a.warmup):
@@ -141,18 +153,20 @@ def main():
         tot["step_ms"] += st["step_time_ms"]
         tot["step_bytes"] += st["step_bytes"]
         tot["launches"] += st["step_launches"]
-        groups.add((st["tile_group"], st["tile_prefetch"]))
+        groups.add((st["tile_group"], st["tile_variant"], st["fused_loads"], st["phase_moduli"]))
         Cs.append(C)
         print(f"# step {k}: status {info['status']} iters {info['iters'].tolist()} solve {st['solve_ms']:.1f} ms, "
               f"kernel {st['step_time_ms'] / max(st['step_launches'], 1):.4f} ms/launch, tile {st['tile_bx']}x"
-              f"{st['tile_by']}x{st['tile_kc']} group {st['tile_group']} prefetch {st['tile_prefetch']}",
+              f"{st['tile_by']}x{st['tile_kc']} group {st['tile_group']} variant {st['tile_variant']} "
+              f"fused {st['fused_loads']} phase moduli {st['phase_moduli']}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t0
     C = Cs[-1]
     achieved = tot["step_bytes"] / (tot["step_ms"] * 1e-3) / 1e9
     traffic = None
-    if kernel_source_hash() == MEASURED_TRAFFIC["ceff_kernels_sha256_prefix"] and groups == {(2, 3)}:
+    if kernel_source_hash() == MEASURED_TRAFFIC["ceff_kernels_sha256_prefix"] and \
+            groups == {MEASURED_TRAFFIC["launch_signature"]}:
         traffic = MEASURED_TRAFFIC["bytes_per_launch"]
 
     out = {
@@ -169,15 +183,18 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{a.n}^3 periodic sphere pack, 10% fluid-filled pores (K=2.2, G=1e-3 GPa) "
-                               f"in a K=70, G=32 GPa matrix; six unit loads fused; FP32 sweeps with FP64 "
+                               f"in a K=70, G=32 GPa matrix; six unit loads "
+                               f"{'fused' if st['fused_loads'] else 'one after another'}; FP32 sweeps with FP64 "
                                f"residuals, folds and averages; rtol {a.rtol:g}",
                    "n": a.n, "voxels": N, "loads": 6, "rtol": a.rtol, "precision": "mixed",
+                   "fused_loads": bool(st["fused_loads"]), "moduli": "phase image" if st["phase_moduli"] else "fields",
                    "strouhal": a.strouhal, "porosity": m.info["porosity"]},
         "time_to_ceff_s": wall / a.steps,
         "iterations_per_solve": tot["iters"] / a.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "step_kernel<float,L,0> (heavy-ball APT iteration, L loads per block)",
+                     "kernel": "%s<float,%s> (heavy-ball APT iteration, loads per block = %s)" % (
+                         VARIANT_KERNEL[st["tile_variant"]], st["tile_group"], st["tile_group"]),
                      "avg_launch_ms": tot["step_ms"] / max(tot["launches"], 1),
                      "bytes_per_launch": tot["step_bytes"] / max(tot["launches"], 1)},
         "C_eff_GPa": np.round(C, 6).tolist(),

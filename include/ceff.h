@@ -53,6 +53,7 @@ typedef enum {
 enum { CEFF_F32 = 0, CEFF_F64 = 1 };          /* element type of caller arrays */
 enum { CEFF_HOST = 0, CEFF_DEVICE = 1 };      /* where caller arrays live */
 enum { CEFF_PREC_FP64 = 0, CEFF_PREC_MIXED = 1 };
+enum { CEFF_FUSE_AUTO = -1 };                 /* ceff_solve_opts.fuse_loads: let the library choose */
 
 typedef struct {
   int precision;        /* CEFF_PREC_FP64: all sweeps in FP64.
@@ -64,7 +65,11 @@ typedef struct {
   double courant;       /* CFL number in (0, 1]: ell = courant / sqrt(sum 1/h^2) */
   double strouhal;      /* St of the paper's numerical parameters, > 0 */
   int fuse_loads;       /* 1: all requested loads advance in one launch per iteration;
-                           0: one load after another */
+                           0: one load after another;
+                           CEFF_FUSE_AUTO: one after another when the iteration working set of
+                           one load (two displacement buffers + moduli) fits in the GPU's
+                           Infinity Cache (256 MiB) and that of all requested loads does not,
+                           fused otherwise.  Results do not depend on this choice. */
   int use_graph;        /* 1: replay each block of check_every iterations as a HIP graph */
   int keep_fields;      /* 1: keep the converged FP64 displacements for ceff_gradient */
   int autotune;         /* 1: time candidate tile shapes first (cached per shape) */
@@ -77,17 +82,25 @@ typedef struct {
   int64_t step_launches;   /* launches of the iteration kernel */
   double step_time_ms;     /* device time of those launches, from HIP events on the solve stream */
   double step_bytes;       /* algorithmic HBM bytes of those launches: per voxel and active load
-                              9 words of displacement (+3 with a body force), plus K and G once */
+                              9 words of displacement (+3 with a body force), plus K and G once
+                              (or the 1-byte phase id, see phase_moduli) */
   double voxel_updates;    /* sum over launches of N * active loads */
   int64_t outer_checks;    /* FP64 residual evaluations */
   double solve_ms;         /* host wall time of the solve call */
   int tile_bx, tile_by, tile_kc;  /* tile shape used (block extent incl. ghosts, z-chunk) */
   int tile_group;          /* loads per block */
-  int tile_prefetch;       /* 1 if the next plane is prefetched into registers */
+  int tile_variant;        /* iteration-kernel variant: 0 plain z-march; 1 next plane prefetched into
+                              registers; 2 march unrolled by two planes; 3 as 2 with all loads of a block
+                              between one barrier pair per plane; 4 as 3 unrolled by three, loads issued
+                              one plane ahead; 5 one load per block, in-plane neighbours read through the
+                              caches instead of LDS */
+  int fused_loads;         /* 1 if the requested loads advanced together, one launch per iteration */
+  int phase_moduli;        /* 1: the iteration kernel read each cell's 1-byte phase id and a per-phase
+                              table (material set with ceff_set_phases) instead of the K and G fields */
 } ceff_stats;
 
 /* Fill *o with the defaults: MIXED, rtol 1e-8, max_iter 2e6, check_every 100,
- * courant 0.95, strouhal 2.0, fuse_loads 1, use_graph 1, keep_fields 0,
+ * courant 0.95, strouhal 2.0, fuse_loads CEFF_FUSE_AUTO, use_graph 1, keep_fields 0,
  * autotune 0, fold_ratio 1e-4. */
 void ceff_default_opts(ceff_solve_opts* o);
 

@@ -20,8 +20,8 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (CEFF_DEVICE, CEFF_F32, CEFF_F64, CEFF_HOST, CEFF_PREC_FP64, CEFF_PREC_MIXED, ceff_solve_opts,
-                   ceff_stats)
+from ._lib import (CEFF_DEVICE, CEFF_F32, CEFF_F64, CEFF_FUSE_AUTO, CEFF_HOST, CEFF_PREC_FP64, CEFF_PREC_MIXED,
+                   ceff_solve_opts, ceff_stats)
 
 _L = _lib.load()
 
@@ -157,7 +157,9 @@ def _torch_stream():
 
 
 def make_opts(precision="mixed", rtol=1e-8, max_iter=2_000_000, check_every=100, courant=0.95, strouhal=2.0,
-              fuse_loads=True, use_graph=True, keep_fields=False, autotune=False, fold_ratio=1e-4):
+              fuse_loads="auto", use_graph=True, keep_fields=False, autotune=False, fold_ratio=1e-4):
+    """Solve options.  fuse_loads: True (one launch per iteration for all loads), False (one load
+    after another) or "auto" (the library decides from the working set and the cache size)."""
     o = ceff_default_opts()
     o.precision = CEFF_PREC_MIXED if precision == "mixed" else CEFF_PREC_FP64
     o.rtol = rtol
@@ -165,7 +167,7 @@ def make_opts(precision="mixed", rtol=1e-8, max_iter=2_000_000, check_every=100,
     o.check_every = check_every
     o.courant = courant
     o.strouhal = strouhal
-    o.fuse_loads = int(bool(fuse_loads))
+    o.fuse_loads = CEFF_FUSE_AUTO if isinstance(fuse_loads, str) and fuse_loads == "auto" else int(bool(fuse_loads))
     o.use_graph = int(bool(use_graph))
     o.keep_fields = int(bool(keep_fields))
     o.autotune = int(bool(autotune))

@@ -16,6 +16,7 @@ CEFF_ENOTCONV, CEFF_EDIVERGED, CEFF_EUNSUPPORTED, CEFF_ESTATE = -4, -5, -6, -7
 CEFF_F32, CEFF_F64 = 0, 1
 CEFF_HOST, CEFF_DEVICE = 0, 1
 CEFF_PREC_FP64, CEFF_PREC_MIXED = 0, 1
+CEFF_FUSE_AUTO = -1
 
 STATUS_NAMES = {0: "CEFF_OK", -1: "CEFF_EINVAL", -2: "CEFF_ENOMEM", -3: "CEFF_EDEVICE", -4: "CEFF_ENOTCONV",
                 -5: "CEFF_EDIVERGED", -6: "CEFF_EUNSUPPORTED", -7: "CEFF_ESTATE"}
@@ -33,7 +34,8 @@ class ceff_stats(ctypes.Structure):
                 ("step_bytes", ctypes.c_double), ("voxel_updates", ctypes.c_double),
                 ("outer_checks", ctypes.c_int64), ("solve_ms", ctypes.c_double),
                 ("tile_bx", ctypes.c_int), ("tile_by", ctypes.c_int), ("tile_kc", ctypes.c_int),
-                ("tile_group", ctypes.c_int), ("tile_prefetch", ctypes.c_int)]
+                ("tile_group", ctypes.c_int), ("tile_variant", ctypes.c_int),
+                ("fused_loads", ctypes.c_int), ("phase_moduli", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

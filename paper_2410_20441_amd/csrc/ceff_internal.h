@@ -21,6 +21,13 @@ struct SampleDesc {
   const T* G;                 // shear modulus per cell (N)
   T* u[2][kMaxLoads];         // two rotating displacement buffers per load (3N each)
   const T* force[kMaxLoads];  // optional constant body force per load (3N) or nullptr
+  // Optional phase image: when phase != nullptr and the launch shape asks for it
+  // (TileShape::pal), the iteration kernel reads the 1-byte phase id of each cell
+  // and takes its moduli from ptab (K of phase p at ptab[p], G at ptab[nphase + p])
+  // instead of reading K and G.  All samples of such a launch share one table.
+  const uint8_t* phase;
+  const T* ptab;
+  int nphase;
   T E[kMaxLoads][6];          // macroscopic tensor strain per load: xx yy zz yz xz xy
   unsigned active;            // bit l: load l is iterated
   int work_begin, work_end;   // this sample's work items [begin, end)
@@ -45,6 +52,7 @@ struct TileShape {
                // 5: one load per block, no LDS: neighbours read through the caches
   int order;   // 0: load groups of a tile 8 items apart; 1: each XCD takes a contiguous band
   int occ;     // 1: build that targets more waves per SIMD (fewer registers)
+  int pal;     // 1: moduli from the samples' phase image and table (variant 3 only)
 };
 
 // ---- launch wrappers (ceff_kernels.hip) ----------------------------------------

@@ -98,6 +98,63 @@ struct MinWaves {
   static constexpr int value = HI ? hi : lo;
 };
 
+// Per-cell coefficients of the isotropic Hooke law on the staggered grid:
+// lambda = K - 2G/3 and 2G for the normal stresses, H = K + 4G/3 for the face
+// step, and 1/G for the harmonic edge moduli.
+template <typename T>
+struct alignas(16) CellCoef {
+  T lam, twoG, H, iG;
+};
+
+template <typename T>
+__device__ __forceinline__ CellCoef<T> cell_coef(T K, T G) {
+  CellCoef<T> c;
+  c.lam = K - T(2.0 / 3.0) * G;
+  c.twoG = T(2) * G;
+  c.H = K + T(4.0 / 3.0) * G;
+  c.iG = recip(G);
+  return c;
+}
+
+// Where the iteration kernel gets a cell's coefficients.  load() issues the
+// global read (so it can be requested a plane ahead), coef() turns what it
+// returned into coefficients.  PAL = false: from the K and G fields (2 words per
+// cell).  PAL = true: from the 1-byte phase id and a per-phase coefficient table
+// staged in LDS; the table entries come from the same cell_coef on the same
+// values, so both give identical results.
+template <typename T, bool PAL>
+struct Moduli {
+  struct Raw {
+    T K, G;
+  };
+  const GLOBAL_AS T* Kf;
+  const GLOBAL_AS T* Gf;
+  __device__ Moduli(const SampleDesc<T>& sd, const CellCoef<T>*) : Kf(gconst(sd.K)), Gf(gconst(sd.G)) {}
+  __device__ __forceinline__ Raw load(int64_t o) const { return Raw{Kf[o], Gf[o]}; }
+  __device__ __forceinline__ CellCoef<T> coef(Raw r) const { return cell_coef(r.K, r.G); }
+};
+
+template <typename T>
+struct Moduli<T, true> {
+  struct Raw {
+    uint32_t p;
+  };
+  const GLOBAL_AS uint8_t* ph;
+  const CellCoef<T>* tab;
+  __device__ Moduli(const SampleDesc<T>& sd, const CellCoef<T>* t) : ph(gconst(sd.phase)), tab(t) {}
+  __device__ __forceinline__ Raw load(int64_t o) const { return Raw{ph[o]}; }
+  __device__ __forceinline__ CellCoef<T> coef(Raw r) const { return tab[r.p]; }
+};
+
+// Fill the 256-entry LDS coefficient table of the launch's phase table (ids
+// beyond nphase get a harmless unit entry; the host has checked every id).
+template <typename T>
+__device__ void stage_coef_table(const SampleDesc<T>& sd, CellCoef<T>* tab) {
+  for (int i = threadIdx.x; i < 256; i += blockDim.x)
+    tab[i] = i < sd.nphase ? cell_coef(sd.ptab[i], sd.ptab[sd.nphase + i]) : cell_coef(T(1), T(1));
+  __syncthreads();
+}
+
 template <typename T, int L, int MODE, typename R, bool PF, bool HI>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWaves<T, L, HI>::value)))
 step_kernel(const SampleDesc<T>* __restrict__ samples,
@@ -556,8 +613,9 @@ step_kernel_u2(const SampleDesc<T>* __restrict__ samples, const WorkItem* __rest
 // Unrolled z-march with all loads of the block's group staged together: one
 // barrier after the displacements of every load are in LDS, one after their
 // stresses, so two barriers per plane whatever the group size.  LDS holds
-// 3 + 8L arrays.
-template <typename T, int L, bool HI>
+// 3 + 8L arrays (and the coefficient table with PAL).  The G arrays hold 1/G,
+// computed once per cell by its owner.
+template <typename T, int L, bool HI, bool PAL>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWaves<T, L, HI>::value)))
 step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
               int by, int parity, int first, double* __restrict__ partials) {
@@ -569,6 +627,8 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
   T* sH = base + 2 * nt;
   T* lds_l = base + 3 * nt;  // per load: ux uy uz sxx syy sxy sxz syz
   auto S = [&](int l, int f) { return lds_l + (size_t)(8 * l + f) * nt; };
+  CellCoef<T>* tab = reinterpret_cast<CellCoef<T>*>(lds_l + (size_t)8 * L * nt);
+  if constexpr (PAL) stage_coef_table(samples[0], tab);
 
   const int tid = threadIdx.x;
   const int tx = tid % bx, ty = tid / bx;
@@ -602,8 +662,7 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
     const int64_t k0 = (int64_t)wi.kz * sd.kc;
     const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
 
-    const GLOBAL_AS T* __restrict__ Kf = gconst(sd.K);
-    const GLOBAL_AS T* __restrict__ Gf = gconst(sd.G);
+    const Moduli<T, PAL> mod(sd, tab);
     const GLOBAL_AS T* ucur[L];
     GLOBAL_AS T* uold[L];
     const GLOBAL_AS T* frc[L];
@@ -619,7 +678,8 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       for (int q = 0; q < 6; ++q) E[l][q] = sd.E[s0 + l][q];
     }
 
-    T Ux[2][L], Uy[2][L], Uz[2][L], Szz[2][L], Sxz[2][L], Syz[2][L], Kc[2], Gc[2], Hh[2];
+    T Ux[2][L], Uy[2][L], Uz[2][L], Szz[2][L], Sxz[2][L], Syz[2][L], Hh[2];
+    CellCoef<T> Cc[2];
     double nsum[L];
     {
       const int64_t kw = k0 - 1 < 0 ? k0 - 1 + nz : k0 - 1;
@@ -635,10 +695,9 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
         Szz[1][l] = Sxz[1][l] = Syz[1][l] = T(0);
         nsum[l] = 0.0;
       }
-      Kc[0] = Kf[o];
-      Gc[0] = Gf[o];
+      Cc[0] = mod.coef(mod.load(o));
       Hh[1] = T(1);
-      sG[0][tid] = Gc[0];
+      sG[0][tid] = Cc[0].iG;
     }
 
     auto plane_step = [&](int64_t k, auto Pc) {
@@ -648,8 +707,7 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       const int64_t kn = k + 1 >= nz ? k + 1 - nz : k + 1;
       const int64_t oc = col + plane * kw, on = col + plane * kn;
       const bool face = k >= k0 && interior;
-      Kc[Q] = Kf[on];
-      Gc[Q] = Gf[on];
+      const auto mr = mod.load(on);
       T uo0[L], uo1[L], uo2[L], f0[L], f1[L], f2[L];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
@@ -674,8 +732,9 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       }
       T* gk = sG[P];
       T* gn = sG[Q];
-      gn[tid] = Gc[Q];
-      Hh[P] = Kc[P] + T(4.0 / 3.0) * Gc[P];
+      Cc[Q] = mod.coef(mr);
+      gn[tid] = Cc[Q].iG;
+      Hh[P] = Cc[P].H;
       sH[tid] = Hh[P];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
@@ -684,11 +743,11 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
         S(l, 2)[tid] = Uz[Q][l];
       }
       __syncthreads();
-      const T lam = Kc[P] - T(2.0 / 3.0) * Gc[P];
-      const T twoG = T(2) * Gc[P];
-      const T ik = recip(gk[tid]), ikx = recip(gk[xm]), iky = recip(gk[ym]);
-      const T in = recip(gn[tid]), inx = recip(gn[xm]), iny = recip(gn[ym]);
-      const T G2xy = T(8) * recip(recip(gk[xmym]) + iky + ikx + ik);
+      const T lam = Cc[P].lam;
+      const T twoG = Cc[P].twoG;
+      const T ik = gk[tid], ikx = gk[xm], iky = gk[ym];
+      const T in = gn[tid], inx = gn[xm], iny = gn[ym];
+      const T G2xy = T(8) * recip(gk[xmym] + iky + ikx + ik);
       const T G2xz = T(8) * recip(ikx + ik + inx + in);
       const T G2yz = T(8) * recip(iky + ik + iny + in);
       const T sfx = sfac * recip(tmax(sH[xm], Hh[P]));
@@ -1414,9 +1473,13 @@ void launch_step_occ(const SampleDesc<T>* d_samples, const WorkItem* d_work, int
   } else if (ts.pf == 4)
     hipLaunchKernelGGL((step_kernel_p3<T, L, HI>), dim3(nwork), dim3(nt), (size_t)(3 + 8 * L) * nt * sizeof(T), s,
                        d_samples, d_work, nwork, ts.bx, ts.by, parity, first, partials);
+  else if (ts.pf == 3 && ts.pal)
+    hipLaunchKernelGGL((step_kernel_b<T, L, HI, true>), dim3(nwork), dim3(nt),
+                       (size_t)(3 + 8 * L) * nt * sizeof(T) + 256 * sizeof(CellCoef<T>), s, d_samples, d_work, nwork,
+                       ts.bx, ts.by, parity, first, partials);
   else if (ts.pf == 3)
-    hipLaunchKernelGGL((step_kernel_b<T, L, HI>), dim3(nwork), dim3(nt), (size_t)(3 + 8 * L) * nt * sizeof(T), s,
-                       d_samples, d_work, nwork, ts.bx, ts.by, parity, first, partials);
+    hipLaunchKernelGGL((step_kernel_b<T, L, HI, false>), dim3(nwork), dim3(nt), (size_t)(3 + 8 * L) * nt * sizeof(T),
+                       s, d_samples, d_work, nwork, ts.bx, ts.by, parity, first, partials);
   else if (ts.pf == 2)
     hipLaunchKernelGGL((step_kernel_u2<T, L, HI>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork, ts.bx,
                        ts.by, parity, first, partials);

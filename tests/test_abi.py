@@ -41,7 +41,7 @@ def test_defaults():
     import paper_2410_20441_amd as p
     o = p.ceff_default_opts()
     assert o.precision == p.CEFF_PREC_MIXED and o.rtol == 1e-8 and o.check_every == 100
-    assert 0 < o.courant <= 1 and o.strouhal > 0 and o.fuse_loads == 1
+    assert 0 < o.courant <= 1 and o.strouhal > 0 and o.fuse_loads == -1
 
 
 def test_null_context_is_rejected():

@@ -240,3 +240,16 @@ def test_unrolled_march_matches(monkeypatch, tile):
     Cq, iq = p.solve(K, G, precision="fp64", rtol=1e-9, fuse_loads=False)
     assert np.array_equal(ir["iters"], iq["iters"])
     assert np.max(np.abs(Cr - Cq)) <= 1e-12 * np.abs(Cq).max()
+
+
+@pytest.mark.parametrize("n,fused", [(32, 1), (120, 1), (128, 0)])
+def test_automatic_load_fusion(n, fused):
+    """Loads run one after another exactly when one load's working set fits in the
+    Infinity Cache and all six do not (homogeneous images: no iterations needed)."""
+    p = need_gpu()
+    m = synth.homogeneous(n)
+    with p.Context() as c:
+        c.set_phases(m.phase, m.K_tab, m.G_tab)
+        C, info = c.solve(precision="mixed")
+    assert info["stats"]["fused_loads"] == fused
+    np.testing.assert_allclose(C, cf.c_iso(70.0, 32.0), rtol=1e-14, atol=1e-12)
