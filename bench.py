@@ -27,10 +27,10 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the iteration kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_hbm_counters.md),
 # valid only for the kernel source they were taken on.
-MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "3b3da3b4e7bc5179", "bytes_per_launch": 1.793178e+09,
+MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "0c8174f3d93c9f7a", "bytes_per_launch": 3.121144e+08,
                     # (loads per block, kernel variant, loads fused, moduli from the phase image)
-                    "launch_signature": (2, 3, 1, 0),
-                    "launch": "step_kernel_b<float,2>, macroscopic-strain phase (no body force)"}
+                    "launch_signature": (1, 3, 0, 1),
+                    "launch": "step_kernel_b<float,1,PAL>, mean over all launches of a full solve"}
 
 
 # iteration-kernel variant (ceff_stats.tile_variant) -> kernel name

@@ -93,7 +93,7 @@ __device__ __forceinline__ float recip<float>(float x) {
 // possibly some spills); the tuner measures both.
 template <typename T, int L, bool HI>
 struct MinWaves {
-  static constexpr int hi = sizeof(T) == 4 ? (L == 1 ? 8 : (L == 2 ? 6 : (L == 3 ? 4 : 1))) : (L == 1 ? 5 : 1);
+  static constexpr int hi = sizeof(T) == 4 ? (L == 1 ? 6 : (L == 2 ? 6 : (L == 3 ? 4 : 1))) : (L == 1 ? 5 : 1);
   static constexpr int lo = (sizeof(T) == 4 && L <= 2) || (sizeof(T) == 8 && L == 1) ? 4 : 1;
   static constexpr int value = HI ? hi : lo;
 };
