@@ -89,9 +89,11 @@ def parse():
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for counter collection: allow stopping at --max-iter")
     ap.add_argument("--workload", default="spheres191",
-                    choices=["spheres191", "batch48", "cracks479", "sizing703"],
+                    choices=["spheres191", "batch48", "cracks479", "sizing703", "hsweep"],
                     help="spheres191 (default bench line); batch48: 48 uneven three-phase samples in one solve; "
-                         "cracks479: 479^3 cracked solid; sizing703: 703^3 sphere pack (memory sizing run)")
+                         "cracks479: 479^3 cracked solid; sizing703: 703^3 sphere pack (memory sizing run); "
+                         "hsweep: contribution tensors of single spheroids, aspect ratio x contrast, one batch")
+    ap.add_argument("--hsweep-r", type=int, default=12, help="hsweep: largest semi-axis of the coarse spheroids")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a buffer of this many MiB three times (a plain copy kernel of known size "
                          "against which HBM byte counters are scaled)")
@@ -234,8 +236,61 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def hsweep(a, torch, synth, ceff, dev):
+    """Compliance contribution tensors of single spheroids (aspect ratio x inclusion contrast,
+    each at two resolutions r and 2r in a box of 8r) from one batch solve, with the error
+    against Eshelby's tensor before and after first-order extrapolation in r."""
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+    import closed_forms as cf
+    host = (36.0, 44.0)
+    incs = {"soft": (7.2, 8.8), "stiff": (180.0, 220.0), "pore": (1e-3, 2e-3)}
+    alphas = (0.1, 0.2, 0.5, 1.0, 2.0, 5.0, 10.0)
+    r0 = a.hsweep_r
+    cases, ms = [], []
+    for al in alphas:
+        shape = (1.0, 1.0, al) if al <= 1 else (1.0 / al, 1.0 / al, 1.0)
+        for name, inc in incs.items():
+            for r in (r0, 2 * r0):
+                cases.append((al, name, r, shape))
+                ms.append(synth.centred_spheroid(8 * r, tuple(r * f for f in shape), matrix=host, inclusion=inc))
+    samples = [tuple(torch.from_numpy(x).to(dev) for x in m.fields(np.float32)) for m in ms]
+    N = sum(m.phase.size for m in ms)
+    print(f"# hsweep: {len(ms)} samples, {N} voxels", file=sys.stderr, flush=True)
+    torch.cuda.synchronize(dev)
+    t1 = time.perf_counter()
+    C, it, info = ceff.solve_batch(samples, precision="mixed", rtol=a.rtol, check_every=a.check_every,
+                                   max_iter=a.max_iter)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t1
+    K1, G1 = host
+    nu = (3 * K1 - 2 * G1) / (2 * (3 * K1 + G1))
+    w = np.array([1, 1, 1, np.sqrt(2), np.sqrt(2), np.sqrt(2)])
+    C1 = cf.c_iso(*host)
+    rows = []
+    for q in range(0, len(cases), 2):
+        al, name, r, shape = cases[q]
+        He = cf.compliance_contribution(C1, cf.c_iso(*incs[name]), cf.eshelby_tensor(np.array(shape), nu))
+        He = He * np.outer(w, w)
+        H1, _ = ceff.contribution_tensors(C[q], C1, ms[q].info["phi"])
+        H2, _ = ceff.contribution_tensors(C[q + 1], C1, ms[q + 1].info["phi"])
+        err = lambda H: float(np.abs(H - He).max() / np.abs(He).max())
+        rows.append({"aspect": al, "inclusion": name, "r": [r, 2 * r],
+                     "phi": [ms[q].info["phi"], ms[q + 1].info["phi"]],
+                     "H_2r_voigt_11_33_44_12_13": [float(H2[0, 0]), float(H2[2, 2]), float(H2[3, 3]), float(H2[0, 1]),
+                                                  float(H2[0, 2])],
+                     "err_r": err(H1), "err_2r": err(H2), "err_extrapolated": err(2 * H2 - H1)})
+    vu = float(sum(ms[s].phase.size * it[s].sum() for s in range(len(ms))))
+    st = info["stats"]
+    res = {"workload": "hsweep", "samples": len(ms), "voxels": N, "status": info["status"], "time_s": wall,
+           "gvu_s": vu / wall / 1e9, "kernel_GB_s": st["step_bytes"] / (st["step_time_ms"] * 1e-3) / 1e9,
+           "rows": rows}
+    print(json.dumps(res), flush=True)
+
+
 def other_workload(a, torch, synth, ceff, dev):
     """Measurement runs of the other workloads (one solve each, not the bench line)."""
+    if a.workload == "hsweep":
+        return hsweep(a, torch, synth, ceff, dev)
     opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, max_iter=a.max_iter,
                 allow_unconverged=a.profile_run, autotune=a.autotune)
     t0 = time.perf_counter()

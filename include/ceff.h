@@ -178,6 +178,24 @@ ceff_status ceff_average_stress(ceff_ctx* ctx, int J, const double* u, double ou
 /* Counters of the most recent solve. */
 ceff_status ceff_get_stats(const ceff_ctx* ctx, ceff_stats* out);
 
+/* ---- property contribution tensors (host arithmetic, no context) ------------ */
+
+/* Contribution tensors of inclusions of total volume fraction phi in a host of
+ * stiffness C_host, from the effective stiffness C_eff of an image that holds
+ * them (paper: "Model 2: validation against an Eshelby solution", the relation
+ * S* = S1 + phi H, and the appendix on the property contribution tensor):
+ *   H = (C_eff^-1 - C_host^-1) / phi   (compliance contribution: S* = S_host + phi H)
+ *   N = (C_eff - C_host) / phi         (stiffness contribution:  C* = C_host + phi N)
+ * All matrices are 6x6 row-major Voigt with engineering shear, so H is in the
+ * compliance convention of C^-1 (H_44 = 4 H_2323, H_14 = 2 H_1123).  With one
+ * inclusion in a periodic box, H tends to the single-inclusion tensor as phi -> 0.
+ * H_out or N_out may be NULL.  Returns CEFF_EINVAL if phi is not in (0, 1] or a
+ * stiffness matrix is singular (pivot below 1e-12 of its largest entry).
+ * Computed on the host in FP64 (Gauss-Jordan with partial pivoting); needs no
+ * device. */
+ceff_status ceff_contribution_tensors(const double C_eff[36], const double C_host[36], double phi, double H_out[36],
+                                      double N_out[36]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,6 +10,8 @@ Convenience layer:
   * :class:`Context` -- owns a ``ceff_ctx``; ``solve``, ``gradient`` etc.
   * :func:`solve` -- one image, returns the 6x6 C* (FP64) and run info.
   * :func:`solve_batch` -- several images of different sizes in one solve.
+  * :func:`contribution_tensors` -- compliance/stiffness contribution tensors
+    of inclusions from C*.
   * :class:`EffectiveStiffness` -- ``torch.autograd.Function``: C*(K, G) with
     the adjoint gradient on backward.
 """
@@ -28,7 +30,8 @@ _L = _lib.load()
 __all__ = ["ceff_default_opts", "ceff_create", "ceff_destroy", "ceff_last_error", "ceff_set_grid",
            "ceff_set_isotropic", "ceff_set_phases", "ceff_set_stiffness", "ceff_solve", "ceff_solve_batch",
            "ceff_gradient", "ceff_apt_steps", "ceff_residual", "ceff_average_stress", "ceff_get_stats",
-           "CeffError", "Context", "solve", "solve_batch", "EffectiveStiffness", "library_path"]
+           "ceff_contribution_tensors", "CeffError", "Context", "solve", "solve_batch", "contribution_tensors",
+           "EffectiveStiffness", "library_path"]
 
 library_path = _lib.LIB_PATH
 
@@ -113,6 +116,13 @@ def ceff_average_stress(ctx, J, u, out6):
 
 def ceff_get_stats(ctx, out):
     return _check(ctx, _L.ceff_get_stats(ctx, out))
+
+
+def ceff_contribution_tensors(C_eff, C_host, phi, H_out, N_out):
+    st = _L.ceff_contribution_tensors(C_eff, C_host, phi, H_out, N_out)
+    if st != 0:
+        raise CeffError(st, "phi must be in (0, 1] and both stiffness matrices finite and invertible")
+    return st
 
 
 # ---- marshalling helpers ----------------------------------------------------------
@@ -288,6 +298,17 @@ def solve(K, G, h=(1.0, 1.0, 1.0), loads=range(6), device=0, **kw):
     with Context(device) as c:
         c.set_material(K, G, h)
         return c.solve(loads=loads, **kw)
+
+
+def contribution_tensors(C_eff, C_host, phi):
+    """Compliance and stiffness contribution tensors (H, N), 6x6 Voigt, of inclusions of
+    volume fraction phi: S* = S_host + phi H and C* = C_host + phi N (see ceff.h)."""
+    Ce = np.ascontiguousarray(C_eff, np.float64).reshape(36)
+    Ch = np.ascontiguousarray(C_host, np.float64).reshape(36)
+    H = np.empty(36)
+    N = np.empty(36)
+    ceff_contribution_tensors(_dptr(Ce), _dptr(Ch), float(phi), _dptr(H), _dptr(N))
+    return H.reshape(6, 6), N.reshape(6, 6)
 
 
 def solve_batch(samples, h=None, loads=range(6), device=0, allow_unconverged=False, **kw):

@@ -935,6 +935,39 @@ ceff_status begin_call(ceff_ctx* c) {
   return CEFF_OK;
 }
 
+// Inverse of a 6x6 row-major matrix by Gauss-Jordan elimination with partial
+// pivoting (FP64).  False if a pivot falls below 1e-12 of the largest entry.
+bool invert6(const double* A, double* X) {
+  double a[6][12];
+  double amax = 0.0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      a[i][j] = A[i * 6 + j];
+      a[i][6 + j] = i == j ? 1.0 : 0.0;
+      amax = std::max(amax, std::fabs(A[i * 6 + j]));
+    }
+  if (!(amax > 0.0)) return false;
+  for (int col = 0; col < 6; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 6; ++r)
+      if (std::fabs(a[r][col]) > std::fabs(a[piv][col])) piv = r;
+    if (!(std::fabs(a[piv][col]) > 1e-12 * amax)) return false;
+    if (piv != col)
+      for (int j = 0; j < 12; ++j) std::swap(a[piv][j], a[col][j]);
+    const double d = a[col][col];
+    for (int j = 0; j < 12; ++j) a[col][j] /= d;
+    for (int r = 0; r < 6; ++r) {
+      if (r == col) continue;
+      const double f = a[r][col];
+      if (f == 0.0) continue;
+      for (int j = 0; j < 12; ++j) a[r][j] -= f * a[col][j];
+    }
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) X[i * 6 + j] = a[i][6 + j];
+  return true;
+}
+
 // MI355X's Infinity Cache (the memory-side last-level cache in front of HBM).
 constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 
@@ -1415,6 +1448,22 @@ ceff_status ceff_average_stress(ceff_ctx* c, int J, const double* u, double out6
 ceff_status ceff_get_stats(const ceff_ctx* c, ceff_stats* out) {
   if (!c || !out) return CEFF_EINVAL;
   *out = c->stats;
+  return CEFF_OK;
+}
+
+ceff_status ceff_contribution_tensors(const double C_eff[36], const double C_host[36], double phi, double H_out[36],
+                                      double N_out[36]) {
+  if (!C_eff || !C_host) return CEFF_EINVAL;
+  if (!(phi > 0.0) || !(phi <= 1.0)) return CEFF_EINVAL;
+  for (int q = 0; q < 36; ++q)
+    if (!std::isfinite(C_eff[q]) || !std::isfinite(C_host[q])) return CEFF_EINVAL;
+  if (H_out) {
+    double Se[36], Sh[36];
+    if (!invert6(C_eff, Se) || !invert6(C_host, Sh)) return CEFF_EINVAL;
+    for (int q = 0; q < 36; ++q) H_out[q] = (Se[q] - Sh[q]) / phi;
+  }
+  if (N_out)
+    for (int q = 0; q < 36; ++q) N_out[q] = (C_eff[q] - C_host[q]) / phi;
   return CEFF_OK;
 }
 

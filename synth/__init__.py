@@ -132,8 +132,9 @@ def _periodic_delta(x, c, L):
     return d - L * np.round(d / L)
 
 
-def stamp_sphere(mask: np.ndarray, centre, radius: float):
-    """Set mask over voxels whose centre is within `radius` of `centre` (periodic)."""
+def stamp_sphere(mask: np.ndarray, centre, radius: float) -> int:
+    """Set mask over voxels whose centre is within `radius` of `centre` (periodic).
+    Returns the number of voxels that were not set before."""
     nz, ny, nx = mask.shape
     cx, cy, cz = centre
     r = radius
@@ -147,7 +148,10 @@ def stamp_sphere(mask: np.ndarray, centre, radius: float):
     dz = _periodic_delta(kk + 0.5, cz, nz)
     d2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
     sub = d2 <= r * r
-    mask[np.ix_(kk, jj, ii)] |= sub
+    idx = np.ix_(kk, jj, ii)
+    fresh = int(np.count_nonzero(sub & ~mask[idx]))
+    mask[idx] |= sub
+    return fresh
 
 
 def homogeneous(n, K=MATRIX[0], G=MATRIX[1]) -> Microstructure:
@@ -166,6 +170,23 @@ def centred_sphere(n=32, radius=8.0, matrix=MATRIX, inclusion=FLUID_PORE) -> Mic
     return m
 
 
+def centred_spheroid(n, semi_axes, matrix=MATRIX, inclusion=FLUID_PORE) -> Microstructure:
+    """One axis-aligned ellipsoid with semi-axes (ax, ay, az) voxels, centred in a periodic
+    box of n = (nx, ny, nz) (or n^3) voxels; a voxel belongs to it iff its centre lies in
+    the closed ellipsoid.  info["phi"] is the realised voxel fraction."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else n
+    ax, ay, az = semi_axes
+    x = (_centres(nx) - nx / 2) / ax
+    y = (_centres(ny) - ny / 2) / ay
+    z = (_centres(nz) - nz / 2) / az
+    inside = z[:, None, None] ** 2 + y[None, :, None] ** 2 + x[None, None, :] ** 2 <= 1.0
+    m = Microstructure(inside.astype(np.uint8), np.array([matrix[0], inclusion[0]]),
+                       np.array([matrix[1], inclusion[1]]))
+    m.info = {"generator": "centred_spheroid", "n": (nx, ny, nz), "semi_axes": tuple(map(float, semi_axes)),
+              "phi": float(inside.mean()), "n_inclusion": int(inside.sum())}
+    return m
+
+
 def random_spheres(n, porosity, seed, rmin=3.0, rmax=9.0, matrix=MATRIX, pore=FLUID_PORE) -> Microstructure:
     """Random sequential addition of non-overlapping spheres (periodic box).
 
@@ -177,24 +198,29 @@ def random_spheres(n, porosity, seed, rmin=3.0, rmax=9.0, matrix=MATRIX, pore=FL
     rng = SplitMix64(seed)
     L = float(n)
     mask = np.zeros((n, n, n), bool)
-    cs = np.zeros((0, 3)); rs = np.zeros(0)
+    nvox = mask.size
+    cs = np.zeros((64, 3)); rs = np.zeros(64)  # accepted spheres in [:na], grown by doubling
+    na = 0
+    filled = 0  # voxels set so far (the porosity is filled / nvox)
     tries = 0
-    while mask.mean() < porosity:
+    while filled / nvox < porosity:
         tries += 1
         if tries > 10_000_000:
             raise RuntimeError("sphere packing did not reach the target porosity")
         r = rng.uniform_range(rmin, rmax)
         c = np.array([rng.uniform() * L, rng.uniform() * L, rng.uniform() * L])
-        if len(rs):
-            d = c[None, :] - cs
+        if na:
+            d = c[None, :] - cs[:na]
             d -= L * np.round(d / L)
-            if np.any(np.sqrt((d * d).sum(1)) < rs + r):
+            if np.any(np.sqrt((d * d).sum(1)) < rs[:na] + r):
                 continue
-        cs = np.vstack([cs, c]); rs = np.append(rs, r)
-        stamp_sphere(mask, c, r)
+        if na == len(rs):
+            cs = np.concatenate([cs, np.zeros_like(cs)]); rs = np.concatenate([rs, np.zeros_like(rs)])
+        cs[na] = c; rs[na] = r; na += 1
+        filled += stamp_sphere(mask, c, r)
     m = Microstructure(mask.astype(np.uint8), np.array([matrix[0], pore[0]]), np.array([matrix[1], pore[1]]))
-    m.info = {"generator": "random_spheres", "n": n, "seed": seed, "n_spheres": int(len(rs)),
-              "porosity": float(mask.mean()), "target": porosity}
+    m.info = {"generator": "random_spheres", "n": n, "seed": seed, "n_spheres": na,
+              "porosity": filled / nvox, "target": porosity}
     return m
 
 
