@@ -7,8 +7,9 @@ never imports, links or calls it, and it shares no code with it.
 Contents
 --------
 * ``ceff_oracle.c`` (loaded through ctypes): FP64 operator, Jacobi-PCG solve,
-  stress averages, the paper-form APT step reference and the closed-form
-  gradient.
+  stress averages, the paper-form APT step reference, the displacement-form
+  APT iteration and the closed-form gradient; isotropic (K, G) cells, and
+  orthotropic cells with nine constants (``*_ortho``).
 * ``dense.py``: brute-force dense solve for tiny grids, assembled from the
   strain energy alone (an independent route to the same discrete problem).
 
@@ -45,6 +46,14 @@ def lib():
         L.or_apt_steps.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int64, _dp]
         L.or_gradient.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_stress_ortho.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
+        L.or_residual_ortho.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
+        L.or_average_stress_ortho.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
+        L.or_pcg_ortho.argtypes = [_ip, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp, _dp,
+                                   ctypes.c_int64]
+        L.or_pcg_ortho.restype = ctypes.c_int64
+        L.or_apt_disp.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                  _dp, _dp]
         _lib = L
     return _lib
 
@@ -149,6 +158,102 @@ def apt_steps(K, G, J, nsteps, courant, strouhal, h=(1.0, 1.0, 1.0), state=None)
     out = {nm: buf[i * N:(i + 1) * N].reshape(sh).copy() for i, nm in enumerate(names)}
     out["v"] = buf[7 * N:].reshape((3,) + sh).copy()
     return out
+
+
+# ---- orthotropic cells (nine constants per cell) -----------------------------------
+#
+# C9 is shaped (9, nz, ny, nx): C11 C22 C33 C23 C13 C12 C44 C55 C66 of each cell
+# (Voigt, engineering shear), axes aligned with the grid.
+
+def iso_to_c9(K, G):
+    """The nine orthotropic constants of isotropic cells (K, G)."""
+    K = np.asarray(K, np.float64); G = np.asarray(G, np.float64)
+    a = K + 4.0 * G / 3.0
+    b = K - 2.0 * G / 3.0
+    return np.stack([a, a, a, b, b, b, G, G, G])
+
+
+def voigt_of_c9(c):
+    """6x6 Voigt stiffness of one cell's nine constants."""
+    C11, C22, C33, C23, C13, C12, C44, C55, C66 = c
+    return np.array([[C11, C12, C13, 0, 0, 0], [C12, C22, C23, 0, 0, 0], [C13, C23, C33, 0, 0, 0],
+                     [0, 0, 0, C44, 0, 0], [0, 0, 0, 0, C55, 0], [0, 0, 0, 0, 0, C66]], float)
+
+
+def _prep9(C9, h):
+    C9 = np.ascontiguousarray(C9, np.float64)
+    if C9.ndim != 4 or C9.shape[0] != 9:
+        raise ValueError("C9 must be shaped (9, nz, ny, nx)")
+    if not np.all(C9[[0, 1, 2, 6, 7, 8]] > 0):
+        raise ValueError("diagonal constants must be positive")
+    nz, ny, nx = C9.shape[1:]
+    return C9, np.array([nx, ny, nz], np.int64), np.array(h, np.float64)
+
+
+def stress_ortho(C9, E, u, h=(1.0, 1.0, 1.0)):
+    C9, dims, hh = _prep9(C9, h)
+    sh = C9.shape[1:]
+    u = np.ascontiguousarray(u, np.float64).reshape((3,) + sh)
+    out = np.empty((6,) + sh)
+    lib().or_stress_ortho(dims.ctypes.data_as(_ip), _d(hh), _d(C9), _d(np.asarray(E, np.float64)), _d(u), _d(out))
+    return out
+
+
+def residual_ortho(C9, E, u, h=(1.0, 1.0, 1.0)):
+    C9, dims, hh = _prep9(C9, h)
+    sh = C9.shape[1:]
+    u = np.ascontiguousarray(u, np.float64).reshape((3,) + sh)
+    out = np.empty((3,) + sh)
+    lib().or_residual_ortho(dims.ctypes.data_as(_ip), _d(hh), _d(C9), _d(np.asarray(E, np.float64)), _d(u), _d(out))
+    return out
+
+
+def average_stress_ortho(C9, E, u, h=(1.0, 1.0, 1.0)):
+    C9, dims, hh = _prep9(C9, h)
+    u = np.ascontiguousarray(u, np.float64).reshape((3,) + C9.shape[1:])
+    out = np.empty(6)
+    lib().or_average_stress_ortho(dims.ctypes.data_as(_ip), _d(hh), _d(C9), _d(np.asarray(E, np.float64)), _d(u),
+                                  _d(out))
+    return out
+
+
+def solve_load_ortho(C9, J, h=(1.0, 1.0, 1.0), rtol=1e-11, max_iter=1_000_000):
+    C9, dims, hh = _prep9(C9, h)
+    u = np.zeros((3,) + C9.shape[1:])
+    rel = np.zeros(1)
+    it = lib().or_pcg_ortho(dims.ctypes.data_as(_ip), _d(hh), _d(C9), _d(unit_strain(J)), rtol, max_iter, _d(u),
+                            _d(rel), None, 0)
+    return u, int(it), float(rel[0])
+
+
+def ceff_ortho(C9, h=(1.0, 1.0, 1.0), rtol=1e-11, loads=range(6), max_iter=1_000_000):
+    """Effective stiffness (6x6) of an image of orthotropic cells."""
+    C = np.full((6, 6), np.nan)
+    info = {}
+    for J in loads:
+        u, it, rel = solve_load_ortho(C9, J, h, rtol, max_iter)
+        C[:, J] = average_stress_ortho(C9, unit_strain(J), u, h)
+        info[J] = (it, rel)
+    return C, info
+
+
+def apt_disp(J, nsteps, courant, strouhal, K=None, G=None, C9=None, h=(1.0, 1.0, 1.0)):
+    """Displacement-form APT iterate u^nsteps and u^(nsteps-1) (each (3, nz, ny, nx)) for
+    isotropic (K, G) or orthotropic (C9) cells, from u^0 = 0."""
+    if C9 is not None:
+        C9, dims, hh = _prep9(C9, h)
+        sh = C9.shape[1:]
+        Kp = Gp = None
+        cp = _d(C9)
+    else:
+        K, G, dims, hh = _prep(K, G, h)
+        sh = K.shape
+        Kp, Gp, cp = _d(K), _d(G), None
+    u = np.empty((3,) + sh)
+    up = np.empty((3,) + sh)
+    lib().or_apt_disp(dims.ctypes.data_as(_ip), _d(hh), Kp, Gp, cp, _d(unit_strain(J)), courant, strouhal, nsteps,
+                      _d(u), _d(up))
+    return u, up
 
 
 def gradient(K, G, fields, W, h=(1.0, 1.0, 1.0)):

@@ -25,6 +25,14 @@
  *   sxx = K*theta + 2G(exx - theta/3),  sxy = 2 G_e exy
  *   (div s)_x[i,j,k] = (sxx[i]-sxx[i-1])/hx + (sxy[j+1]-sxy[j])/hy + (sxz[k+1]-sxz[k])/hz
  *
+ * Orthotropic cells (axes aligned with the grid; an extension the paper lists
+ * among its perspectives) carry nine constants instead of K and G:
+ *   c9[q*N + cell], q = 0..8: C11 C22 C33 C23 C13 C12 C44 C55 C66 (Voigt,
+ *   engineering shear), so sxx = C11 exx + C12 eyy + C13 ezz (and alike) at
+ *   cells, and at edges syz = 2 C44_e eyz, sxz = 2 C55_e exz, sxy = 2 C66_e exy
+ *   with the edge constant the harmonic mean over the four cells, as for G.
+ *   With C11 = K + 4G/3, C12 = K - 2G/3 and C44 = G this is the isotropic law.
+ *
  * Build: gcc -O2 -fopenmp -shared -fPIC (see oracle/build.py).
  * Arrays: x fastest, linear index i + nx*(j + ny*k); vector fields are stored
  * component-major: f[c*N + idx].  Tensor strain components are passed as
@@ -39,6 +47,11 @@ typedef struct {
     int64_t nx, ny, nz;
     double hx, hy, hz;
 } grid_t;
+
+/* Material: isotropic K, G per cell, or nine orthotropic constants per cell (c9 != NULL). */
+typedef struct {
+    const double *K, *G, *c9;
+} mat_t;
 
 static inline int64_t wrap(int64_t a, int64_t n) { a %= n; return a < 0 ? a + n : a; }
 static inline int64_t at(const grid_t *g, int64_t i, int64_t j, int64_t k) {
@@ -60,6 +73,15 @@ static double edge_modulus(const grid_t *g, const double *G, int plane, int64_t 
         s = 1.0 / G[at(g, i, j - 1, k - 1)] + 1.0 / G[at(g, i, j, k - 1)] +
             1.0 / G[at(g, i, j - 1, k)] + 1.0 / G[at(g, i, j, k)];
     return 4.0 / s;
+}
+
+/* Shear constant of an edge for material m: the harmonic mean over the four
+ * cells of G (isotropic) or of C66 (xy), C55 (xz), C44 (yz) (orthotropic). */
+static double edge_shear(const grid_t *g, const mat_t *m, int plane, int64_t i, int64_t j, int64_t k) {
+    if (!m->c9) return edge_modulus(g, m->G, plane, i, j, k);
+    const int64_t N = g->nx * g->ny * g->nz;
+    const double *C = m->c9 + (plane == 0 ? 8 : (plane == 1 ? 7 : 6)) * N;
+    return edge_modulus(g, C, plane, i, j, k);
 }
 
 /* Total strain (E + grad u) at every cell and edge.
@@ -85,21 +107,32 @@ static void strains(const grid_t *g, const double E[6], const double *u, double 
             }
 }
 
-/* Hooke's law, isotropic: sigma = K tr(eps) I + 2 G dev(eps) at cells,
- * sigma_e = 2 G_e eps_e at edges. */
-static void hooke(const grid_t *g, const double *K, const double *G, const double *eps, double *sig) {
+/* Hooke's law.  Isotropic: sigma = K tr(eps) I + 2 G dev(eps) at cells;
+ * orthotropic: the normal block of the 6x6 Voigt matrix times the normal
+ * strains.  Edges: sigma_e = 2 (edge shear constant) eps_e. */
+static void hooke(const grid_t *g, const mat_t *m, const double *eps, double *sig) {
     const int64_t N = g->nx * g->ny * g->nz;
 #pragma omp parallel for collapse(2) schedule(static)
     for (int64_t k = 0; k < g->nz; k++)
         for (int64_t j = 0; j < g->ny; j++)
             for (int64_t i = 0; i < g->nx; i++) {
                 int64_t c = at(g, i, j, k);
-                double th = eps[c] + eps[N + c] + eps[2 * N + c];
-                for (int d = 0; d < 3; d++)
-                    sig[d * N + c] = K[c] * th + 2.0 * G[c] * (eps[d * N + c] - th / 3.0);
-                sig[3 * N + c] = 2.0 * edge_modulus(g, G, 2, i, j, k) * eps[3 * N + c];
-                sig[4 * N + c] = 2.0 * edge_modulus(g, G, 1, i, j, k) * eps[4 * N + c];
-                sig[5 * N + c] = 2.0 * edge_modulus(g, G, 0, i, j, k) * eps[5 * N + c];
+                if (m->c9) {
+                    const double *C = m->c9;
+                    double exx = eps[c], eyy = eps[N + c], ezz = eps[2 * N + c];
+                    double C11 = C[c], C22 = C[N + c], C33 = C[2 * N + c];
+                    double C23 = C[3 * N + c], C13 = C[4 * N + c], C12 = C[5 * N + c];
+                    sig[c] = C11 * exx + C12 * eyy + C13 * ezz;
+                    sig[N + c] = C12 * exx + C22 * eyy + C23 * ezz;
+                    sig[2 * N + c] = C13 * exx + C23 * eyy + C33 * ezz;
+                } else {
+                    double th = eps[c] + eps[N + c] + eps[2 * N + c];
+                    for (int d = 0; d < 3; d++)
+                        sig[d * N + c] = m->K[c] * th + 2.0 * m->G[c] * (eps[d * N + c] - th / 3.0);
+                }
+                sig[3 * N + c] = 2.0 * edge_shear(g, m, 2, i, j, k) * eps[3 * N + c];
+                sig[4 * N + c] = 2.0 * edge_shear(g, m, 1, i, j, k) * eps[4 * N + c];
+                sig[5 * N + c] = 2.0 * edge_shear(g, m, 0, i, j, k) * eps[5 * N + c];
             }
 }
 
@@ -134,35 +167,26 @@ static double dot(int64_t n, const double *a, const double *b) {
 
 /* ---- exported entry points ------------------------------------------------ */
 
-/* Stresses (6N, order xx yy zz at cells, yz xz xy at edges) for displacement u. */
-void or_stress(const int64_t dims[3], const double h[3], const double *K, const double *G,
-               const double E[6], const double *u, double *sig) {
-    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    const int64_t N = g.nx * g.ny * g.nz;
+static void m_stress(const grid_t *g, const mat_t *m, const double E[6], const double *u, double *sig) {
+    const int64_t N = g->nx * g->ny * g->nz;
     double *eps = malloc(sizeof(double) * 6 * N);
-    strains(&g, E, u, eps);
-    hooke(&g, K, G, eps, sig);
+    strains(g, E, u, eps);
+    hooke(g, m, eps, sig);
     free(eps);
 }
 
-/* Residual r = div(C : (E + grad u)) at faces (3N). */
-void or_residual(const int64_t dims[3], const double h[3], const double *K, const double *G,
-                 const double E[6], const double *u, double *r) {
-    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    const int64_t N = g.nx * g.ny * g.nz;
+static void m_residual(const grid_t *g, const mat_t *m, const double E[6], const double *u, double *r) {
+    const int64_t N = g->nx * g->ny * g->nz;
     double *sig = malloc(sizeof(double) * 6 * N);
-    or_stress(dims, h, K, G, E, u, sig);
-    divergence(&g, sig, r);
+    m_stress(g, m, E, u, sig);
+    divergence(g, sig, r);
     free(sig);
 }
 
-/* Volume averages of the six stress components (Voigt order 11 22 33 23 13 12),
- * each over its own node set (cells or edges, N points each). */
-void or_average_stress(const int64_t dims[3], const double h[3], const double *K, const double *G,
-                       const double E[6], const double *u, double out[6]) {
-    const int64_t N = dims[0] * dims[1] * dims[2];
+static void m_average_stress(const grid_t *g, const mat_t *m, const double E[6], const double *u, double out[6]) {
+    const int64_t N = g->nx * g->ny * g->nz;
     double *sig = malloc(sizeof(double) * 6 * N);
-    or_stress(dims, h, K, G, E, u, sig);
+    m_stress(g, m, E, u, sig);
     for (int c = 0; c < 6; c++) {
         double s = 0.0;
         for (int64_t t = 0; t < N; t++) s += sig[c * N + t];
@@ -171,28 +195,81 @@ void or_average_stress(const int64_t dims[3], const double h[3], const double *K
     free(sig);
 }
 
+/* Stresses (6N, order xx yy zz at cells, yz xz xy at edges) for displacement u. */
+void or_stress(const int64_t dims[3], const double h[3], const double *K, const double *G,
+               const double E[6], const double *u, double *sig) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, NULL};
+    m_stress(&g, &m, E, u, sig);
+}
+
+/* Residual r = div(C : (E + grad u)) at faces (3N). */
+void or_residual(const int64_t dims[3], const double h[3], const double *K, const double *G,
+                 const double E[6], const double *u, double *r) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, NULL};
+    m_residual(&g, &m, E, u, r);
+}
+
+/* Volume averages of the six stress components (Voigt order 11 22 33 23 13 12),
+ * each over its own node set (cells or edges, N points each). */
+void or_average_stress(const int64_t dims[3], const double h[3], const double *K, const double *G,
+                       const double E[6], const double *u, double out[6]) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, NULL};
+    m_average_stress(&g, &m, E, u, out);
+}
+
+/* The same three for orthotropic cells (c9: 9N constants, see the header). */
+void or_stress_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6],
+                     const double *u, double *sig) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {NULL, NULL, c9};
+    m_stress(&g, &m, E, u, sig);
+}
+
+void or_residual_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6],
+                       const double *u, double *r) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {NULL, NULL, c9};
+    m_residual(&g, &m, E, u, r);
+}
+
+void or_average_stress_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6],
+                             const double *u, double out[6]) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {NULL, NULL, c9};
+    m_average_stress(&g, &m, E, u, out);
+}
+
 /* Diagonal of the stiffness operator A = -div C grad (Jacobi preconditioner). */
-static void diagonal(const grid_t *g, const double *K, const double *G, double *dg) {
+/* Normal stiffness acting on face displacements of direction d in cell c:
+ * K + 4G/3 (isotropic) or C11/C22/C33 (orthotropic). */
+static double normal_stiffness(const mat_t *m, int64_t N, int d, int64_t c) {
+    if (m->c9) return m->c9[d * N + c];
+    return m->K[c] + 4.0 * m->G[c] / 3.0;
+}
+
+static void diagonal(const grid_t *g, const mat_t *m, double *dg) {
     const int64_t N = g->nx * g->ny * g->nz;
 #pragma omp parallel for collapse(2) schedule(static)
     for (int64_t k = 0; k < g->nz; k++)
         for (int64_t j = 0; j < g->ny; j++)
             for (int64_t i = 0; i < g->nx; i++) {
                 int64_t c = at(g, i, j, k);
-                double Mc = K[c] + 4.0 * G[c] / 3.0;
-                double Mx = K[at(g, i - 1, j, k)] + 4.0 * G[at(g, i - 1, j, k)] / 3.0;
-                double My = K[at(g, i, j - 1, k)] + 4.0 * G[at(g, i, j - 1, k)] / 3.0;
-                double Mz = K[at(g, i, j, k - 1)] + 4.0 * G[at(g, i, j, k - 1)] / 3.0;
+                double Mx = normal_stiffness(m, N, 0, at(g, i - 1, j, k)) + normal_stiffness(m, N, 0, c);
+                double My = normal_stiffness(m, N, 1, at(g, i, j - 1, k)) + normal_stiffness(m, N, 1, c);
+                double Mz = normal_stiffness(m, N, 2, at(g, i, j, k - 1)) + normal_stiffness(m, N, 2, c);
                 double hx2 = g->hx * g->hx, hy2 = g->hy * g->hy, hz2 = g->hz * g->hz;
-                dg[c] = (Mx + Mc) / hx2 +
-                        (edge_modulus(g, G, 0, i, j, k) + edge_modulus(g, G, 0, i, j + 1, k)) / hy2 +
-                        (edge_modulus(g, G, 1, i, j, k) + edge_modulus(g, G, 1, i, j, k + 1)) / hz2;
-                dg[N + c] = (My + Mc) / hy2 +
-                            (edge_modulus(g, G, 0, i, j, k) + edge_modulus(g, G, 0, i + 1, j, k)) / hx2 +
-                            (edge_modulus(g, G, 2, i, j, k) + edge_modulus(g, G, 2, i, j, k + 1)) / hz2;
-                dg[2 * N + c] = (Mz + Mc) / hz2 +
-                                (edge_modulus(g, G, 1, i, j, k) + edge_modulus(g, G, 1, i + 1, j, k)) / hx2 +
-                                (edge_modulus(g, G, 2, i, j, k) + edge_modulus(g, G, 2, i, j + 1, k)) / hy2;
+                dg[c] = Mx / hx2 +
+                        (edge_shear(g, m, 0, i, j, k) + edge_shear(g, m, 0, i, j + 1, k)) / hy2 +
+                        (edge_shear(g, m, 1, i, j, k) + edge_shear(g, m, 1, i, j, k + 1)) / hz2;
+                dg[N + c] = My / hy2 +
+                            (edge_shear(g, m, 0, i, j, k) + edge_shear(g, m, 0, i + 1, j, k)) / hx2 +
+                            (edge_shear(g, m, 2, i, j, k) + edge_shear(g, m, 2, i, j, k + 1)) / hz2;
+                dg[2 * N + c] = Mz / hz2 +
+                                (edge_shear(g, m, 1, i, j, k) + edge_shear(g, m, 1, i + 1, j, k)) / hx2 +
+                                (edge_shear(g, m, 2, i, j, k) + edge_shear(g, m, 2, i, j + 1, k)) / hy2;
             }
 }
 
@@ -211,20 +288,19 @@ static void remove_mean(int64_t N, double *v) {
  * Returns the iteration count; *relres gets the final true relative residual
  * (recomputed from u, not the recursive one).  hist (optional, length hist_cap)
  * receives the recursive relative residual of every iteration. */
-int64_t or_pcg(const int64_t dims[3], const double h[3], const double *K, const double *G,
-               const double E[6], double rtol, int64_t max_iter, double *u, double *relres,
-               double *hist, int64_t hist_cap) {
-    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+static int64_t m_pcg(const grid_t *gp, const mat_t *m, const double E[6], double rtol, int64_t max_iter,
+                     double *u, double *relres, double *hist, int64_t hist_cap) {
+    const grid_t g = *gp;
     const int64_t N = g.nx * g.ny * g.nz, n3 = 3 * N;
     const double zero[6] = {0, 0, 0, 0, 0, 0};
     double *r = malloc(sizeof(double) * n3), *z = malloc(sizeof(double) * n3);
     double *p = malloc(sizeof(double) * n3), *q = malloc(sizeof(double) * n3);
     double *dg = malloc(sizeof(double) * n3), *b = malloc(sizeof(double) * n3);
-    diagonal(&g, K, G, dg);
-    or_residual(dims, h, K, G, E, u, r); /* r = div C (E + grad u) = b - A u */
+    diagonal(&g, m, dg);
+    m_residual(&g, m, E, u, r); /* r = div C (E + grad u) = b - A u */
     {
         double *u0 = calloc(n3, sizeof(double));
-        or_residual(dims, h, K, G, E, u0, b); /* b = div C E */
+        m_residual(&g, m, E, u0, b); /* b = div C E */
         free(u0);
     }
     double bnorm = sqrt(dot(n3, b, b));
@@ -242,7 +318,7 @@ int64_t or_pcg(const int64_t dims[3], const double h[3], const double *K, const 
         if (hist && it < hist_cap) hist[it] = rn;
         if (rn <= rtol) break;
         /* q = A p = -div C grad p */
-        or_residual(dims, h, K, G, zero, p, q);
+        m_residual(&g, m, zero, p, q);
         for (int64_t t = 0; t < n3; t++) q[t] = -q[t];
         double alpha = rz / dot(n3, p, q);
         for (int64_t t = 0; t < n3; t++) {
@@ -257,11 +333,84 @@ int64_t or_pcg(const int64_t dims[3], const double h[3], const double *K, const 
         for (int64_t t = 0; t < n3; t++) p[t] = z[t] + beta * p[t];
     }
     remove_mean(N, u);
-    or_residual(dims, h, K, G, E, u, r);
+    m_residual(&g, m, E, u, r);
     *relres = sqrt(dot(n3, r, r)) / bnorm;
 done:
     free(r); free(z); free(p); free(q); free(dg); free(b);
     return it;
+}
+
+int64_t or_pcg(const int64_t dims[3], const double h[3], const double *K, const double *G,
+               const double E[6], double rtol, int64_t max_iter, double *u, double *relres,
+               double *hist, int64_t hist_cap) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, NULL};
+    return m_pcg(&g, &m, E, rtol, max_iter, u, relres, hist, hist_cap);
+}
+
+int64_t or_pcg_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6], double rtol,
+                     int64_t max_iter, double *u, double *relres, double *hist, int64_t hist_cap) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {NULL, NULL, c9};
+    return m_pcg(&g, &m, E, rtol, max_iter, u, relres, hist, hist_cap);
+}
+
+/* Stiffness that limits the explicit step of face displacements of direction d
+ * in cell c: for isotropic cells K + 4G/3; for orthotropic cells the largest of
+ * the normal constant and the two shear constants acting on that component
+ * (x: C11, C66, C55; y: C22, C66, C44; z: C33, C55, C44), which bounds the
+ * diagonal of the operator the same way K + 4G/3 does in the isotropic case. */
+static double step_stiffness(const mat_t *m, int64_t N, int d, int64_t c) {
+    if (!m->c9) return m->K[c] + 4.0 * m->G[c] / 3.0;
+    static const int sh[3][2] = {{8, 7}, {8, 6}, {7, 6}};
+    double a = m->c9[d * N + c], b = m->c9[sh[d][0] * N + c], e = m->c9[sh[d][1] * N + c];
+    return fmax(a, fmax(b, e));
+}
+
+/* The APT iteration written on the displacement fluctuation alone.  With unit
+ * physical step and pseudo moduli equal to the local moduli, the stress of the
+ * paper's relaxation equations is an exponential average of Hooke's stress, and
+ * eliminating it from the momentum equation leaves the two-level recurrence
+ *   u^1     = u^0 + (beta / H_f) r(u^0)
+ *   u^{n+1} = u^n + a (u^n - u^{n-1}) + (a c beta / H_f) r(u^n)
+ * with r = div C:(E + grad u), c = ell St / Lx, beta = ell Lx / St, a = 1/(1+c),
+ * ell = courant / sqrt(sum 1/h^2), Lx the largest box edge, and H_f the larger
+ * step stiffness of the two cells a face separates.  For isotropic cells this
+ * is the same iterate sequence as or_apt_steps (tests check that); for
+ * orthotropic cells it is the definition of the iteration.
+ * Starts from u^0 = 0 and returns u^nsteps in u (3N) and u^(nsteps-1) in u_prev
+ * (3N, may be NULL). */
+static void m_apt_disp(const grid_t *g, const mat_t *m, const double E[6], double courant, double strouhal,
+                       int64_t nsteps, double *u, double *u_prev) {
+    const int64_t N = g->nx * g->ny * g->nz, n3 = 3 * N;
+    double Lx = fmax(fmax(g->nx * g->hx, g->ny * g->hy), g->nz * g->hz);
+    double ell = courant / sqrt(1.0 / (g->hx * g->hx) + 1.0 / (g->hy * g->hy) + 1.0 / (g->hz * g->hz));
+    double c = ell * strouhal / Lx, beta = ell * Lx / strouhal, a = 1.0 / (1.0 + c);
+    double *old = calloc(n3, sizeof(double)), *r = malloc(sizeof(double) * n3), *Hf = malloc(sizeof(double) * n3);
+    for (int64_t t = 0; t < N; t++) {
+        int64_t i = t % g->nx, j = (t / g->nx) % g->ny, k = t / (g->nx * g->ny);
+        int64_t nb[3] = {at(g, i - 1, j, k), at(g, i, j - 1, k), at(g, i, j, k - 1)};
+        for (int d = 0; d < 3; d++) Hf[d * N + t] = fmax(step_stiffness(m, N, d, t), step_stiffness(m, N, d, nb[d]));
+    }
+    memset(u, 0, sizeof(double) * n3);
+    for (int64_t s = 0; s < nsteps; s++) {
+        m_residual(g, m, E, u, r);
+        for (int64_t t = 0; t < n3; t++) {
+            double nu = s == 0 ? u[t] + beta / Hf[t] * r[t]
+                               : u[t] + a * (u[t] - old[t]) + a * c * beta / Hf[t] * r[t];
+            old[t] = u[t];
+            u[t] = nu;
+        }
+    }
+    if (u_prev) memcpy(u_prev, old, sizeof(double) * n3);
+    free(old); free(r); free(Hf);
+}
+
+void or_apt_disp(const int64_t dims[3], const double h[3], const double *K, const double *G, const double *c9,
+                 const double E[6], double courant, double strouhal, int64_t nsteps, double *u, double *u_prev) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, c9};
+    m_apt_disp(&g, &m, E, courant, strouhal, nsteps, u, u_prev);
 }
 
 /* Accelerated pseudo-transient iterations written in the paper's own variables

@@ -69,6 +69,34 @@ def stress_field(K, G, eps):
     return out
 
 
+def stress_field_c9(C9, eps):
+    """Stresses of orthotropic cells (C9: C11 C22 C33 C23 C13 C12 C44 C55 C66)."""
+    C11, C22, C33, C23, C13, C12, C44, C55, C66 = C9
+    out = np.empty_like(eps)
+    out[0] = C11 * eps[0] + C12 * eps[1] + C13 * eps[2]
+    out[1] = C12 * eps[0] + C22 * eps[1] + C23 * eps[2]
+    out[2] = C13 * eps[0] + C23 * eps[1] + C33 * eps[2]
+    for c, Cs in enumerate((C44, C55, C66)):
+        out[3 + c] = 2.0 * edge_moduli(Cs)[c] * eps[3 + c]
+    return out
+
+
+def _energy_weights_c9(C9):
+    """As _energy_weights, for W = 1/2 sum_cells e_n . Cn e_n + sum_edges 2 C_e eps_e^2."""
+    C11, C22, C33, C23, C13, C12, C44, C55, C66 = [c.ravel() for c in C9]
+    Ce = np.stack([edge_moduli(Cs)[c].ravel() for c, Cs in enumerate((C9[6], C9[7], C9[8]))])
+
+    def apply(eps):
+        out = np.empty_like(eps)
+        out[0] = C11 * eps[0] + C12 * eps[1] + C13 * eps[2]
+        out[1] = C12 * eps[0] + C22 * eps[1] + C23 * eps[2]
+        out[2] = C13 * eps[0] + C23 * eps[1] + C33 * eps[2]
+        for c in range(3):
+            out[3 + c] = 4.0 * Ce[c] * eps[3 + c]
+        return out
+    return apply
+
+
 def _energy_weights(K, G):
     """Quadratic form of the energy density per node: returns a function that
     maps strains (6, N) to the weighted strains D eps (so W = eps^T D eps / 2)."""
@@ -88,16 +116,17 @@ def _energy_weights(K, G):
     return apply
 
 
-def solve_dense(K, G, E, h=(1.0, 1.0, 1.0)):
-    """Displacement fluctuation minimising the discrete strain energy (3, nz, ny, nx)."""
-    shape = K.shape
-    N = K.size
+def solve_dense(K, G, E, h=(1.0, 1.0, 1.0), C9=None):
+    """Displacement fluctuation minimising the discrete strain energy (3, nz, ny, nx).
+    Isotropic (K, G) cells, or orthotropic cells when C9 is given."""
+    shape = K.shape if C9 is None else C9.shape[1:]
+    N = int(np.prod(shape))
     zero = np.zeros(6)
     B = np.empty((6 * N, 3 * N))
     for col in range(3 * N):
         u = np.zeros(3 * N); u[col] = 1.0
         B[:, col] = strain_field(u.reshape((3,) + shape), zero, h).reshape(6 * N)
-    Dapply = _energy_weights(K, G)
+    Dapply = _energy_weights(K, G) if C9 is None else _energy_weights_c9(C9)
     DB = np.empty_like(B)
     for col in range(3 * N):
         DB[:, col] = Dapply(B[:, col].reshape(6, N)).reshape(6 * N)
@@ -108,12 +137,13 @@ def solve_dense(K, G, E, h=(1.0, 1.0, 1.0)):
     return u.reshape((3,) + shape), A
 
 
-def ceff_dense(K, G, h=(1.0, 1.0, 1.0)):
+def ceff_dense(K, G, h=(1.0, 1.0, 1.0), C9=None):
     """6x6 effective stiffness by dense energy minimisation, Voigt order."""
     C = np.empty((6, 6))
     for J in range(6):
         E = np.zeros(6); E[J] = 1.0 if J < 3 else 0.5
-        u, _ = solve_dense(K, G, E, h)
-        sig = stress_field(K, G, strain_field(u, E, h))
+        u, _ = solve_dense(K, G, E, h, C9)
+        eps = strain_field(u, E, h)
+        sig = stress_field(K, G, eps) if C9 is None else stress_field_c9(C9, eps)
         C[:, J] = sig.reshape(6, -1).mean(axis=1)
     return C

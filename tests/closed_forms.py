@@ -57,6 +57,29 @@ def backus_z(fracs, Ks, Gs):
     return C
 
 
+def backus_z_ortho(fracs, Cs):
+    """Effective Voigt stiffness of orthotropic layers (axes aligned) stacked along z.
+    The in-plane strains (11, 22, 12) and the tractions (33, 13, 23) are the same in every
+    layer; eliminating the layer strains eps33, eps13, eps23 gives the averages below."""
+    f = np.asarray(fracs, float); f = f / f.sum()
+    avg = lambda a: float(np.sum(f * np.asarray(a, float)))
+    C = [np.asarray(c, float) for c in Cs]
+    g = lambda I, J: np.array([c[I, J] for c in C])
+    C33 = 1.0 / avg(1.0 / g(2, 2))
+    a13 = avg(g(0, 2) / g(2, 2)); a23 = avg(g(1, 2) / g(2, 2))
+    out = np.zeros((6, 6))
+    out[2, 2] = C33
+    out[0, 2] = out[2, 0] = C33 * a13
+    out[1, 2] = out[2, 1] = C33 * a23
+    out[0, 0] = avg(g(0, 0) - g(0, 2) ** 2 / g(2, 2)) + C33 * a13 ** 2
+    out[1, 1] = avg(g(1, 1) - g(1, 2) ** 2 / g(2, 2)) + C33 * a23 ** 2
+    out[0, 1] = out[1, 0] = avg(g(0, 1) - g(0, 2) * g(1, 2) / g(2, 2)) + C33 * a13 * a23
+    out[3, 3] = 1.0 / avg(1.0 / g(3, 3))
+    out[4, 4] = 1.0 / avg(1.0 / g(4, 4))
+    out[5, 5] = avg(g(5, 5))
+    return out
+
+
 def voigt_bound(K, G):
     """Arithmetic mean of the local stiffness (per-voxel fields)."""
     return c_iso(np.mean(K), np.mean(G))
