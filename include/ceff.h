@@ -126,7 +126,18 @@ ceff_status ceff_set_phases(ceff_ctx* ctx, const uint8_t* phase, int where, int 
                             const double* G_tab);
 
 /* Anisotropic local stiffness c_ijkl(x) (paper, "Future perspectives", items
- * 2-3).  Not implemented: always returns CEFF_EUNSUPPORTED. */
+ * 2-3).  ncomp = 9: orthotropic cells with axes aligned with the grid, given as
+ * 9 x N values, component-major (c[q*N + cell]), q = 0..8:
+ *   C11 C22 C33 C23 C13 C12 C44 C55 C66   (Voigt, engineering shear).
+ * Normal stresses at a cell are its 3x3 normal block times the normal strains;
+ * the shear stress at an edge is 2 eps times the harmonic mean, over the four
+ * cells around the edge, of C44 (yz-edges), C55 (xz) or C66 (xy), as for G in
+ * the isotropic case (isotropic cells: C11 = K + 4G/3, C12 = K - 2G/3, C44 = G).
+ * dtype CEFF_F32/CEFF_F64, host or device; copied.  Every constant must be
+ * finite, the diagonal ones > 0 and each normal block positive definite, else
+ * CEFF_EINVAL.  ncomp = 21 (general anisotropy, which needs strains
+ * interpolated between cells and edges) returns CEFF_EUNSUPPORTED.  Replaces
+ * any material set before; ceff_gradient is not available for such materials. */
 ceff_status ceff_set_stiffness(ceff_ctx* ctx, const void* c, int ncomp, int dtype, int where);
 
 /* Solve the unit loads in load_mask (bit J = Voigt column J, 0..5) and write
@@ -151,7 +162,8 @@ ceff_status ceff_solve_batch(ceff_ctx* ctx, int nsamples, const int64_t* dims, c
 
 /* Gradient of J = sum_IJ W[I*6+J] C_IJ with respect to the per-voxel K and G
  * of the current material, from the displacements kept by the last
- * ceff_solve (keep_fields = 1, all loads that W touches).  The solution is
+ * ceff_solve (keep_fields = 1, all loads that W touches; isotropic materials
+ * only, else CEFF_EUNSUPPORTED).  The solution is
  * stationary, so only the explicit dependence of the strain energy on the
  * moduli enters (no second solve).  dK, dG: N values each, dtype, host or
  * device. */

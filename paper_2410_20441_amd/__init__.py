@@ -222,6 +222,18 @@ class Context:
         self.shape = (nz, ny, nx)
         self.h_spacing = tuple(map(float, h))
 
+    def set_stiffness(self, C9, h=(1.0, 1.0, 1.0)):
+        """Orthotropic cells: C9 shaped (9, nz, ny, nx), constants C11 C22 C33 C23 C13 C12 C44 C55 C66
+        (numpy or torch, float32/float64)."""
+        if C9.ndim != 4 or C9.shape[0] != 9:
+            raise ValueError("C9 must be shaped (9, nz, ny, nx)")
+        nz, ny, nx = (int(v) for v in C9.shape[1:])
+        ceff_set_grid(self.h, nx, ny, nz, *map(float, h))
+        p, dt, wh, keep = _array_arg(C9, "C9")
+        ceff_set_stiffness(self.h, p, 9, dt, wh)
+        self.shape = (nz, ny, nx)
+        self.h_spacing = tuple(map(float, h))
+
     def set_phases(self, phase, K_tab, G_tab, h=(1.0, 1.0, 1.0)):
         ph = np.ascontiguousarray(phase, np.uint8)
         nx, ny, nz = _shape3(ph)

@@ -86,6 +86,9 @@ struct ceff_ctx {
   // G), in FP64 and FP32; nphase = 0 when the material came as fields
   DevBuf phase8, ptab64, ptab32;
   int nphase = 0;
+  // material given as orthotropic cells: 9N constants (FP64, FP32 copy for the mixed path)
+  DevBuf c64, c32;
+  bool ortho = false;
   DevBuf keep[6];
   bool kept[6] = {false, false, false, false, false, false};
   std::string err;
@@ -192,6 +195,12 @@ ceff_status check_positive(ceff_ctx* c, const double* K, const double* G, int64_
   return CEFF_OK;
 }
 
+void clear_ortho(ceff_ctx* c) {
+  c->c64.reset();
+  c->c32.reset();
+  c->ortho = false;
+}
+
 void clear_phases(ceff_ctx* c) {
   c->phase8.reset();
   c->ptab64.reset();
@@ -219,6 +228,8 @@ struct SampleIn {
   const double* ptab64 = nullptr;
   const float* ptab32 = nullptr;
   int nphase = 0;
+  const double* c64 = nullptr;  // orthotropic cells (9N) or nullptr
+  const float* c32 = nullptr;
 };
 
 struct Prob {
@@ -292,14 +303,18 @@ struct Engine {
 
   bool single() const { return Js.size() == 1; }
   int slot_of(int J) const { return single() ? 0 : J; }
-  int group() const { return single() || ts.pf == 5 ? 1 : (ts.group > 0 ? ts.group : kMaxLoads); }
+  int group() const {
+    return single() || ts.pf == 5 || ts.ortho ? 1 : (ts.group > 0 ? ts.group : kMaxLoads);
+  }
 
   // Read the moduli from the phase image when there is one (one sample) and the
   // kernel variant supports it; CEFF_MODULI=fields keeps the K and G fields.
+  // Orthotropic cells always take their own kernel (one load per block).
   TileShape with_moduli(TileShape t) const {
     const char* env = std::getenv("CEFF_MODULI");
     const bool fields = env != nullptr && std::strcmp(env, "fields") == 0;
-    t.pal = in.size() == 1 && in[0].phase != nullptr && t.pf == 3 && !fields ? 1 : 0;
+    t.ortho = in[0].c64 != nullptr ? 1 : 0;
+    t.pal = !t.ortho && in.size() == 1 && in[0].phase != nullptr && t.pf == 3 && !fields ? 1 : 0;
     return t;
   }
 
@@ -396,7 +411,7 @@ struct Engine {
           ++nact;
           b += N * sizeof(T) * (9.0 + (h_in[si].force[l] ? 3.0 : 0.0));
         }
-      if (nact) b += N * (ts.pal ? 1.0 : sizeof(T) * 2.0);
+      if (nact) b += N * (ts.ortho ? sizeof(T) * 9.0 : (ts.pal ? 1.0 : sizeof(T) * 2.0));
     }
     return b;
   }
@@ -410,6 +425,7 @@ struct Engine {
 
   hipError_t step_on(const WorkItem* dw, int nw, TileShape t, int grp, int par, int first, double* partials) {
     const SampleDesc<T>* d = d_in.as<SampleDesc<T>>();
+    if (t.ortho) return launch_step_ortho<T>(d, dw, nw, t, par, first, partials, c->s);
     switch (grp) {
       case 1: return launch_step<T, 1>(d, dw, nw, t, par, first, partials, c->s);
       case 2: return launch_step<T, 2>(d, dw, nw, t, par, first, partials, c->s);
@@ -426,7 +442,10 @@ struct Engine {
   hipError_t outer_residual(bool write_force) {
     hipError_t e;
     float* const* rout = write_force ? d_rout.as<float*>() : nullptr;
-    if (single())
+    if (ts.ortho)
+      e = launch_residual_ortho<double, float>(d_out.as<SampleDesc<double>>(), d_work_o.as<WorkItem>(),
+                                               (int)work_o.size(), ts, 0, rout, d_partials.as<double>(), c->s);
+    else if (single())
       e = launch_residual<double, float, 1>(d_out.as<SampleDesc<double>>(), d_work_o.as<WorkItem>(),
                                             (int)work_o.size(), ts, 0, rout, d_partials.as<double>(), c->s);
     else
@@ -462,7 +481,7 @@ struct Engine {
       return CEFF_OK;
     }
     ts = with_moduli(default_tile(in[0].nx, in[0].ny, fp64, single()));
-    if (!o.autotune) return CEFF_OK;
+    if (!o.autotune || ts.ortho) return CEFF_OK;
     std::vector<TileShape> cand;
     const int bxs[] = {18, 34, 66};
     const int bys[] = {6, 7, 10, 14};
@@ -554,12 +573,14 @@ struct Engine {
         dsc->phase = s.phase;
         dsc->ptab = sizeof(T) == 8 ? (const T*)s.ptab64 : (const T*)s.ptab32;
         dsc->nphase = s.nphase;
+        dsc->cst = sizeof(T) == 8 ? (const T*)s.c64 : (const T*)s.c32;
       }
       SampleDesc<double>& od = h_out[si];
       od.nx = s.nx; od.ny = s.ny; od.nz = s.nz; od.N = N;
       od.rhx = 1.0 / s.h[0]; od.rhy = 1.0 / s.h[1]; od.rhz = 1.0 / s.h[2];
       od.mom = p.mom; od.sfac = p.sfac; od.sfac_first = p.sfac_first;
       od.K = s.K64; od.G = s.G64;
+      od.cst = s.c64;
       for (int J : Js) {
         const int l = slot_of(J);
         for (int b = 0; b < 2; ++b) {
@@ -593,7 +614,7 @@ struct Engine {
     STCK(build_work(ts, group(), work, ranges, kcs));
     TileShape to = ts;
     to.kc = 0;
-    STCK(build_work(to, single() ? 1 : kMaxLoads, work_o, ranges_o, kcs_o));
+    STCK(build_work(to, single() || ts.ortho ? 1 : kMaxLoads, work_o, ranges_o, kcs_o));
     for (int si = 0; si < ns; ++si) {
       h_in[si].kc = kcs[si];
       h_out[si].kc = kcs_o[si];
@@ -867,8 +888,12 @@ ceff_status stress_average(ceff_ctx* c, const SampleIn& s, int J, const double* 
   HIPCK(c, o6.alloc(sizeof(double) * 6));
   double E[6];
   unit_strain(J, E);
-  HIPCK(c, launch_average_stress(s.nx, s.ny, s.nz, s.h, s.K64, s.G64, E, u, part.as<double>(), cap, o6.as<double>(),
-                                 c->s));
+  if (s.c64)
+    HIPCK(c, launch_average_stress_ortho(s.nx, s.ny, s.nz, s.h, s.c64, E, u, part.as<double>(), cap,
+                                         o6.as<double>(), c->s));
+  else
+    HIPCK(c, launch_average_stress(s.nx, s.ny, s.nz, s.h, s.K64, s.G64, E, u, part.as<double>(), cap,
+                                   o6.as<double>(), c->s));
   HIPCK(c, hipMemcpyAsync(out6, o6.p, sizeof(double) * 6, hipMemcpyDeviceToHost, c->s));
   HIPCK(c, hipStreamSynchronize(c->s));
   for (int q = 0; q < 6; ++q) out6[q] /= (double)N;
@@ -919,6 +944,12 @@ ceff_status run_engine(ceff_ctx* c, std::vector<SampleIn> samples, std::vector<i
 ceff_status ensure32(ceff_ctx* c) {
   if (c->have32) return CEFF_OK;
   const int64_t N = c->nx * c->ny * c->nz;
+  if (c->ortho) {
+    HIPCK(c, c->c32.alloc(sizeof(float) * 9 * N));
+    HIPCK(c, launch_convert<double, float>(c->c64.as<double>(), c->c32.as<float>(), 9 * N, c->s));
+    c->have32 = true;
+    return CEFF_OK;
+  }
   HIPCK(c, c->K32.alloc(sizeof(float) * N));
   HIPCK(c, c->G32.alloc(sizeof(float) * N));
   HIPCK(c, launch_convert<double, float>(c->K64.as<double>(), c->K32.as<float>(), N, c->s));
@@ -981,7 +1012,7 @@ bool fuse_by_cache(const ceff_ctx* c, bool mixed, int nloads) {
   if (nloads < 2) return true;
   const double N = (double)c->nx * c->ny * c->nz;
   const double w = mixed ? 4.0 : 8.0;
-  const double mat = c->nphase > 0 ? 1.0 : 2.0 * w;
+  const double mat = c->ortho ? 9.0 * w : (c->nphase > 0 ? 1.0 : 2.0 * w);
   const double one = N * (6.0 * w + mat), all = N * (6.0 * w * nloads + mat);
   return !(one <= kInfinityCacheBytes && all > kInfinityCacheBytes);
 }
@@ -993,6 +1024,10 @@ SampleIn ctx_sample(ceff_ctx* c) {
   s.K64 = c->K64.as<double>(); s.G64 = c->G64.as<double>();
   s.K32 = c->have32 ? c->K32.as<float>() : nullptr;
   s.G32 = c->have32 ? c->G32.as<float>() : nullptr;
+  if (c->ortho) {
+    s.c64 = c->c64.as<double>();
+    s.c32 = c->have32 ? c->c32.as<float>() : nullptr;
+  }
   if (c->nphase > 0) {
     s.phase = c->phase8.as<uint8_t>();
     s.ptab64 = c->ptab64.as<double>();
@@ -1046,6 +1081,7 @@ void ceff_destroy(ceff_ctx* c) {
   if (c->s) (void)hipStreamSynchronize(c->s);
   c->K64.reset(); c->G64.reset(); c->K32.reset(); c->G32.reset();
   clear_phases(c);
+  clear_ortho(c);
   clear_kept(c);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -1069,6 +1105,7 @@ ceff_status ceff_set_grid(ceff_ctx* c, int64_t nx, int64_t ny, int64_t nz, doubl
   c->have32 = false;
   c->K64.reset(); c->G64.reset(); c->K32.reset(); c->G32.reset();
   clear_phases(c);
+  clear_ortho(c);
   clear_kept(c);
   c->err.clear();
   return CEFF_OK;
@@ -1085,6 +1122,7 @@ ceff_status ceff_set_isotropic(ceff_ctx* c, const void* K, const void* G, int dt
   c->have_material = false;
   c->have32 = false;
   clear_phases(c);
+  clear_ortho(c);
   clear_kept(c);
   STCK(load_moduli(c, K, dtype, where, N, c->K64));
   STCK(load_moduli(c, G, dtype, where, N, c->G64));
@@ -1117,6 +1155,7 @@ ceff_status ceff_set_phases(ceff_ctx* c, const uint8_t* phase, int where, int np
   c->have_material = false;
   c->have32 = false;
   clear_phases(c);
+  clear_ortho(c);
   clear_kept(c);
   // the table in both precisions; (float)x rounds as the device conversion of
   // the FP64 fields does, so table and fields hold the same values
@@ -1145,9 +1184,40 @@ ceff_status ceff_set_phases(ceff_ctx* c, const uint8_t* phase, int where, int np
 }
 
 ceff_status ceff_set_stiffness(ceff_ctx* c, const void* cmat, int ncomp, int dtype, int where) {
-  (void)cmat; (void)ncomp; (void)dtype; (void)where;
   if (!c) return CEFF_EINVAL;
-  return fail(c, CEFF_EUNSUPPORTED, "anisotropic local stiffness is not implemented");
+  if (!c->grid_set) return fail(c, CEFF_ESTATE, "set the grid first");
+  if (ncomp == 21) return fail(c, CEFF_EUNSUPPORTED, "general anisotropic (21-constant) cells are not implemented");
+  if (ncomp != 9) return fail(c, CEFF_EINVAL, "ncomp must be 9 (orthotropic, axes aligned with the grid)");
+  if (!cmat) return fail(c, CEFF_EINVAL, "null stiffness");
+  if (dtype != CEFF_F32 && dtype != CEFF_F64) return fail(c, CEFF_EINVAL, "dtype must be CEFF_F32 or CEFF_F64");
+  if (where != CEFF_HOST && where != CEFF_DEVICE) return fail(c, CEFF_EINVAL, "where must be CEFF_HOST or CEFF_DEVICE");
+  STCK(begin_call(c));
+  const int64_t N = c->nx * c->ny * c->nz;
+  c->have_material = false;
+  c->have32 = false;
+  c->K64.reset(); c->G64.reset(); c->K32.reset(); c->G32.reset();
+  clear_phases(c);
+  clear_ortho(c);
+  clear_kept(c);
+  STCK(load_moduli(c, cmat, dtype, where, 9 * N, c->c64));
+  {
+    DevBuf bad;
+    int nb = 0;
+    HIPCK(c, bad.alloc(sizeof(int) * 65536));
+    HIPCK(c, launch_check_ortho(c->c64.as<double>(), N, bad.as<int>(), &nb, c->s));
+    std::vector<int> h(nb);
+    HIPCK(c, hipMemcpyAsync(h.data(), bad.p, sizeof(int) * nb, hipMemcpyDeviceToHost, c->s));
+    HIPCK(c, hipStreamSynchronize(c->s));
+    for (int v : h)
+      if (v) {
+        c->c64.reset();
+        return fail(c, CEFF_EINVAL, "orthotropic constants must be finite, with positive diagonal and a "
+                                    "positive definite normal block");
+      }
+  }
+  c->ortho = true;
+  c->have_material = true;
+  return CEFF_OK;
 }
 
 ceff_status ceff_solve(ceff_ctx* c, uint32_t load_mask, const ceff_solve_opts* opts, double C_out[36], double* hist,
@@ -1278,6 +1348,7 @@ ceff_status ceff_gradient(ceff_ctx* c, const double W[36], void* dK, void* dG, i
   for (int q = 0; q < 36; ++q)
     if (!std::isfinite(W[q])) return fail(c, CEFF_EINVAL, "W must be finite");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  if (c->ortho) return fail(c, CEFF_EUNSUPPORTED, "the gradient is defined for isotropic (K, G) materials only");
   const double* u6[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   for (int I = 0; I < 6; ++I)
     for (int J = 0; J < 6; ++J)
@@ -1407,9 +1478,14 @@ ceff_status ceff_residual(ceff_ctx* c, int J, int precision, const double* u, do
     T* rptr[1] = {r.as<T>()};
     HIPCK(c, rp.alloc(sizeof rptr));
     HIPCK(c, hipMemcpyAsync(rp.p, rptr, sizeof rptr, hipMemcpyHostToDevice, c->s));
-    HIPCK(c, launch_residual<T, T, 1>(e.d_in.template as<SampleDesc<T>>(), e.d_work.template as<WorkItem>(),
-                                      (int)e.work.size(), e.ts, 0, rp.as<T*>(), e.d_partials.template as<double>(),
-                                      c->s));
+    if (e.ts.ortho)
+      HIPCK(c, launch_residual_ortho<T, T>(e.d_in.template as<SampleDesc<T>>(), e.d_work.template as<WorkItem>(),
+                                           (int)e.work.size(), e.ts, 0, rp.as<T*>(),
+                                           e.d_partials.template as<double>(), c->s));
+    else
+      HIPCK(c, launch_residual<T, T, 1>(e.d_in.template as<SampleDesc<T>>(), e.d_work.template as<WorkItem>(),
+                                        (int)e.work.size(), e.ts, 0, rp.as<T*>(), e.d_partials.template as<double>(),
+                                        c->s));
     HIPCK(c, launch_finalize_norms(e.d_ranges.template as<int>(), 1, e.d_partials.template as<double>(),
                                    e.d_norms.template as<double>(), c->s));
     double nn[kMaxLoads];

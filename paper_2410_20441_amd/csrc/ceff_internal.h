@@ -28,6 +28,10 @@ struct SampleDesc {
   const uint8_t* phase;
   const T* ptab;
   int nphase;
+  // Orthotropic cells: 9N constants C11 C22 C33 C23 C13 C12 C44 C55 C66
+  // (component-major) or nullptr; when set, K, G and the phase image are unused
+  // and the orthotropic kernels run (TileShape::ortho).
+  const T* cst;
   T E[kMaxLoads][6];          // macroscopic tensor strain per load: xx yy zz yz xz xy
   unsigned active;            // bit l: load l is iterated
   int work_begin, work_end;   // this sample's work items [begin, end)
@@ -53,6 +57,7 @@ struct TileShape {
   int order;   // 0: load groups of a tile 8 items apart; 1: each XCD takes a contiguous band
   int occ;     // 1: build that targets more waves per SIMD (fewer registers)
   int pal;     // 1: moduli from the samples' phase image and table (variant 3 only)
+  int ortho;   // 1: orthotropic cells (one load per block, its own kernel)
 };
 
 // ---- launch wrappers (ceff_kernels.hip) ----------------------------------------
@@ -72,6 +77,16 @@ template <typename T, typename R, int L>
 hipError_t launch_residual(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
                            int parity, R* const* rout, double* partials, hipStream_t s);
 
+// The same two for orthotropic cells (SampleDesc::cst).
+template <typename T>
+hipError_t launch_step_ortho(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
+                             int parity, int first, double* partials, hipStream_t s);
+template <typename T, typename R>
+hipError_t launch_residual_ortho(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
+                                 int parity, R* const* rout, double* partials, hipStream_t s);
+// Dynamic LDS of the orthotropic kernels for shape ts and element size elem.
+size_t ortho_lds_bytes(TileShape ts, size_t elem);
+
 // Sum partials of each (sample, load) in fixed order: out[s*kMaxLoads + l].
 hipError_t launch_finalize_norms(const int* d_ranges /* 2 per sample */, int nsamples, const double* partials,
                                  double* out, hipStream_t s);
@@ -81,6 +96,11 @@ hipError_t launch_finalize_norms(const int* d_ranges /* 2 per sample */, int nsa
 hipError_t launch_average_stress(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K,
                                  const double* G, const double E[6], const double* u, double* partials,
                                  int nblocks_cap, double* out6, hipStream_t s);
+
+// The same for orthotropic cells (cst: 9N FP64 constants).
+hipError_t launch_average_stress_ortho(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* cst,
+                                       const double E[6], const double* u, double* partials, int nblocks_cap,
+                                       double* out6, hipStream_t s);
 
 // Gradient of sum W_IJ C_IJ with respect to per-voxel K and G from six FP64
 // displacement fields.
@@ -105,5 +125,8 @@ hipError_t launch_phase_to_fields(const uint8_t* phase, int64_t n, const double*
 // (bad must hold 65536 ints).
 template <typename T>
 hipError_t launch_check_moduli(const T* K, const T* G, int64_t n, int* bad, int* nblocks, hipStream_t s);
+// Per-block flags (1 = some cell's orthotropic constants are not finite, a
+// diagonal one is not > 0, or its normal block is not positive definite).
+hipError_t launch_check_ortho(const double* c, int64_t n, int* bad, int* nblocks, hipStream_t s);
 
 }  // namespace ceff

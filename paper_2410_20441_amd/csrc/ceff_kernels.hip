@@ -1261,6 +1261,190 @@ step_kernel_c(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
   }
 }
 
+// Orthotropic cells (nine constants per cell, axes aligned with the grid;
+// SampleDesc::cst).  One load per block, same z-march and LDS staging as the
+// kernels above.  Normal stresses: the 3x3 normal block of the cell's Voigt
+// matrix; edge stresses: twice the harmonic mean of C44 (yz), C55 (xz) or C66
+// (xy) over the four cells of the edge, times the tensor strain.  A face's step
+// stiffness is the larger over its two cells of max(normal constant, the two
+// shear constants acting on that displacement component) -- for isotropic
+// cells that is K + 4G/3.  MODE 0: iteration; MODE 1: residual into rout.
+constexpr int kOrthoArrays = 15;  // LDS arrays of bx*by (rounded) elements
+
+template <typename T, int MODE, typename R>
+__global__ void __launch_bounds__(512)
+step_kernel_ortho(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
+                  int by, int parity, int first, double* __restrict__ partials, R* const* __restrict__ rout) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const int nt = blockDim.x;
+  T* base = reinterpret_cast<T*>(smem_raw);
+  T* s66 = base;                          // 1/C66 of plane k
+  T* s55[2] = {base + nt, base + 2 * nt};  // 1/C55 of two planes
+  T* s44[2] = {base + 3 * nt, base + 4 * nt};
+  T* sHx = base + 5 * nt;
+  T* sHy = base + 6 * nt;
+  T* sUx = base + 7 * nt;
+  T* sUy = base + 8 * nt;
+  T* sUz = base + 9 * nt;
+  T* sSxx = base + 10 * nt;
+  T* sSyy = base + 11 * nt;
+  T* sSxy = base + 12 * nt;
+  T* sSxz = base + 13 * nt;
+  T* sSyz = base + 14 * nt;
+
+  const int tid = threadIdx.x;
+  const int tx = tid % bx, ty = tid / bx;
+  const int TX = bx - 2, TY = by - 2;
+  const int xm = tid > 0 && tx > 0 ? tid - 1 : tid;
+  const int xp = tx < bx - 1 && tid + 1 < nt ? tid + 1 : tid;
+  const int ym = ty > 0 ? tid - bx : tid;
+  const int yp = ty < by - 1 && tid + bx < nt ? tid + bx : tid;
+  const int xmym = ty > 0 ? xm - bx : xm;
+
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const WorkItem wi = work[w];
+    if (wi.sample < 0) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const SampleDesc<T>& sd = samples[wi.sample];
+    const int l = wi.slot0;
+    if (!((sd.active >> l) & 1u)) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N, plane = nx * ny;
+    const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
+    const T mom = first ? T(0) : sd.mom;
+    const T sfac = first ? sd.sfac_first : sd.sfac;
+    const int64_t gi = (int64_t)wi.tx * TX + tx - 1, gj = (int64_t)wi.ty * TY + ty - 1;
+    const int64_t col = wrap_idx(gi, nx) + nx * wrap_idx(gj, ny);
+    const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
+    const int64_t k0 = (int64_t)wi.kz * sd.kc;
+    const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
+
+    const GLOBAL_AS T* __restrict__ cst = gconst(sd.cst);
+    const GLOBAL_AS T* ucur = gconst(sd.u[parity][l]);
+    GLOBAL_AS T* uold = gmut(sd.u[parity ^ 1][l]);
+    const bool hasf = sd.force[l] != nullptr;
+    const GLOBAL_AS T* frc = gconst(sd.force[l]);
+    const T* E = sd.E[l];
+    auto load9 = [&](int64_t o, T* c) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) c[q] = cst[q * N + o];
+    };
+
+    T cc[9], cn[9];
+    T ux, uy, uz, szz_p = T(0), sxz_c = T(0), syz_c = T(0), Hz_p = T(1);
+    double nsum = 0.0;
+    {
+      const int64_t kw = k0 - 1 < 0 ? k0 - 1 + nz : k0 - 1;
+      const int64_t o = col + plane * kw;
+      ux = ucur[o];
+      uy = ucur[N + o];
+      uz = ucur[2 * N + o];
+      load9(o, cc);
+      s55[0][tid] = recip(cc[7]);
+      s44[0][tid] = recip(cc[6]);
+    }
+
+    for (int64_t k = k0 - 1; k < k1; ++k) {
+      const int P = (int)((k - (k0 - 1)) & 1), Q = P ^ 1;
+      const int64_t kw = k < 0 ? k + nz : k;
+      const int64_t kn = k + 1 >= nz ? k + 1 - nz : k + 1;
+      const int64_t oc = col + plane * kw, on = col + plane * kn;
+      const bool face = k >= k0 && interior;
+      load9(on, cn);
+      const T unx = ucur[on], uny = ucur[N + on], unz = ucur[2 * N + on];
+      T uo0 = T(0), uo1 = T(0), uo2 = T(0), f0 = T(0), f1 = T(0), f2 = T(0);
+      if (face) {
+        if (MODE == 0 && !first) {
+          uo0 = uold[oc];
+          uo1 = uold[N + oc];
+          uo2 = uold[2 * N + oc];
+        }
+        if (hasf) {
+          f0 = frc[oc];
+          f1 = frc[N + oc];
+          f2 = frc[2 * N + oc];
+        }
+      }
+      // cc: this plane's cell; cn: the next plane's
+      const T Hx = tmax(cc[0], tmax(cc[8], cc[7]));
+      const T Hy = tmax(cc[1], tmax(cc[8], cc[6]));
+      const T Hz = tmax(cc[2], tmax(cc[7], cc[6]));
+      s66[tid] = recip(cc[8]);
+      s55[Q][tid] = recip(cn[7]);
+      s44[Q][tid] = recip(cn[6]);
+      sHx[tid] = Hx;
+      sHy[tid] = Hy;
+      sUx[tid] = ux;
+      sUy[tid] = uy;
+      sUz[tid] = unz;
+      __syncthreads();
+      const T C66e2 = T(8) * recip(s66[xmym] + s66[ym] + s66[xm] + s66[tid]);
+      const T C55e2 = T(8) * recip(s55[P][xm] + s55[P][tid] + s55[Q][xm] + s55[Q][tid]);
+      const T C44e2 = T(8) * recip(s44[P][ym] + s44[P][tid] + s44[Q][ym] + s44[Q][tid]);
+      const T sfx = sfac * recip(tmax(sHx[xm], Hx));
+      const T sfy = sfac * recip(tmax(sHy[ym], Hy));
+      const T sfz = sfac * recip(tmax(Hz_p, Hz));
+      const T exx = E[0] + (sUx[xp] - ux) * rhx;
+      const T eyy = E[1] + (sUy[yp] - uy) * rhy;
+      const T ezz = E[2] + (unz - uz) * rhz;
+      const T sxx = cc[0] * exx + cc[5] * eyy + cc[4] * ezz;
+      const T syy = cc[5] * exx + cc[1] * eyy + cc[3] * ezz;
+      const T szz = cc[4] * exx + cc[3] * eyy + cc[2] * ezz;
+      const T sxy = C66e2 * (E[5] + T(0.5) * ((ux - sUx[ym]) * rhy + (uy - sUy[xm]) * rhx));
+      const T sxz_n = C55e2 * (E[4] + T(0.5) * ((unx - ux) * rhz + (unz - sUz[xm]) * rhx));
+      const T syz_n = C44e2 * (E[3] + T(0.5) * ((uny - uy) * rhz + (unz - sUz[ym]) * rhy));
+      sSxx[tid] = sxx;
+      sSyy[tid] = syy;
+      sSxy[tid] = sxy;
+      sSxz[tid] = sxz_c;
+      sSyz[tid] = syz_c;
+      __syncthreads();
+      if (face) {
+        T rx = (sxx - sSxx[xm]) * rhx + (sSxy[yp] - sxy) * rhy + (sxz_n - sxz_c) * rhz;
+        T ry = (sSxy[xp] - sxy) * rhx + (syy - sSyy[ym]) * rhy + (syz_n - syz_c) * rhz;
+        T rz = (sSxz[xp] - sxz_c) * rhx + (sSyz[yp] - syz_c) * rhy + (szz - szz_p) * rhz;
+        rx += f0;
+        ry += f1;
+        rz += f2;
+        if (partials != nullptr) nsum += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
+        if (MODE == 0) {
+          uold[oc] = ux + mom * (ux - uo0) + sfx * rx;
+          uold[N + oc] = uy + mom * (uy - uo1) + sfy * ry;
+          uold[2 * N + oc] = uz + mom * (uz - uo2) + sfz * rz;
+        } else {
+          GLOBAL_AS R* ro = rout != nullptr ? gmut(rout[l]) : nullptr;
+          if (ro != nullptr) {
+            ro[oc] = (R)rx;
+            ro[N + oc] = (R)ry;
+            ro[2 * N + oc] = (R)rz;
+          }
+        }
+      }
+      szz_p = szz;
+      sxz_c = sxz_n;
+      syz_c = syz_n;
+      Hz_p = Hz;
+      ux = unx;
+      uy = uny;
+      uz = unz;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) cc[q] = cn[q];
+    }
+
+    if (partials != nullptr) {
+      const double s = block_sum(nsum, red);
+      if (tid == 0)
+        for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = q == l ? s : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void finalize_norms_kernel(const int* __restrict__ ranges, const double* __restrict__ partials,
                                       double* __restrict__ out) {
   __shared__ double red[16];
@@ -1310,6 +1494,69 @@ __global__ void average_partials_kernel(int64_t nx, int64_t ny, int64_t nz, doub
     const double s = block_sum(acc[q], red);
     if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * 6 + q] = s;
   }
+}
+
+// FP64 stress averages for orthotropic cells (c: 9N constants).
+__global__ void average_partials_ortho_kernel(int64_t nx, int64_t ny, int64_t nz, double rhx, double rhy,
+                                              double rhz, const double* __restrict__ cst, double E0, double E1,
+                                              double E2, double E3, double E4, double E5,
+                                              const double* __restrict__ u, double* __restrict__ partials) {
+  __shared__ double red[16];
+  const int64_t N = nx * ny * nz;
+  const double* ux = u;
+  const double* uy = u + N;
+  const double* uz = u + 2 * N;
+  const double* C44 = cst + 6 * N;
+  const double* C55 = cst + 7 * N;
+  const double* C66 = cst + 8 * N;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    const int64_t ip = i + 1 == nx ? 0 : i + 1, im = i == 0 ? nx - 1 : i - 1;
+    const int64_t jp = j + 1 == ny ? 0 : j + 1, jm = j == 0 ? ny - 1 : j - 1;
+    const int64_t kp = k + 1 == nz ? 0 : k + 1, km = k == 0 ? nz - 1 : k - 1;
+    auto at = [&](int64_t a, int64_t b, int64_t d) { return a + nx * (b + ny * d); };
+    const double exx = E0 + (ux[at(ip, j, k)] - ux[c]) * rhx;
+    const double eyy = E1 + (uy[at(i, jp, k)] - uy[c]) * rhy;
+    const double ezz = E2 + (uz[at(i, j, kp)] - uz[c]) * rhz;
+    const double C11 = cst[c], C22 = cst[N + c], C33 = cst[2 * N + c];
+    const double C23 = cst[3 * N + c], C13 = cst[4 * N + c], C12 = cst[5 * N + c];
+    acc[0] += C11 * exx + C12 * eyy + C13 * ezz;
+    acc[1] += C12 * exx + C22 * eyy + C23 * ezz;
+    acc[2] += C13 * exx + C23 * eyy + C33 * ezz;
+    const double cyz = 8.0 / (1.0 / C44[c] + 1.0 / C44[at(i, jm, k)] + 1.0 / C44[at(i, j, km)] + 1.0 / C44[at(i, jm, km)]);
+    const double cxz = 8.0 / (1.0 / C55[c] + 1.0 / C55[at(im, j, k)] + 1.0 / C55[at(i, j, km)] + 1.0 / C55[at(im, j, km)]);
+    const double cxy = 8.0 / (1.0 / C66[c] + 1.0 / C66[at(im, j, k)] + 1.0 / C66[at(i, jm, k)] + 1.0 / C66[at(im, jm, k)]);
+    acc[3] += cyz * (E3 + 0.5 * ((uy[c] - uy[at(i, j, km)]) * rhz + (uz[c] - uz[at(i, jm, k)]) * rhy));
+    acc[4] += cxz * (E4 + 0.5 * ((ux[c] - ux[at(i, j, km)]) * rhz + (uz[c] - uz[at(im, j, k)]) * rhx));
+    acc[5] += cxy * (E5 + 0.5 * ((ux[c] - ux[at(i, jm, k)]) * rhy + (uy[c] - uy[at(im, j, k)]) * rhx));
+  }
+  for (int q = 0; q < 6; ++q) {
+    const double s = block_sum(acc[q], red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * 6 + q] = s;
+  }
+}
+
+// Orthotropic constants checks: per-block flag 1 when some cell's diagonal
+// constant is not finite and > 0 or its 3x3 normal block is not positive
+// definite (leading minors).
+template <typename T>
+__global__ void check_ortho_kernel(const T* __restrict__ c, int64_t n, int* __restrict__ bad) {
+  __shared__ double red[16];
+  double b = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const double C11 = c[t], C22 = c[n + t], C33 = c[2 * n + t], C23 = c[3 * n + t], C13 = c[4 * n + t],
+                 C12 = c[5 * n + t], C44 = c[6 * n + t], C55 = c[7 * n + t], C66 = c[8 * n + t];
+    bool ok = isfinite(C11) && isfinite(C22) && isfinite(C33) && isfinite(C23) && isfinite(C13) && isfinite(C12) &&
+              isfinite(C44) && isfinite(C55) && isfinite(C66);
+    ok = ok && C11 > 0.0 && C22 > 0.0 && C33 > 0.0 && C44 > 0.0 && C55 > 0.0 && C66 > 0.0;
+    const double m2 = C11 * C22 - C12 * C12;
+    const double m3 = C11 * (C22 * C33 - C23 * C23) - C12 * (C12 * C33 - C23 * C13) + C13 * (C12 * C23 - C22 * C13);
+    ok = ok && m2 > 0.0 && m3 > 0.0;
+    if (!ok) b = 1.0;
+  }
+  b = block_sum(b, red);
+  if (threadIdx.x == 0) bad[blockIdx.x] = b > 0.0 ? 1 : 0;
 }
 
 __global__ void average_finalize_kernel(const double* __restrict__ partials, int nblocks, double* __restrict__ out6) {
@@ -1513,6 +1760,28 @@ hipError_t launch_residual(const SampleDesc<T>* d_samples, const WorkItem* d_wor
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_step_ortho(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
+                             int parity, int first, double* partials, hipStream_t s) {
+  const int nt = ((ts.bx * ts.by + 63) / 64) * 64;
+  hipLaunchKernelGGL((step_kernel_ortho<T, 0, T>), dim3(nwork), dim3(nt), (size_t)kOrthoArrays * nt * sizeof(T), s,
+                     d_samples, d_work, nwork, ts.bx, ts.by, parity, first, partials, (T* const*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T, typename R>
+hipError_t launch_residual_ortho(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
+                                 int parity, R* const* rout, double* partials, hipStream_t s) {
+  const int nt = ((ts.bx * ts.by + 63) / 64) * 64;
+  hipLaunchKernelGGL((step_kernel_ortho<T, 1, R>), dim3(nwork), dim3(nt), (size_t)kOrthoArrays * nt * sizeof(T), s,
+                     d_samples, d_work, nwork, ts.bx, ts.by, parity, 0, partials, rout);
+  return hipGetLastError();
+}
+
+size_t ortho_lds_bytes(TileShape ts, size_t elem) {
+  return (size_t)kOrthoArrays * (((ts.bx * ts.by + 63) / 64) * 64) * elem;
+}
+
 hipError_t launch_finalize_norms(const int* d_ranges, int nsamples, const double* partials, double* out,
                                  hipStream_t s) {
   hipLaunchKernelGGL(finalize_norms_kernel, dim3(nsamples * kMaxLoads), dim3(256), 0, s, d_ranges, partials, out);
@@ -1526,6 +1795,19 @@ hipError_t launch_average_stress(int64_t nx, int64_t ny, int64_t nz, const doubl
   if (nb > nblocks_cap) nb = nblocks_cap;
   hipLaunchKernelGGL(average_partials_kernel, dim3(nb), dim3(256), 0, s, nx, ny, nz, 1.0 / h[0], 1.0 / h[1],
                      1.0 / h[2], K, G, E[0], E[1], E[2], E[3], E[4], E[5], u, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(average_finalize_kernel, dim3(6), dim3(256), 0, s, partials, nb, out6);
+  return hipGetLastError();
+}
+
+hipError_t launch_average_stress_ortho(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* cst,
+                                       const double E[6], const double* u, double* partials, int nblocks_cap,
+                                       double* out6, hipStream_t s) {
+  int nb = grid_for(nx * ny * nz, 256);
+  if (nb > nblocks_cap) nb = nblocks_cap;
+  hipLaunchKernelGGL(average_partials_ortho_kernel, dim3(nb), dim3(256), 0, s, nx, ny, nz, 1.0 / h[0], 1.0 / h[1],
+                     1.0 / h[2], cst, E[0], E[1], E[2], E[3], E[4], E[5], u, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(average_finalize_kernel, dim3(6), dim3(256), 0, s, partials, nb, out6);
@@ -1578,7 +1860,24 @@ hipError_t launch_check_moduli(const T* K, const T* G, int64_t n, int* bad, int*
   return hipGetLastError();
 }
 
+hipError_t launch_check_ortho(const double* c, int64_t n, int* bad, int* nblocks, hipStream_t s) {
+  const int g = grid_for(n);
+  *nblocks = g;
+  hipLaunchKernelGGL((check_ortho_kernel<double>), dim3(g), dim3(256), 0, s, c, n, bad);
+  return hipGetLastError();
+}
+
 // explicit instantiations
+template hipError_t launch_step_ortho<float>(const SampleDesc<float>*, const WorkItem*, int, TileShape, int, int,
+                                             double*, hipStream_t);
+template hipError_t launch_step_ortho<double>(const SampleDesc<double>*, const WorkItem*, int, TileShape, int, int,
+                                              double*, hipStream_t);
+template hipError_t launch_residual_ortho<double, float>(const SampleDesc<double>*, const WorkItem*, int, TileShape,
+                                                         int, float* const*, double*, hipStream_t);
+template hipError_t launch_residual_ortho<double, double>(const SampleDesc<double>*, const WorkItem*, int, TileShape,
+                                                          int, double* const*, double*, hipStream_t);
+template hipError_t launch_residual_ortho<float, float>(const SampleDesc<float>*, const WorkItem*, int, TileShape,
+                                                        int, float* const*, double*, hipStream_t);
 #define CEFF_INST_STEP(T, L)                                                                                       \
   template hipError_t launch_step<T, L>(const SampleDesc<T>*, const WorkItem*, int, TileShape, int, int, double*, \
                                         hipStream_t);

@@ -298,6 +298,26 @@ def random_fields(shape, seed, lo=(1.0, 0.5), hi=(100.0, 50.0)):
 
 # ---- the five workloads -------------------------------------------------------
 
+def random_orthotropic(shape, seed, normal=(20.0, 120.0), shear=(5.0, 50.0), coupling=(-0.3, 0.6)):
+    """Per-cell orthotropic constants (9, nz, ny, nx): C11 C22 C33 C23 C13 C12 C44 C55 C66.
+    Normal constants uniform in `normal`, shear constants uniform in `shear`, each
+    coupling C_ij = t sqrt(C_ii C_jj) with t uniform in `coupling`; cells whose normal
+    block is not positive definite (leading minors) are redrawn by the caller's seed
+    change, so the generator raises instead of returning them."""
+    rng = SplitMix64(seed)
+    n = int(np.prod(shape))
+    u = lambda lo, hi: lo + (hi - lo) * rng.uniform_array(n).reshape(shape)
+    C11, C22, C33 = u(*normal), u(*normal), u(*normal)
+    C23 = u(*coupling) * np.sqrt(C22 * C33)
+    C13 = u(*coupling) * np.sqrt(C11 * C33)
+    C12 = u(*coupling) * np.sqrt(C11 * C22)
+    m2 = C11 * C22 - C12 ** 2
+    m3 = C11 * (C22 * C33 - C23 ** 2) - C12 * (C12 * C33 - C23 * C13) + C13 * (C12 * C23 - C22 * C13)
+    if not (np.all(m2 > 0) and np.all(m3 > 0)):
+        raise ValueError("a normal block is not positive definite; use another seed")
+    return np.stack([C11, C22, C33, C23, C13, C12, u(*shear), u(*shear), u(*shear)])
+
+
 def workload_sphere32() -> Microstructure:
     """32^3, matrix (70, 32), one centred fluid sphere of radius 8."""
     return centred_sphere(32, 8.0)

@@ -18,19 +18,9 @@ def rel(A, B):
 
 
 def random_ortho(shape, seed):
-    """Positive definite orthotropic cells: random principal stiffnesses and
-    couplings below the geometric mean of the two normal constants."""
-    rng = synth.SplitMix64(seed)
-    n = int(np.prod(shape))
-    u = lambda lo, hi: lo + (hi - lo) * rng.uniform_array(n).reshape(shape)
-    C11, C22, C33 = u(20, 120), u(20, 120), u(20, 120)
-    C23 = u(-0.3, 0.6) * np.sqrt(C22 * C33)
-    C13 = u(-0.3, 0.6) * np.sqrt(C11 * C33)
-    C12 = u(-0.3, 0.6) * np.sqrt(C11 * C22)
-    C9 = np.stack([C11, C22, C33, C23, C13, C12, u(5, 50), u(5, 50), u(5, 50)])
-    for t in range(n):
-        c = C9.reshape(9, -1)[:, t]
-        assert np.all(np.linalg.eigvalsh(oracle.voigt_of_c9(c)) > 0)
+    C9 = synth.random_orthotropic(shape, seed)
+    for t in range(int(np.prod(shape))):
+        assert np.all(np.linalg.eigvalsh(oracle.voigt_of_c9(C9.reshape(9, -1)[:, t])) > 0)
     return C9
 
 
