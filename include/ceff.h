@@ -112,7 +112,8 @@ void ceff_destroy(ceff_ctx* ctx);
 /* Message of the last failure (context-owned; valid until the next call). */
 const char* ceff_last_error(const ceff_ctx* ctx);
 
-/* Grid dimensions (each >= 2) and voxel spacings (> 0).  Clears material and kept fields. */
+/* Grid dimensions (each in [2, 2^20], with nx*ny <= 2^28) and voxel spacings
+ * (> 0).  Clears material and kept fields. */
 ceff_status ceff_set_grid(ceff_ctx* ctx, int64_t nx, int64_t ny, int64_t nz, double hx, double hy, double hz);
 
 /* Per-voxel isotropic moduli K(x), G(x) (paper: each voxel carries the bulk

@@ -139,7 +139,8 @@ ceff_status validate_opts(ceff_ctx* c, const ceff_solve_opts& o) {
 ceff_status validate_grid(ceff_ctx* c, int64_t nx, int64_t ny, int64_t nz, const double* h) {
   if (nx < 2 || ny < 2 || nz < 2) return fail(c, CEFF_EINVAL, "grid dimensions must be >= 2");
   if (nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20)) return fail(c, CEFF_EINVAL, "grid dimension too large");
-  if (nx * ny > (int64_t)1 << 40) return fail(c, CEFF_EINVAL, "grid too large");
+  // the iteration kernels address a column within a z-plane with a 32-bit byte offset
+  if (nx * ny * (int64_t)sizeof(double) > ((int64_t)1 << 31)) return fail(c, CEFF_EINVAL, "z-plane too large");
   for (int d = 0; d < 3; ++d)
     if (!(h[d] > 0.0) || !std::isfinite(h[d])) return fail(c, CEFF_EINVAL, "spacings must be finite and > 0");
   return CEFF_OK;

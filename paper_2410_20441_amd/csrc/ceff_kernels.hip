@@ -99,11 +99,12 @@ struct MinWaves {
 };
 
 // Per-cell coefficients of the isotropic Hooke law on the staggered grid:
-// lambda = K - 2G/3 and 2G for the normal stresses, H = K + 4G/3 for the face
-// step, and 1/G for the harmonic edge moduli.
+// lambda = K - 2G/3 and 2G for the normal stresses, 1/H with H = K + 4G/3 for
+// the face step (the step of a face takes the smaller 1/H of its two cells,
+// i.e. 1/max H), and 1/G for the harmonic edge moduli.
 template <typename T>
 struct alignas(16) CellCoef {
-  T lam, twoG, H, iG;
+  T lam, twoG, iH, iG;
 };
 
 template <typename T>
@@ -111,10 +112,49 @@ __device__ __forceinline__ CellCoef<T> cell_coef(T K, T G) {
   CellCoef<T> c;
   c.lam = K - T(2.0 / 3.0) * G;
   c.twoG = T(2) * G;
-  c.H = K + T(4.0 / 3.0) * G;
+  c.iH = recip(K + T(4.0 / 3.0) * G);
   c.iG = recip(G);
   return c;
 }
+
+// Minimum of two positive finite values (one v_min instruction).
+__device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
+
+// Raw buffer view of a device array (at most 4 GiB - 1 bytes).  Accesses take
+// a per-thread 32-bit byte offset (here: the column within a z-plane, fixed for
+// the whole march) plus a uniform 32-bit byte offset (component and plane), and
+// the descriptor sits in scalar registers, so no per-access address arithmetic
+// runs on the vector ALU.  Reads outside the range return 0.
+struct BufView {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ BufView() {}
+  __device__ __forceinline__ BufView(const void* p, uint32_t bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
+  __device__ __forceinline__ float ldf(uint32_t v, uint32_t s) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, 0));
+  }
+  __device__ __forceinline__ double ldd(uint32_t v, uint32_t s) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, 0));
+  }
+  __device__ __forceinline__ uint32_t ldb(uint32_t v, uint32_t s) const {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)v, (int)s, 0);
+  }
+  __device__ __forceinline__ void st(uint32_t v, uint32_t s, float x) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, (int)v, (int)s, 0);
+  }
+  __device__ __forceinline__ void st(uint32_t v, uint32_t s, double x) const {
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, (int)v, (int)s, 0);
+  }
+  template <typename T>
+  __device__ __forceinline__ T ld(uint32_t v, uint32_t s) const {
+    if constexpr (sizeof(T) == 4)
+      return ldf(v, s);
+    else
+      return ldd(v, s);
+  }
+};
 
 // Where the iteration kernel gets a cell's coefficients.  load() issues the
 // global read (so it can be requested a plane ahead), coef() turns what it
@@ -122,27 +162,52 @@ __device__ __forceinline__ CellCoef<T> cell_coef(T K, T G) {
 // cell).  PAL = true: from the 1-byte phase id and a per-phase coefficient table
 // staged in LDS; the table entries come from the same cell_coef on the same
 // values, so both give identical results.
-template <typename T, bool PAL>
+// BUF: buffer accesses (see BufView); otherwise pointer plus 64-bit index.
+template <typename T, bool PAL, bool BUF>
 struct Moduli {
   struct Raw {
     T K, G;
   };
+  BufView Kb, Gb;
   const GLOBAL_AS T* Kf;
   const GLOBAL_AS T* Gf;
-  __device__ Moduli(const SampleDesc<T>& sd, const CellCoef<T>*) : Kf(gconst(sd.K)), Gf(gconst(sd.G)) {}
-  __device__ __forceinline__ Raw load(int64_t o) const { return Raw{Kf[o], Gf[o]}; }
+  __device__ Moduli(const SampleDesc<T>& sd, const CellCoef<T>*) : Kf(gconst(sd.K)), Gf(gconst(sd.G)) {
+    if constexpr (BUF) {
+      Kb = BufView(sd.K, (uint32_t)(sd.N * sizeof(T)));
+      Gb = BufView(sd.G, (uint32_t)(sd.N * sizeof(T)));
+    }
+  }
+  // cell of column col (byte offset colb = col * sizeof(T)) in the plane starting at element pk
+  __device__ __forceinline__ Raw load(int64_t pk, int64_t o, uint32_t col, uint32_t colb) const {
+    (void)col;
+    if constexpr (BUF) {
+      const uint32_t so = (uint32_t)(pk * (int64_t)sizeof(T));
+      return Raw{Kb.template ld<T>(colb, so), Gb.template ld<T>(colb, so)};
+    } else {
+      return Raw{Kf[o], Gf[o]};
+    }
+  }
   __device__ __forceinline__ CellCoef<T> coef(Raw r) const { return cell_coef(r.K, r.G); }
 };
 
-template <typename T>
-struct Moduli<T, true> {
+template <typename T, bool BUF>
+struct Moduli<T, true, BUF> {
   struct Raw {
     uint32_t p;
   };
+  BufView pb;
   const GLOBAL_AS uint8_t* ph;
   const CellCoef<T>* tab;
-  __device__ Moduli(const SampleDesc<T>& sd, const CellCoef<T>* t) : ph(gconst(sd.phase)), tab(t) {}
-  __device__ __forceinline__ Raw load(int64_t o) const { return Raw{ph[o]}; }
+  __device__ Moduli(const SampleDesc<T>& sd, const CellCoef<T>* t) : ph(gconst(sd.phase)), tab(t) {
+    if constexpr (BUF) pb = BufView(sd.phase, (uint32_t)sd.N);
+  }
+  __device__ __forceinline__ Raw load(int64_t pk, int64_t o, uint32_t col, uint32_t colb) const {
+    (void)colb;
+    if constexpr (BUF)
+      return Raw{pb.ldb(col, (uint32_t)pk)};
+    else
+      return Raw{ph[o]};
+  }
   __device__ __forceinline__ CellCoef<T> coef(Raw r) const { return tab[r.p]; }
 };
 
@@ -659,73 +724,120 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
     const int64_t gi = (int64_t)wi.tx * TX + tx - 1, gj = (int64_t)wi.ty * TY + ty - 1;
     const int64_t col = wrap_idx(gi, nx) + nx * wrap_idx(gj, ny);
     const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
-    const int64_t k0 = (int64_t)wi.kz * sd.kc;
-    const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
+    // z indices in 32 bits (nz <= 2^20) so that the march's bookkeeping is scalar
+    const int nz32 = (int)nz;
+    const int k0 = wi.kz * sd.kc;
+    const int k1 = k0 + sd.kc < nz32 ? k0 + sd.kc : nz32;
 
-    const Moduli<T, PAL> mod(sd, tab);
-    const GLOBAL_AS T* ucur[L];
-    GLOBAL_AS T* uold[L];
-    const GLOBAL_AS T* frc[L];
+    // One load per block: every access is a buffer access (descriptor and
+    // component/plane offset uniform, the column's 32-bit byte offset per
+    // thread; the host keeps each 3N-element field below 4 GiB for this).  With
+    // several loads the descriptors would crowd the scalar registers, so those
+    // use pointers and 64-bit element indices.
+    constexpr bool BUF = L == 1;
+    const Moduli<T, PAL, BUF> mod(sd, tab);
+    const uint32_t col32 = (uint32_t)col, colb = (uint32_t)col * (uint32_t)sizeof(T);
+    const uint32_t fb = (uint32_t)(3 * N * (int64_t)sizeof(T));
+    const int64_t cN = N * (int64_t)sizeof(T);  // byte stride between components
+    BufView ucur[L], uold[L], frc[L];
+    const GLOBAL_AS T* pcur[L];
+    GLOBAL_AS T* pold[L];
+    const GLOBAL_AS T* pfrc[L];
     bool hasf[L];
     T E[L][6];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-      ucur[l] = gconst(sd.u[parity][s0 + l]);
-      uold[l] = gmut(sd.u[parity ^ 1][s0 + l]);
       hasf[l] = sd.force[s0 + l] != nullptr;
-      frc[l] = gconst(sd.force[s0 + l]);
+      if constexpr (BUF) {
+        ucur[l] = BufView(sd.u[parity][s0 + l], fb);
+        uold[l] = BufView(sd.u[parity ^ 1][s0 + l], fb);
+        frc[l] = BufView(sd.force[s0 + l], hasf[l] ? fb : 0u);
+      } else {
+        pcur[l] = gconst(sd.u[parity][s0 + l]);
+        pold[l] = gmut(sd.u[parity ^ 1][s0 + l]);
+        pfrc[l] = gconst(sd.force[s0 + l]);
+      }
 #pragma unroll
       for (int q = 0; q < 6; ++q) E[l][q] = sd.E[s0 + l][q];
     }
+    // component c of load l's fields at plane element offset pk; o = col + pk
+    // is the cell's element index (used by the pointer form)
+    auto ldu = [&](int l, int c, int64_t pk, int64_t o) -> T {
+      if constexpr (BUF)
+        return ucur[l].template ld<T>(colb, (uint32_t)(c * cN + pk * (int64_t)sizeof(T)));
+      else
+        return pcur[l][c * N + o];
+    };
+    auto ldo_ = [&](int l, int c, int64_t pk, int64_t o) -> T {
+      if constexpr (BUF)
+        return uold[l].template ld<T>(colb, (uint32_t)(c * cN + pk * (int64_t)sizeof(T)));
+      else
+        return pold[l][c * N + o];
+    };
+    auto ldf = [&](int l, int c, int64_t pk, int64_t o) -> T {
+      if constexpr (BUF)
+        return frc[l].template ld<T>(colb, (uint32_t)(c * cN + pk * (int64_t)sizeof(T)));
+      else
+        return pfrc[l][c * N + o];
+    };
+    auto sto_ = [&](int l, int c, int64_t pk, int64_t o, T v) {
+      if constexpr (BUF)
+        uold[l].st(colb, (uint32_t)(c * cN + pk * (int64_t)sizeof(T)), v);
+      else
+        pold[l][c * N + o] = v;
+    };
 
-    T Ux[2][L], Uy[2][L], Uz[2][L], Szz[2][L], Sxz[2][L], Syz[2][L], Hh[2];
+    T Ux[2][L], Uy[2][L], Uz[2][L], Szz[2][L], Sxz[2][L], Syz[2][L], iHh[2];
     CellCoef<T> Cc[2];
     double nsum[L];
     {
-      const int64_t kw = k0 - 1 < 0 ? k0 - 1 + nz : k0 - 1;
-      const int64_t o = col + plane * kw;
+      const int kw = k0 - 1 < 0 ? k0 - 1 + nz32 : k0 - 1;
+      const int64_t po = plane * kw;
 #pragma unroll
       for (int l = 0; l < L; ++l) {
         Ux[0][l] = Uy[0][l] = Uz[0][l] = T(0);
         if (act & (1u << l)) {
-          Ux[0][l] = ucur[l][o];
-          Uy[0][l] = ucur[l][N + o];
-          Uz[0][l] = ucur[l][2 * N + o];
+          Ux[0][l] = ldu(l, 0, po, col + po);
+          Uy[0][l] = ldu(l, 1, po, col + po);
+          Uz[0][l] = ldu(l, 2, po, col + po);
         }
         Szz[1][l] = Sxz[1][l] = Syz[1][l] = T(0);
         nsum[l] = 0.0;
       }
-      Cc[0] = mod.coef(mod.load(o));
-      Hh[1] = T(1);
+      Cc[0] = mod.coef(mod.load(po, col + po, col32, colb));
+      iHh[1] = T(1);
       sG[0][tid] = Cc[0].iG;
     }
 
-    auto plane_step = [&](int64_t k, auto Pc) {
+    // NORM: accumulate the squared residual (check iterations only)
+    auto plane_step = [&](int k, auto Pc, auto Nc) {
       constexpr int P = decltype(Pc)::value;
       constexpr int Q = 1 - P;
-      const int64_t kw = k < 0 ? k + nz : k;
-      const int64_t kn = k + 1 >= nz ? k + 1 - nz : k + 1;
-      const int64_t oc = col + plane * kw, on = col + plane * kn;
+      constexpr bool NORM = decltype(Nc)::value;
+      const int kw = k < 0 ? k + nz32 : k;
+      const int kn = k + 1 >= nz32 ? k + 1 - nz32 : k + 1;
+      const int64_t pc = plane * kw, pn = plane * kn;
+      const int64_t oc = col + pc, on = col + pn;
       const bool face = k >= k0 && interior;
-      const auto mr = mod.load(on);
+      const auto mr = mod.load(pn, on, col32, colb);
       T uo0[L], uo1[L], uo2[L], f0[L], f1[L], f2[L];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
         Ux[Q][l] = Uy[Q][l] = Uz[Q][l] = uo0[l] = uo1[l] = uo2[l] = f0[l] = f1[l] = f2[l] = T(0);
         if (act & (1u << l)) {
-          Ux[Q][l] = ucur[l][on];
-          Uy[Q][l] = ucur[l][N + on];
-          Uz[Q][l] = ucur[l][2 * N + on];
+          Ux[Q][l] = ldu(l, 0, pn, on);
+          Uy[Q][l] = ldu(l, 1, pn, on);
+          Uz[Q][l] = ldu(l, 2, pn, on);
           if (face) {
             if (!first) {
-              uo0[l] = uold[l][oc];
-              uo1[l] = uold[l][N + oc];
-              uo2[l] = uold[l][2 * N + oc];
+              uo0[l] = ldo_(l, 0, pc, oc);
+              uo1[l] = ldo_(l, 1, pc, oc);
+              uo2[l] = ldo_(l, 2, pc, oc);
             }
             if (hasf[l]) {
-              f0[l] = frc[l][oc];
-              f1[l] = frc[l][N + oc];
-              f2[l] = frc[l][2 * N + oc];
+              f0[l] = ldf(l, 0, pc, oc);
+              f1[l] = ldf(l, 1, pc, oc);
+              f2[l] = ldf(l, 2, pc, oc);
             }
           }
         }
@@ -734,8 +846,8 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       T* gn = sG[Q];
       Cc[Q] = mod.coef(mr);
       gn[tid] = Cc[Q].iG;
-      Hh[P] = Cc[P].H;
-      sH[tid] = Hh[P];
+      iHh[P] = Cc[P].iH;
+      sH[tid] = iHh[P];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
         S(l, 0)[tid] = Ux[P][l];
@@ -750,9 +862,9 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       const T G2xy = T(8) * recip(gk[xmym] + iky + ikx + ik);
       const T G2xz = T(8) * recip(ikx + ik + inx + in);
       const T G2yz = T(8) * recip(iky + ik + iny + in);
-      const T sfx = sfac * recip(tmax(sH[xm], Hh[P]));
-      const T sfy = sfac * recip(tmax(sH[ym], Hh[P]));
-      const T sfz = sfac * recip(tmax(Hh[Q], Hh[P]));
+      const T sfx = sfac * tmin(sH[xm], iHh[P]);
+      const T sfy = sfac * tmin(sH[ym], iHh[P]);
+      const T sfz = sfac * tmin(iHh[Q], iHh[P]);
       T sxx[L], syy[L], szz[L], sxy[L], sxz_n[L], syz_n[L];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
@@ -793,12 +905,12 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
           rx += f0[l];
           ry += f1[l];
           rz += f2[l];
-          if (partials != nullptr)
+          if (NORM && (L == 1 || partials != nullptr))
             nsum[l] += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
           const T ux = Ux[P][l], uy = Uy[P][l], uz = Uz[P][l];
-          uold[l][oc] = ux + mom * (ux - uo0[l]) + sfx * rx;
-          uold[l][N + oc] = uy + mom * (uy - uo1[l]) + sfy * ry;
-          uold[l][2 * N + oc] = uz + mom * (uz - uo2[l]) + sfz * rz;
+          sto_(l, 0, pc, oc, ux + mom * (ux - uo0[l]) + sfx * rx);
+          sto_(l, 1, pc, oc, uy + mom * (uy - uo1[l]) + sfy * ry);
+          sto_(l, 2, pc, oc, uz + mom * (uz - uo2[l]) + sfz * rz);
         }
         Szz[P][l] = szz[l];
         Sxz[P][l] = sxz_n[l];
@@ -806,9 +918,22 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       }
     };
 
-    for (int64_t k = k0 - 1; k < k1; k += 2) {
-      plane_step(k, std::integral_constant<int, 0>{});
-      if (k + 1 < k1) plane_step(k + 1, std::integral_constant<int, 1>{});
+    auto march = [&](auto Nc) {
+      for (int k = k0 - 1; k < k1; k += 2) {
+        plane_step(k, std::integral_constant<int, 0>{}, Nc);
+        if (k + 1 < k1) plane_step(k + 1, std::integral_constant<int, 1>{}, Nc);
+      }
+    };
+    // one load per block: a march without the norm for the plain iterations;
+    // with several loads a second copy of the march costs more registers than
+    // the norm's instructions, so the norm is guarded at run time
+    if constexpr (L > 1) {
+      march(std::true_type{});
+    } else {
+      if (partials != nullptr)
+        march(std::true_type{});
+      else
+        march(std::false_type{});
     }
 
     if (partials != nullptr) {

@@ -3,9 +3,10 @@
 tests/golden/spheres191_oracle.json holds oracle C* columns of the 191^3
 sphere pack (Jacobi-PCG to rtol 1e-11), written by
 tests/golden/make_spheres191_golden.py, which calls only the oracle.  The GPU
-solves the same image in the benchmark's configuration (mixed precision, six
-loads fused, rtol 1e-8) and in the plain FP64 one-load-at-a-time
-configuration."""
+solves the same image in the benchmark's configuration (mixed precision, the library's own choice of
+load fusion -- one load after another at this size -- with the moduli read
+from the phase image, rtol 1e-8), with the six loads forced into one launch,
+and in the plain FP64 one-load-at-a-time configuration."""
 import hashlib
 import json
 import os
@@ -30,7 +31,7 @@ def golden():
     return m, g
 
 
-@pytest.mark.parametrize("precision,fuse", [("mixed", True), ("fp64", False)])
+@pytest.mark.parametrize("precision,fuse", [("mixed", "auto"), ("mixed", True), ("fp64", False)])
 def test_spheres191_matches_oracle_columns(golden, precision, fuse):
     p = need_gpu()
     m, g = golden
@@ -39,6 +40,8 @@ def test_spheres191_matches_oracle_columns(golden, precision, fuse):
         c.set_phases(m.phase, m.K_tab, m.G_tab)
         C, info = c.solve(precision=precision, fuse_loads=fuse, rtol=1e-8)
     assert info["status"] == 0
+    if fuse == "auto":
+        assert info["stats"]["fused_loads"] == 0 and info["stats"]["phase_moduli"] == 1
     cols = {int(J): np.array(v["C_column"]) for J, v in g["columns"].items()}
     scale = max(np.abs(v).max() for v in cols.values())
     for J, col in cols.items():
