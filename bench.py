@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the iteration kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_hbm_counters.md),
 # valid only for the kernel source they were taken on.
-MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "7734964c7216c147", "bytes_per_launch": 3.166449e+08,
+MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "cbcbc94ecbd5bdb2", "bytes_per_launch": 3.154786e+08,
                     # (loads per block, kernel variant, loads fused, moduli from the phase image)
                     "launch_signature": (1, 3, 0, 1),
                     "launch": "step_kernel_b<float,1,PAL>, mean over all launches of a full solve"}

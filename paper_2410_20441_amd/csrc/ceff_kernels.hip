@@ -101,10 +101,12 @@ struct MinWaves {
 // Per-cell coefficients of the isotropic Hooke law on the staggered grid:
 // lambda = K - 2G/3 and 2G for the normal stresses, 1/H with H = K + 4G/3 for
 // the face step (the step of a face takes the smaller 1/H of its two cells,
-// i.e. 1/max H), and 1/G for the harmonic edge moduli.
+// i.e. 1/max H), and 1/(8G) for the harmonic edge moduli (twice the harmonic
+// mean of four cells is 1 / (sum of their 1/(8G)); the factor is a power of two,
+// so this is exactly 8 / (sum of 1/G)).
 template <typename T>
 struct alignas(16) CellCoef {
-  T lam, twoG, iH, iG;
+  T lam, twoG, iH, iG8;
 };
 
 template <typename T>
@@ -113,12 +115,16 @@ __device__ __forceinline__ CellCoef<T> cell_coef(T K, T G) {
   c.lam = K - T(2.0 / 3.0) * G;
   c.twoG = T(2) * G;
   c.iH = recip(K + T(4.0 / 3.0) * G);
-  c.iG = recip(G);
+  c.iG8 = T(0.125) * recip(G);
   return c;
 }
 
-// Minimum of two positive finite values (one v_min instruction).
-__device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
+// Minimum of two positive finite values.  For FP32 the bit patterns of
+// positive floats order like unsigned integers: one v_min_u32.
+__device__ __forceinline__ float tmin(float a, float b) {
+  return __builtin_bit_cast(float, __builtin_elementwise_min(__builtin_bit_cast(unsigned int, a),
+                                                             __builtin_bit_cast(unsigned int, b)));
+}
 __device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
 
 // Raw buffer view of a device array (at most 4 GiB - 1 bytes).  Accesses take
@@ -806,7 +812,7 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       }
       Cc[0] = mod.coef(mod.load(po, col + po, col32, colb));
       iHh[1] = T(1);
-      sG[0][tid] = Cc[0].iG;
+      sG[0][tid] = Cc[0].iG8;
     }
 
     // NORM: accumulate the squared residual (check iterations only)
@@ -820,6 +826,8 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       const int64_t oc = col + pc, on = col + pn;
       const bool face = k >= k0 && interior;
       const auto mr = mod.load(pn, on, col32, colb);
+      // u^{n-1} and the force only where a face is updated (ghost threads
+      // reading them costs more memory requests than the masking costs ALU)
       T uo0[L], uo1[L], uo2[L], f0[L], f1[L], f2[L];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
@@ -845,7 +853,7 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       T* gk = sG[P];
       T* gn = sG[Q];
       Cc[Q] = mod.coef(mr);
-      gn[tid] = Cc[Q].iG;
+      gn[tid] = Cc[Q].iG8;
       iHh[P] = Cc[P].iH;
       sH[tid] = iHh[P];
 #pragma unroll
@@ -859,9 +867,9 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       const T twoG = Cc[P].twoG;
       const T ik = gk[tid], ikx = gk[xm], iky = gk[ym];
       const T in = gn[tid], inx = gn[xm], iny = gn[ym];
-      const T G2xy = T(8) * recip(gk[xmym] + iky + ikx + ik);
-      const T G2xz = T(8) * recip(ikx + ik + inx + in);
-      const T G2yz = T(8) * recip(iky + ik + iny + in);
+      const T G2xy = recip(gk[xmym] + iky + ikx + ik);
+      const T G2xz = recip(ikx + ik + inx + in);
+      const T G2yz = recip(iky + ik + iny + in);
       const T sfx = sfac * tmin(sH[xm], iHh[P]);
       const T sfy = sfac * tmin(sH[ym], iHh[P]);
       const T sfz = sfac * tmin(iHh[Q], iHh[P]);
