@@ -101,7 +101,7 @@ typedef struct {
 
 /* Fill *o with the defaults: MIXED, rtol 1e-8, max_iter 2e6, check_every 100,
  * courant 0.95, strouhal 2.0, fuse_loads CEFF_FUSE_AUTO, use_graph 1, keep_fields 0,
- * autotune 0, fold_ratio 1e-4. */
+ * autotune 0, fold_ratio 1e-3. */
 void ceff_default_opts(ceff_solve_opts* o);
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t the

@@ -167,7 +167,7 @@ def _torch_stream():
 
 
 def make_opts(precision="mixed", rtol=1e-8, max_iter=2_000_000, check_every=100, courant=0.95, strouhal=2.0,
-              fuse_loads="auto", use_graph=True, keep_fields=False, autotune=False, fold_ratio=1e-4):
+              fuse_loads="auto", use_graph=True, keep_fields=False, autotune=False, fold_ratio=1e-3):
     """Solve options.  fuse_loads: True (one launch per iteration for all loads), False (one load
     after another) or "auto" (the library decides from the working set and the cache size)."""
     o = ceff_default_opts()

@@ -1056,7 +1056,7 @@ void ceff_default_opts(ceff_solve_opts* o) {
   o->use_graph = 1;
   o->keep_fields = 0;
   o->autotune = 0;
-  o->fold_ratio = 1e-4;
+  o->fold_ratio = 1e-3;
 }
 
 ceff_status ceff_create(int device, void* hip_stream, ceff_ctx** out) {
