@@ -33,6 +33,15 @@
  *   with the edge constant the harmonic mean over the four cells, as for G.
  *   With C11 = K + 4G/3, C12 = K - 2G/3 and C44 = G this is the isotropic law.
  *
+ * Wall boundaries (the paper's direct tests, appendix on boundary conditions:
+ * faces of the box are rigid in the normal direction and traction-free in the
+ * tangential ones) on the same periodic layout: the box boundary in direction
+ * d is the grid plane of index 0 in d (it is both the first and, by the wrap,
+ * the last plane).  The displacement fluctuation of the d-faces there is held at
+ * zero, so the total displacement of both walls is the macroscopic strain's, and
+ * the shear stress of every edge lying in a boundary plane is zero (free slip;
+ * those edges would couple the two sides of the box across the wrap).
+ *
  * Build: gcc -O2 -fopenmp -shared -fPIC (see oracle/build.py).
  * Arrays: x fastest, linear index i + nx*(j + ny*k); vector fields are stored
  * component-major: f[c*N + idx].  Tensor strain components are passed as
@@ -48,9 +57,11 @@ typedef struct {
     double hx, hy, hz;
 } grid_t;
 
-/* Material: isotropic K, G per cell, or nine orthotropic constants per cell (c9 != NULL). */
+/* Material: isotropic K, G per cell, or nine orthotropic constants per cell (c9 != NULL);
+ * walls != 0: rigid, free-slip walls instead of periodic boundaries. */
 typedef struct {
     const double *K, *G, *c9;
+    int walls;
 } mat_t;
 
 static inline int64_t wrap(int64_t a, int64_t n) { a %= n; return a < 0 ? a + n : a; }
@@ -133,6 +144,11 @@ static void hooke(const grid_t *g, const mat_t *m, const double *eps, double *si
                 sig[3 * N + c] = 2.0 * edge_shear(g, m, 2, i, j, k) * eps[3 * N + c];
                 sig[4 * N + c] = 2.0 * edge_shear(g, m, 1, i, j, k) * eps[4 * N + c];
                 sig[5 * N + c] = 2.0 * edge_shear(g, m, 0, i, j, k) * eps[5 * N + c];
+                if (m->walls) {  /* edges in a boundary plane carry no shear stress */
+                    if (j == 0 || k == 0) sig[3 * N + c] = 0.0;
+                    if (i == 0 || k == 0) sig[4 * N + c] = 0.0;
+                    if (i == 0 || j == 0) sig[5 * N + c] = 0.0;
+                }
             }
 }
 
@@ -175,11 +191,25 @@ static void m_stress(const grid_t *g, const mat_t *m, const double E[6], const d
     free(eps);
 }
 
+/* Zero the entries of a face field (3N) that belong to wall faces (held fixed). */
+static void mask_walls(const grid_t *g, double *f) {
+    const int64_t N = g->nx * g->ny * g->nz;
+    for (int64_t k = 0; k < g->nz; k++)
+        for (int64_t j = 0; j < g->ny; j++)
+            for (int64_t i = 0; i < g->nx; i++) {
+                int64_t c = at(g, i, j, k);
+                if (i == 0) f[c] = 0.0;
+                if (j == 0) f[N + c] = 0.0;
+                if (k == 0) f[2 * N + c] = 0.0;
+            }
+}
+
 static void m_residual(const grid_t *g, const mat_t *m, const double E[6], const double *u, double *r) {
     const int64_t N = g->nx * g->ny * g->nz;
     double *sig = malloc(sizeof(double) * 6 * N);
     m_stress(g, m, E, u, sig);
     divergence(g, sig, r);
+    if (m->walls) mask_walls(g, r); /* a wall face is held, its out-of-balance force is the reaction */
     free(sig);
 }
 
@@ -199,7 +229,7 @@ static void m_average_stress(const grid_t *g, const mat_t *m, const double E[6],
 void or_stress(const int64_t dims[3], const double h[3], const double *K, const double *G,
                const double E[6], const double *u, double *sig) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL};
+    mat_t m = {K, G, NULL, 0};
     m_stress(&g, &m, E, u, sig);
 }
 
@@ -207,7 +237,7 @@ void or_stress(const int64_t dims[3], const double h[3], const double *K, const 
 void or_residual(const int64_t dims[3], const double h[3], const double *K, const double *G,
                  const double E[6], const double *u, double *r) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL};
+    mat_t m = {K, G, NULL, 0};
     m_residual(&g, &m, E, u, r);
 }
 
@@ -216,7 +246,7 @@ void or_residual(const int64_t dims[3], const double h[3], const double *K, cons
 void or_average_stress(const int64_t dims[3], const double h[3], const double *K, const double *G,
                        const double E[6], const double *u, double out[6]) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL};
+    mat_t m = {K, G, NULL, 0};
     m_average_stress(&g, &m, E, u, out);
 }
 
@@ -224,21 +254,21 @@ void or_average_stress(const int64_t dims[3], const double h[3], const double *K
 void or_stress_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6],
                      const double *u, double *sig) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {NULL, NULL, c9};
+    mat_t m = {NULL, NULL, c9, 0};
     m_stress(&g, &m, E, u, sig);
 }
 
 void or_residual_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6],
                        const double *u, double *r) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {NULL, NULL, c9};
+    mat_t m = {NULL, NULL, c9, 0};
     m_residual(&g, &m, E, u, r);
 }
 
 void or_average_stress_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6],
                              const double *u, double out[6]) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {NULL, NULL, c9};
+    mat_t m = {NULL, NULL, c9, 0};
     m_average_stress(&g, &m, E, u, out);
 }
 
@@ -310,7 +340,7 @@ static int64_t m_pcg(const grid_t *gp, const mat_t *m, const double E[6], double
         goto done;
     }
     for (int64_t t = 0; t < n3; t++) z[t] = r[t] / dg[t];
-    remove_mean(N, z);
+    if (m->walls) mask_walls(&g, z); else remove_mean(N, z);
     memcpy(p, z, sizeof(double) * n3);
     double rz = dot(n3, r, z);
     for (it = 0; it < max_iter; it++) {
@@ -326,13 +356,13 @@ static int64_t m_pcg(const grid_t *gp, const mat_t *m, const double E[6], double
             r[t] -= alpha * q[t];
         }
         for (int64_t t = 0; t < n3; t++) z[t] = r[t] / dg[t];
-        remove_mean(N, z);
+        if (m->walls) mask_walls(&g, z); else remove_mean(N, z);
         double rz_new = dot(n3, r, z);
         double beta = rz_new / rz;
         rz = rz_new;
         for (int64_t t = 0; t < n3; t++) p[t] = z[t] + beta * p[t];
     }
-    remove_mean(N, u);
+    if (!m->walls) remove_mean(N, u);
     m_residual(&g, m, E, u, r);
     *relres = sqrt(dot(n3, r, r)) / bnorm;
 done:
@@ -344,14 +374,14 @@ int64_t or_pcg(const int64_t dims[3], const double h[3], const double *K, const 
                const double E[6], double rtol, int64_t max_iter, double *u, double *relres,
                double *hist, int64_t hist_cap) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL};
+    mat_t m = {K, G, NULL, 0};
     return m_pcg(&g, &m, E, rtol, max_iter, u, relres, hist, hist_cap);
 }
 
 int64_t or_pcg_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6], double rtol,
                      int64_t max_iter, double *u, double *relres, double *hist, int64_t hist_cap) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {NULL, NULL, c9};
+    mat_t m = {NULL, NULL, c9, 0};
     return m_pcg(&g, &m, E, rtol, max_iter, u, relres, hist, hist_cap);
 }
 
@@ -407,10 +437,34 @@ static void m_apt_disp(const grid_t *g, const mat_t *m, const double E[6], doubl
 }
 
 void or_apt_disp(const int64_t dims[3], const double h[3], const double *K, const double *G, const double *c9,
-                 const double E[6], double courant, double strouhal, int64_t nsteps, double *u, double *u_prev) {
+                 int walls, const double E[6], double courant, double strouhal, int64_t nsteps, double *u,
+                 double *u_prev) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, c9};
+    mat_t m = {K, G, c9, walls};
     m_apt_disp(&g, &m, E, courant, strouhal, nsteps, u, u_prev);
+}
+
+/* Wall-boundary versions (isotropic cells) of the residual, the stress averages
+ * and the PCG solve. */
+void or_residual_walls(const int64_t dims[3], const double h[3], const double *K, const double *G,
+                       const double E[6], const double *u, double *r) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, NULL, 1};
+    m_residual(&g, &m, E, u, r);
+}
+
+void or_average_stress_walls(const int64_t dims[3], const double h[3], const double *K, const double *G,
+                             const double E[6], const double *u, double out[6]) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, NULL, 1};
+    m_average_stress(&g, &m, E, u, out);
+}
+
+int64_t or_pcg_walls(const int64_t dims[3], const double h[3], const double *K, const double *G, const double E[6],
+                     double rtol, int64_t max_iter, double *u, double *relres) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, NULL, 1};
+    return m_pcg(&g, &m, E, rtol, max_iter, u, relres, NULL, 0);
 }
 
 /* Accelerated pseudo-transient iterations written in the paper's own variables

@@ -116,9 +116,23 @@ def _energy_weights(K, G):
     return apply
 
 
-def solve_dense(K, G, E, h=(1.0, 1.0, 1.0), C9=None):
+def wall_masks(shape):
+    """Rigid free-slip walls on the periodic layout: (free, edge_keep).  free (3N,
+    bool) marks face displacements that may move (not the d-faces of the plane of
+    index 0 in d); edge_keep (3, N) is 0 for edges lying in a boundary plane
+    (order yz, xz, xy), whose shear stiffness is dropped."""
+    nz, ny, nx = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    free = np.concatenate([(i != 0).ravel(), (j != 0).ravel(), (k != 0).ravel()])
+    keep = np.stack([((j != 0) & (k != 0)).ravel(), ((i != 0) & (k != 0)).ravel(),
+                     ((i != 0) & (j != 0)).ravel()]).astype(float)
+    return free, keep
+
+
+def solve_dense(K, G, E, h=(1.0, 1.0, 1.0), C9=None, walls=False):
     """Displacement fluctuation minimising the discrete strain energy (3, nz, ny, nx).
-    Isotropic (K, G) cells, or orthotropic cells when C9 is given."""
+    Isotropic (K, G) cells, or orthotropic cells when C9 is given; walls: rigid
+    free-slip walls (pinned wall faces, no shear energy on boundary edges)."""
     shape = K.shape if C9 is None else C9.shape[1:]
     N = int(np.prod(shape))
     zero = np.zeros(6)
@@ -126,7 +140,17 @@ def solve_dense(K, G, E, h=(1.0, 1.0, 1.0), C9=None):
     for col in range(3 * N):
         u = np.zeros(3 * N); u[col] = 1.0
         B[:, col] = strain_field(u.reshape((3,) + shape), zero, h).reshape(6 * N)
-    Dapply = _energy_weights(K, G) if C9 is None else _energy_weights_c9(C9)
+    Dapply0 = _energy_weights(K, G) if C9 is None else _energy_weights_c9(C9)
+    if walls:
+        free, keep = wall_masks(shape)
+
+        def Dapply(eps):
+            out = Dapply0(eps)
+            out[3:] *= keep
+            return out
+        B[:, ~free] = 0.0
+    else:
+        Dapply = Dapply0
     DB = np.empty_like(B)
     for col in range(3 * N):
         DB[:, col] = Dapply(B[:, col].reshape(6, N)).reshape(6 * N)
@@ -135,6 +159,25 @@ def solve_dense(K, G, E, h=(1.0, 1.0, 1.0), C9=None):
     rhs = -B.T @ Dapply(e0).reshape(6 * N)
     u, *_ = np.linalg.lstsq(A, rhs, rcond=1e-13)
     return u.reshape((3,) + shape), A
+
+
+def stress_walls(K, G, eps):
+    """Stresses with the boundary edges of the wall layout carrying none."""
+    sig = stress_field(K, G, eps)
+    _, keep = wall_masks(K.shape)
+    sig[3:] *= keep.reshape((3,) + K.shape)
+    return sig
+
+
+def ceff_dense_walls(K, G, h=(1.0, 1.0, 1.0)):
+    """Columns 0..2 of C* for rigid free-slip walls, by dense energy minimisation."""
+    C = np.full((6, 6), np.nan)
+    for J in range(3):
+        E = np.zeros(6); E[J] = 1.0
+        u, _ = solve_dense(K, G, E, h, walls=True)
+        sig = stress_walls(K, G, strain_field(u, E, h))
+        C[:, J] = sig.reshape(6, -1).mean(axis=1)
+    return C
 
 
 def ceff_dense(K, G, h=(1.0, 1.0, 1.0), C9=None):

@@ -1,0 +1,77 @@
+"""Pins of the oracle's wall-boundary mode (the paper's normal-compression and
+triaxial direct tests: rigid walls, free slip), CPU.
+
+Checked against an independent dense energy minimisation with the same walls,
+against the homogeneous medium (exact, no iterations), against the exact
+layer averages of a z-laminate (whose solution the walls do not disturb) and
+against the paper's layered-model analytic values."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import oracle
+from oracle import dense
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+IDX = {"C11": (0, 0), "C22": (1, 1), "C33": (2, 2), "C12": (0, 1), "C13": (0, 2), "C23": (1, 2)}
+
+
+def rel(A, B):
+    return np.nanmax(np.abs(A - B)) / np.nanmax(np.abs(B))
+
+
+def test_walls_dense_matches_pcg():
+    K, G = synth.random_fields((3, 4, 3), 5, lo=(5.0, 2.0), hi=(90.0, 45.0))
+    Cw, _ = oracle.ceff_walls(K, G, rtol=1e-13)
+    Cd = dense.ceff_dense_walls(K, G)
+    assert rel(Cw[:, :3], Cd[:, :3]) < 1e-10
+    # the walls change the answer (they are not the periodic problem)
+    Cp, _ = oracle.ceff(K, G, rtol=1e-13, loads=range(3))
+    assert rel(Cw[:3, :3], Cp[:3, :3]) > 1e-3
+
+
+def test_walls_homogeneous_exact():
+    m = synth.homogeneous((5, 4, 6))
+    Cw, info = oracle.ceff_walls(*m.fields())
+    np.testing.assert_allclose(Cw[:, :3], cf.c_iso(70.0, 32.0)[:, :3], rtol=1e-14, atol=1e-12)
+    assert all(it == 0 for it, _ in info.values())
+
+
+def test_walls_laminate_normal_block_exact():
+    Ks, Gs, thick = [30.0, 6.0, 80.0], [20.0, 3.0, 40.0], [3, 2, 4]
+    K = np.concatenate([np.full((t, 4, 5), k) for t, k in zip(thick, Ks)])
+    G = np.concatenate([np.full((t, 4, 5), g) for t, g in zip(thick, Gs)])
+    Cw, _ = oracle.ceff_walls(K, G, rtol=1e-13)
+    Cb = cf.backus_z(thick, Ks, Gs)
+    assert rel(Cw[:3, :3], Cb[:3, :3]) < 1e-10
+
+
+def test_walls_paper_layered_model_analytic_values():
+    """Model 1 (six stiff 15-voxel layers in 191): with walls, the normal block
+    still equals the analytic values to every printed digit (a 2 x 2 x 191 prism is
+    the same problem, the solution being uniform in x and y)."""
+    g = json.load(open(os.path.join(GOLD, "table2_layered.json")))
+    geo = g["geometry"]
+    m = synth.laminate_z(2, 2, geo["n"], geo["stiff_layers"], geo["layer_thickness"],
+                         stiff=(g["layers"]["stiff"]["K"], g["layers"]["stiff"]["G"]),
+                         soft=(g["layers"]["soft"]["K"], g["layers"]["soft"]["G"]))
+    C, _ = oracle.ceff_walls(*m.fields(), rtol=1e-12)
+    for name, (I, J) in IDX.items():
+        assert round(C[I, J], g["printed_decimals"]) == pytest.approx(g["analytic_GPa"][name], abs=1e-12), name
+
+
+def test_walls_residual_and_iteration_fixed_point():
+    K, G = synth.random_fields((4, 5, 6), 3, lo=(10.0, 5.0), hi=(80.0, 40.0))
+    for J in (0, 2):
+        u_ref, _, _ = oracle.solve_load_walls(K, G, J, rtol=1e-13)
+        r = oracle.residual_walls(K, G, oracle.unit_strain(J), u_ref)
+        assert np.max(np.abs(r)) < 1e-9 * np.max(np.abs(oracle.residual_walls(K, G, oracle.unit_strain(J),
+                                                                                np.zeros_like(u_ref))))
+        # wall faces stay put
+        assert np.all(u_ref[0][:, :, 0] == 0) and np.all(u_ref[1][:, 0, :] == 0) and np.all(u_ref[2][0] == 0)
+        u, _ = oracle.apt_disp(J, 3000, 0.95, 4.0, K=K, G=G, walls=True)
+        assert np.max(np.abs(u - u_ref)) < 1e-9 * np.max(np.abs(u_ref))
