@@ -54,6 +54,7 @@ enum { CEFF_F32 = 0, CEFF_F64 = 1 };          /* element type of caller arrays *
 enum { CEFF_HOST = 0, CEFF_DEVICE = 1 };      /* where caller arrays live */
 enum { CEFF_PREC_FP64 = 0, CEFF_PREC_MIXED = 1 };
 enum { CEFF_FUSE_AUTO = -1 };                 /* ceff_solve_opts.fuse_loads: let the library choose */
+enum { CEFF_BC_PERIODIC = 0, CEFF_BC_WALLS = 1 };  /* ceff_set_boundary */
 
 typedef struct {
   int precision;        /* CEFF_PREC_FP64: all sweeps in FP64.
@@ -140,6 +141,22 @@ ceff_status ceff_set_phases(ceff_ctx* ctx, const uint8_t* phase, int where, int 
  * interpolated between cells and edges) returns CEFF_EUNSUPPORTED.  Replaces
  * any material set before; ceff_gradient is not available for such materials. */
 ceff_status ceff_set_stiffness(ceff_ctx* ctx, const void* c, int ncomp, int dtype, int where);
+
+/* Boundary conditions of the context's problem (default CEFF_BC_PERIODIC).
+ * CEFF_BC_WALLS: the paper's direct tests (appendix on boundary conditions:
+ * normal compression and the tests for the off-diagonal constants): every
+ * face of the box is a rigid wall in its normal direction and free to slip
+ * tangentially.  On the periodic grid layout the box boundary in direction d is
+ * the grid plane of index 0 in d; there the displacement fluctuation of the
+ * d-faces is held at zero (both walls move with the macroscopic strain, e.g.
+ * by E_zz * L_z in z) and edges lying in a boundary plane carry no shear
+ * stress.  Only the normal loads (bits 0-2 of ceff_solve's mask) are defined:
+ * each gives a column of the confined-compression stiffness, whose upper 3x3
+ * block is what the paper's C11, C22, C33 and its formulas for C12, C13, C23
+ * compute.  The loads run one after another; orthotropic cells, the batch
+ * path and the gradient need periodic boundaries (CEFF_EUNSUPPORTED).  Applies
+ * to ceff_solve, ceff_apt_steps, ceff_residual and ceff_average_stress. */
+ceff_status ceff_set_boundary(ceff_ctx* ctx, int mode);
 
 /* Solve the unit loads in load_mask (bit J = Voigt column J, 0..5) and write
  * those columns of C_out (other entries untouched).  opts may be NULL

@@ -28,7 +28,8 @@ from ._lib import (CEFF_DEVICE, CEFF_F32, CEFF_F64, CEFF_FUSE_AUTO, CEFF_HOST, C
 _L = _lib.load()
 
 __all__ = ["ceff_default_opts", "ceff_create", "ceff_destroy", "ceff_last_error", "ceff_set_grid",
-           "ceff_set_isotropic", "ceff_set_phases", "ceff_set_stiffness", "ceff_solve", "ceff_solve_batch",
+           "ceff_set_isotropic", "ceff_set_phases", "ceff_set_stiffness", "ceff_set_boundary", "ceff_solve",
+           "ceff_solve_batch",
            "ceff_gradient", "ceff_apt_steps", "ceff_residual", "ceff_average_stress", "ceff_get_stats",
            "ceff_contribution_tensors", "CeffError", "Context", "solve", "solve_batch", "contribution_tensors",
            "EffectiveStiffness", "library_path"]
@@ -87,6 +88,10 @@ def ceff_set_phases(ctx, phase, where, nphase, K_tab, G_tab):
 
 def ceff_set_stiffness(ctx, c, ncomp, dtype, where):
     return _check(ctx, _L.ceff_set_stiffness(ctx, c, ncomp, dtype, where))
+
+
+def ceff_set_boundary(ctx, mode):
+    return _check(ctx, _L.ceff_set_boundary(ctx, mode))
 
 
 def ceff_solve(ctx, load_mask, opts, C_out, hist, hist_cap, hist_len, iters_out, allow=()):
@@ -233,6 +238,11 @@ class Context:
         ceff_set_stiffness(self.h, p, 9, dt, wh)
         self.shape = (nz, ny, nx)
         self.h_spacing = tuple(map(float, h))
+
+    def set_boundary(self, mode):
+        """"periodic" (default) or "walls" (rigid, free-slip walls: the paper's direct tests;
+        normal loads only)."""
+        ceff_set_boundary(self.h, {"periodic": _lib.CEFF_BC_PERIODIC, "walls": _lib.CEFF_BC_WALLS}[mode])
 
     def set_phases(self, phase, K_tab, G_tab, h=(1.0, 1.0, 1.0)):
         ph = np.ascontiguousarray(phase, np.uint8)

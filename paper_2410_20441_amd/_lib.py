@@ -17,6 +17,7 @@ CEFF_F32, CEFF_F64 = 0, 1
 CEFF_HOST, CEFF_DEVICE = 0, 1
 CEFF_PREC_FP64, CEFF_PREC_MIXED = 0, 1
 CEFF_FUSE_AUTO = -1
+CEFF_BC_PERIODIC, CEFF_BC_WALLS = 0, 1
 
 STATUS_NAMES = {0: "CEFF_OK", -1: "CEFF_EINVAL", -2: "CEFF_ENOMEM", -3: "CEFF_EDEVICE", -4: "CEFF_ENOTCONV",
                 -5: "CEFF_EDIVERGED", -6: "CEFF_EUNSUPPORTED", -7: "CEFF_ESTATE"}
@@ -54,6 +55,7 @@ SIGNATURES = {
     "ceff_set_isotropic": (_st, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int]),
     "ceff_set_phases": (_st, [_vp, _vp, ctypes.c_int, ctypes.c_int, _dp, _dp]),
     "ceff_set_stiffness": (_st, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "ceff_set_boundary": (_st, [_vp, ctypes.c_int]),
     "ceff_solve": (_st, [_vp, ctypes.c_uint32, ctypes.POINTER(ceff_solve_opts), _dp, _dp, _i64, _i64p, _i64p]),
     "ceff_solve_batch": (_st, [_vp, ctypes.c_int, _i64p, _dp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int,
                                ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ceff_solve_opts), _dp, _i64p]),

@@ -89,6 +89,7 @@ struct ceff_ctx {
   // material given as orthotropic cells: 9N constants (FP64, FP32 copy for the mixed path)
   DevBuf c64, c32;
   bool ortho = false;
+  int boundary = CEFF_BC_PERIODIC;
   DevBuf keep[6];
   bool kept[6] = {false, false, false, false, false, false};
   std::string err;
@@ -231,6 +232,7 @@ struct SampleIn {
   int nphase = 0;
   const double* c64 = nullptr;  // orthotropic cells (9N) or nullptr
   const float* c32 = nullptr;
+  int walls = 0;                 // 1: rigid, free-slip walls
 };
 
 struct Prob {
@@ -305,7 +307,7 @@ struct Engine {
   bool single() const { return Js.size() == 1; }
   int slot_of(int J) const { return single() ? 0 : J; }
   int group() const {
-    return single() || ts.pf == 5 || ts.ortho ? 1 : (ts.group > 0 ? ts.group : kMaxLoads);
+    return single() || ts.pf == 5 || ts.ortho || ts.walls ? 1 : (ts.group > 0 ? ts.group : kMaxLoads);
   }
 
   // Read the moduli from the phase image when there is one (one sample) and the
@@ -315,6 +317,8 @@ struct Engine {
     const char* env = std::getenv("CEFF_MODULI");
     const bool fields = env != nullptr && std::strcmp(env, "fields") == 0;
     t.ortho = in[0].c64 != nullptr ? 1 : 0;
+    t.walls = in[0].walls;
+    if (t.walls) t.pf = 3;  // the wall-boundary kernels are variant 3, one load per block
     t.pal = !t.ortho && in.size() == 1 && in[0].phase != nullptr && t.pf == 3 && !fields ? 1 : 0;
     return t;
   }
@@ -482,7 +486,7 @@ struct Engine {
       return CEFF_OK;
     }
     ts = with_moduli(default_tile(in[0].nx, in[0].ny, fp64, single()));
-    if (!o.autotune || ts.ortho) return CEFF_OK;
+    if (!o.autotune || ts.ortho || ts.walls) return CEFF_OK;
     std::vector<TileShape> cand;
     const int bxs[] = {18, 34, 66};
     const int bys[] = {6, 7, 10, 14};
@@ -575,6 +579,7 @@ struct Engine {
         dsc->ptab = sizeof(T) == 8 ? (const T*)s.ptab64 : (const T*)s.ptab32;
         dsc->nphase = s.nphase;
         dsc->cst = sizeof(T) == 8 ? (const T*)s.c64 : (const T*)s.c32;
+        dsc->walls = s.walls;
       }
       SampleDesc<double>& od = h_out[si];
       od.nx = s.nx; od.ny = s.ny; od.nz = s.nz; od.N = N;
@@ -582,6 +587,7 @@ struct Engine {
       od.mom = p.mom; od.sfac = p.sfac; od.sfac_first = p.sfac_first;
       od.K = s.K64; od.G = s.G64;
       od.cst = s.c64;
+      od.walls = s.walls;
       for (int J : Js) {
         const int l = slot_of(J);
         for (int b = 0; b < 2; ++b) {
@@ -615,7 +621,7 @@ struct Engine {
     STCK(build_work(ts, group(), work, ranges, kcs));
     TileShape to = ts;
     to.kc = 0;
-    STCK(build_work(to, single() || ts.ortho ? 1 : kMaxLoads, work_o, ranges_o, kcs_o));
+    STCK(build_work(to, single() || ts.ortho || ts.walls ? 1 : kMaxLoads, work_o, ranges_o, kcs_o));
     for (int si = 0; si < ns; ++si) {
       h_in[si].kc = kcs[si];
       h_out[si].kc = kcs_o[si];
@@ -894,7 +900,7 @@ ceff_status stress_average(ceff_ctx* c, const SampleIn& s, int J, const double* 
                                          o6.as<double>(), c->s));
   else
     HIPCK(c, launch_average_stress(s.nx, s.ny, s.nz, s.h, s.K64, s.G64, E, u, part.as<double>(), cap,
-                                   o6.as<double>(), c->s));
+                                   o6.as<double>(), s.walls, c->s));
   HIPCK(c, hipMemcpyAsync(out6, o6.p, sizeof(double) * 6, hipMemcpyDeviceToHost, c->s));
   HIPCK(c, hipStreamSynchronize(c->s));
   for (int q = 0; q < 6; ++q) out6[q] /= (double)N;
@@ -1025,6 +1031,7 @@ SampleIn ctx_sample(ceff_ctx* c) {
   s.K64 = c->K64.as<double>(); s.G64 = c->G64.as<double>();
   s.K32 = c->have32 ? c->K32.as<float>() : nullptr;
   s.G32 = c->have32 ? c->G32.as<float>() : nullptr;
+  s.walls = c->boundary == CEFF_BC_WALLS ? 1 : 0;
   if (c->ortho) {
     s.c64 = c->c64.as<double>();
     s.c32 = c->have32 ? c->c32.as<float>() : nullptr;
@@ -1221,6 +1228,16 @@ ceff_status ceff_set_stiffness(ceff_ctx* c, const void* cmat, int ncomp, int dty
   return CEFF_OK;
 }
 
+ceff_status ceff_set_boundary(ceff_ctx* c, int mode) {
+  if (!c) return CEFF_EINVAL;
+  if (mode != CEFF_BC_PERIODIC && mode != CEFF_BC_WALLS)
+    return fail(c, CEFF_EINVAL, "mode must be CEFF_BC_PERIODIC or CEFF_BC_WALLS");
+  c->boundary = mode;
+  clear_kept(c);
+  c->err.clear();
+  return CEFF_OK;
+}
+
 ceff_status ceff_solve(ceff_ctx* c, uint32_t load_mask, const ceff_solve_opts* opts, double C_out[36], double* hist,
                        int64_t hist_cap, int64_t* hist_len, int64_t iters_out[6]) {
   if (!c) return CEFF_EINVAL;
@@ -1232,6 +1249,10 @@ ceff_status ceff_solve(ceff_ctx* c, uint32_t load_mask, const ceff_solve_opts* o
   if (load_mask == 0 || (load_mask & ~0x3Fu)) return fail(c, CEFF_EINVAL, "load_mask must be a nonzero 6-bit mask");
   if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(c, CEFF_EINVAL, "bad history buffer");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  const bool walls = c->boundary == CEFF_BC_WALLS;
+  if (walls && (load_mask & 0x38u))
+    return fail(c, CEFF_EINVAL, "with wall boundaries only the normal loads (bits 0-2) are defined");
+  if (walls && c->ortho) return fail(c, CEFF_EUNSUPPORTED, "wall boundaries with orthotropic cells");
   STCK(begin_call(c));
   const auto t0 = std::chrono::steady_clock::now();
   c->stats = ceff_stats{};
@@ -1248,7 +1269,8 @@ ceff_status ceff_solve(ceff_ctx* c, uint32_t load_mask, const ceff_solve_opts* o
   std::vector<double> hv;
   ceff_status worst = CEFF_OK;
   std::vector<std::vector<int>> groups;
-  const bool fuse = o.fuse_loads == CEFF_FUSE_AUTO ? fuse_by_cache(c, mixed, (int)Js.size()) : o.fuse_loads != 0;
+  const bool fuse = !walls && (o.fuse_loads == CEFF_FUSE_AUTO ? fuse_by_cache(c, mixed, (int)Js.size())
+                                                               : o.fuse_loads != 0);
   if (fuse && Js.size() > 1)
     groups.push_back(Js);
   else
@@ -1350,6 +1372,7 @@ ceff_status ceff_gradient(ceff_ctx* c, const double W[36], void* dK, void* dG, i
     if (!std::isfinite(W[q])) return fail(c, CEFF_EINVAL, "W must be finite");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
   if (c->ortho) return fail(c, CEFF_EUNSUPPORTED, "the gradient is defined for isotropic (K, G) materials only");
+  if (c->boundary != CEFF_BC_PERIODIC) return fail(c, CEFF_EUNSUPPORTED, "the gradient needs periodic boundaries");
   const double* u6[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   for (int I = 0; I < 6; ++I)
     for (int J = 0; J < 6; ++J)

@@ -32,6 +32,10 @@ struct SampleDesc {
   // (component-major) or nullptr; when set, K, G and the phase image are unused
   // and the orthotropic kernels run (TileShape::ortho).
   const T* cst;
+  // 1: rigid, free-slip walls instead of periodic boundaries: the d-faces of the
+  // grid plane of index 0 in d are held, and edges lying in such a plane carry
+  // no shear stress (one load per block; TileShape::walls)
+  int walls;
   T E[kMaxLoads][6];          // macroscopic tensor strain per load: xx yy zz yz xz xy
   unsigned active;            // bit l: load l is iterated
   int work_begin, work_end;   // this sample's work items [begin, end)
@@ -58,6 +62,7 @@ struct TileShape {
   int occ;     // 1: build that targets more waves per SIMD (fewer registers)
   int pal;     // 1: moduli from the samples' phase image and table (variant 3 only)
   int ortho;   // 1: orthotropic cells (one load per block, its own kernel)
+  int walls;   // 1: wall boundaries (variant 3, one load per block)
 };
 
 // ---- launch wrappers (ceff_kernels.hip) ----------------------------------------
@@ -95,7 +100,7 @@ hipError_t launch_finalize_norms(const int* d_ranges /* 2 per sample */, int nsa
 // block partials (6 per block) then the final 6 sums (not yet divided by N).
 hipError_t launch_average_stress(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K,
                                  const double* G, const double E[6], const double* u, double* partials,
-                                 int nblocks_cap, double* out6, hipStream_t s);
+                                 int nblocks_cap, double* out6, int walls, hipStream_t s);
 
 // The same for orthotropic cells (cst: 9N FP64 constants).
 hipError_t launch_average_stress_ortho(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* cst,

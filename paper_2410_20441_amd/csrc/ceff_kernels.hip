@@ -226,7 +226,7 @@ __device__ void stage_coef_table(const SampleDesc<T>& sd, CellCoef<T>* tab) {
   __syncthreads();
 }
 
-template <typename T, int L, int MODE, typename R, bool PF, bool HI>
+template <typename T, int L, int MODE, typename R, bool PF, bool HI, bool WALLS = false>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWaves<T, L, HI>::value)))
 step_kernel(const SampleDesc<T>* __restrict__ samples,
                                                    const WorkItem* __restrict__ work, int nwork, int bx, int by,
@@ -280,6 +280,8 @@ step_kernel(const SampleDesc<T>* __restrict__ samples,
     const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
     const int64_t k0 = (int64_t)wi.kz * sd.kc;
     const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
+    // wall boundaries: this column lies in the x (y) boundary plane
+    const bool wx = WALLS && wrap_idx(gi, nx) == 0, wy = WALLS && wrap_idx(gj, ny) == 0;
 
     const GLOBAL_AS T* __restrict__ Kf = gconst(sd.K);
     const GLOBAL_AS T* __restrict__ Gf = gconst(sd.G);
@@ -414,9 +416,15 @@ step_kernel(const SampleDesc<T>* __restrict__ samples,
         const T sxx = lam * th + twoG * exx;
         const T syy = lam * th + twoG * eyy;
         const T szz = lam * th + twoG * ezz;
-        const T sxy = G2xy * (E[5] + T(0.5) * ((ux[l] - sUx[ym]) * rhy + (uy[l] - sUy[xm]) * rhx));
-        const T sxz_n = G2xz * (E[4] + T(0.5) * ((unx[l] - ux[l]) * rhz + (unz[l] - sUz[xm]) * rhx));
-        const T syz_n = G2yz * (E[3] + T(0.5) * ((uny[l] - uy[l]) * rhz + (unz[l] - sUz[ym]) * rhy));
+        T sxy = G2xy * (E[5] + T(0.5) * ((ux[l] - sUx[ym]) * rhy + (uy[l] - sUy[xm]) * rhx));
+        T sxz_n = G2xz * (E[4] + T(0.5) * ((unx[l] - ux[l]) * rhz + (unz[l] - sUz[xm]) * rhx));
+        T syz_n = G2yz * (E[3] + T(0.5) * ((uny[l] - uy[l]) * rhz + (unz[l] - sUz[ym]) * rhy));
+        if constexpr (WALLS) {  // edges in a boundary plane: no shear stress
+          const bool wzn = k + 1 == nz || k + 1 == 0;  // xz/yz-edges owned here sit between k and k+1
+          if (wx || wy) sxy = T(0);
+          if (wx || wzn) sxz_n = T(0);
+          if (wy || wzn) syz_n = T(0);
+        }
         sSxx[tid] = sxx;
         sSyy[tid] = syy;
         sSxy[tid] = sxy;
@@ -430,6 +438,11 @@ step_kernel(const SampleDesc<T>* __restrict__ samples,
           rx += f0[l];
           ry += f1[l];
           rz += f2[l];
+          if constexpr (WALLS) {  // held wall faces: no out-of-balance force
+            if (wx) rx = T(0);
+            if (wy) ry = T(0);
+            if (kw == 0) rz = T(0);
+          }
           if (partials != nullptr)
             nsum[l] += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
           if (MODE == 0) {
@@ -686,7 +699,7 @@ step_kernel_u2(const SampleDesc<T>* __restrict__ samples, const WorkItem* __rest
 // stresses, so two barriers per plane whatever the group size.  LDS holds
 // 3 + 8L arrays (and the coefficient table with PAL).  The G arrays hold 1/G,
 // computed once per cell by its owner.
-template <typename T, int L, bool HI, bool PAL>
+template <typename T, int L, bool HI, bool PAL, bool WALLS = false>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWaves<T, L, HI>::value)))
 step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
               int by, int parity, int first, double* __restrict__ partials) {
@@ -734,6 +747,8 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
     const int nz32 = (int)nz;
     const int k0 = wi.kz * sd.kc;
     const int k1 = k0 + sd.kc < nz32 ? k0 + sd.kc : nz32;
+    // wall boundaries: this column lies in the x (y) boundary plane
+    const bool wx = WALLS && wrap_idx(gi, nx) == 0, wy = WALLS && wrap_idx(gj, ny) == 0;
 
     // One load per block: every access is a buffer access (descriptor and
     // component/plane offset uniform, the column's 32-bit byte offset per
@@ -891,6 +906,11 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
         sxy[l] = G2xy * (E[l][5] + T(0.5) * ((ux - sUx[ym]) * rhy + (uy - sUy[xm]) * rhx));
         sxz_n[l] = G2xz * (E[l][4] + T(0.5) * ((unx - ux) * rhz + (unz - sUz[xm]) * rhx));
         syz_n[l] = G2yz * (E[l][3] + T(0.5) * ((uny - uy) * rhz + (unz - sUz[ym]) * rhy));
+        if constexpr (WALLS) {  // edges in a boundary plane: no shear stress
+          if (wx || wy) sxy[l] = T(0);
+          if (wx || kn == 0) sxz_n[l] = T(0);
+          if (wy || kn == 0) syz_n[l] = T(0);
+        }
         S(l, 3)[tid] = sxx[l];
         S(l, 4)[tid] = syy[l];
         S(l, 5)[tid] = sxy[l];
@@ -913,6 +933,11 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
           rx += f0[l];
           ry += f1[l];
           rz += f2[l];
+          if constexpr (WALLS) {  // held wall faces: no out-of-balance force
+            if (wx) rx = T(0);
+            if (wy) ry = T(0);
+            if (kw == 0) rz = T(0);
+          }
           if (NORM && (L == 1 || partials != nullptr))
             nsum[l] += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
           const T ux = Ux[P][l], uy = Uy[P][l], uz = Uz[P][l];
@@ -1594,7 +1619,7 @@ __global__ void finalize_norms_kernel(const int* __restrict__ ranges, const doub
 __global__ void average_partials_kernel(int64_t nx, int64_t ny, int64_t nz, double rhx, double rhy, double rhz,
                                         const double* __restrict__ K, const double* __restrict__ G, double E0,
                                         double E1, double E2, double E3, double E4, double E5,
-                                        const double* __restrict__ u, double* __restrict__ partials) {
+                                        const double* __restrict__ u, double* __restrict__ partials, int walls) {
   __shared__ double red[16];
   const int64_t N = nx * ny * nz;
   const double* ux = u;
@@ -1616,9 +1641,14 @@ __global__ void average_partials_kernel(int64_t nx, int64_t ny, int64_t nz, doub
     acc[1] += lam * th + 2.0 * G[c] * eyy;
     acc[2] += lam * th + 2.0 * G[c] * ezz;
     const double gc = 1.0 / G[c];
-    const double gyz = 8.0 / (gc + 1.0 / G[at(i, jm, k)] + 1.0 / G[at(i, j, km)] + 1.0 / G[at(i, jm, km)]);
-    const double gxz = 8.0 / (gc + 1.0 / G[at(im, j, k)] + 1.0 / G[at(i, j, km)] + 1.0 / G[at(im, j, km)]);
-    const double gxy = 8.0 / (gc + 1.0 / G[at(im, j, k)] + 1.0 / G[at(i, jm, k)] + 1.0 / G[at(im, jm, k)]);
+    double gyz = 8.0 / (gc + 1.0 / G[at(i, jm, k)] + 1.0 / G[at(i, j, km)] + 1.0 / G[at(i, jm, km)]);
+    double gxz = 8.0 / (gc + 1.0 / G[at(im, j, k)] + 1.0 / G[at(i, j, km)] + 1.0 / G[at(im, j, km)]);
+    double gxy = 8.0 / (gc + 1.0 / G[at(im, j, k)] + 1.0 / G[at(i, jm, k)] + 1.0 / G[at(im, jm, k)]);
+    if (walls) {  // edges in a boundary plane carry no shear stress
+      if (j == 0 || k == 0) gyz = 0.0;
+      if (i == 0 || k == 0) gxz = 0.0;
+      if (i == 0 || j == 0) gxy = 0.0;
+    }
     acc[3] += gyz * (E3 + 0.5 * ((uy[c] - uy[at(i, j, km)]) * rhz + (uz[c] - uz[at(i, jm, k)]) * rhy));
     acc[4] += gxz * (E4 + 0.5 * ((ux[c] - ux[at(i, j, km)]) * rhz + (uz[c] - uz[at(im, j, k)]) * rhx));
     acc[5] += gxy * (E5 + 0.5 * ((ux[c] - ux[at(i, jm, k)]) * rhy + (uy[c] - uy[at(im, j, k)]) * rhx));
@@ -1853,7 +1883,16 @@ void launch_step_occ(const SampleDesc<T>* d_samples, const WorkItem* d_work, int
   } else if (ts.pf == 4)
     hipLaunchKernelGGL((step_kernel_p3<T, L, HI>), dim3(nwork), dim3(nt), (size_t)(3 + 8 * L) * nt * sizeof(T), s,
                        d_samples, d_work, nwork, ts.bx, ts.by, parity, first, partials);
-  else if (ts.pf == 3 && ts.pal)
+  else if (ts.walls) {
+    // wall boundaries: variant 3, one load per block (the engine guarantees L == 1)
+    const size_t lds = (size_t)11 * nt * sizeof(T) + (ts.pal ? 256 * sizeof(CellCoef<T>) : 0);
+    if (ts.pal)
+      hipLaunchKernelGGL((step_kernel_b<T, 1, HI, true, true>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work,
+                         nwork, ts.bx, ts.by, parity, first, partials);
+    else
+      hipLaunchKernelGGL((step_kernel_b<T, 1, HI, false, true>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work,
+                         nwork, ts.bx, ts.by, parity, first, partials);
+  } else if (ts.pf == 3 && ts.pal)
     hipLaunchKernelGGL((step_kernel_b<T, L, HI, true>), dim3(nwork), dim3(nt),
                        (size_t)(3 + 8 * L) * nt * sizeof(T) + 256 * sizeof(CellCoef<T>), s, d_samples, d_work, nwork,
                        ts.bx, ts.by, parity, first, partials);
@@ -1888,8 +1927,12 @@ hipError_t launch_residual(const SampleDesc<T>* d_samples, const WorkItem* d_wor
                            int parity, R* const* rout, double* partials, hipStream_t s) {
   const int nt = ((ts.bx * ts.by + 63) / 64) * 64;
   const size_t lds = (size_t)11 * nt * sizeof(T);
-  hipLaunchKernelGGL((step_kernel<T, L, 1, R, false, false>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work,
-                     nwork, ts.bx, ts.by, parity, 0, partials, rout);
+  if (ts.walls)
+    hipLaunchKernelGGL((step_kernel<T, L, 1, R, false, false, true>), dim3(nwork), dim3(nt), lds, s, d_samples,
+                       d_work, nwork, ts.bx, ts.by, parity, 0, partials, rout);
+  else
+    hipLaunchKernelGGL((step_kernel<T, L, 1, R, false, false>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work,
+                       nwork, ts.bx, ts.by, parity, 0, partials, rout);
   return hipGetLastError();
 }
 
@@ -1923,11 +1966,11 @@ hipError_t launch_finalize_norms(const int* d_ranges, int nsamples, const double
 
 hipError_t launch_average_stress(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K,
                                  const double* G, const double E[6], const double* u, double* partials,
-                                 int nblocks_cap, double* out6, hipStream_t s) {
+                                 int nblocks_cap, double* out6, int walls, hipStream_t s) {
   int nb = grid_for(nx * ny * nz, 256);
   if (nb > nblocks_cap) nb = nblocks_cap;
   hipLaunchKernelGGL(average_partials_kernel, dim3(nb), dim3(256), 0, s, nx, ny, nz, 1.0 / h[0], 1.0 / h[1],
-                     1.0 / h[2], K, G, E[0], E[1], E[2], E[3], E[4], E[5], u, partials);
+                     1.0 / h[2], K, G, E[0], E[1], E[2], E[3], E[4], E[5], u, partials, walls);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(average_finalize_kernel, dim3(6), dim3(256), 0, s, partials, nb, out6);

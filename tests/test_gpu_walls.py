@@ -1,0 +1,148 @@
+"""Wall boundaries (ceff_set_boundary(CEFF_BC_WALLS): the paper's direct tests
+with rigid, free-slip walls), GPU.
+
+Step, residual and average parity with the oracle's wall mode, C* columns of
+the normal loads against the oracle's wall-mode PCG solve, the paper's layered
+Model 1 at its full size against the analytic values (the walls do not
+disturb a z-laminate's solution), and the error paths."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import oracle
+import synth
+from gpu_common import announce, need_gpu
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+SHAPES = [((8, 8, 8), 1), ((12, 10, 9), 2), ((70, 9, 5), 3), ((5, 23, 6), 4), ((6, 5, 41), 5)]
+
+
+def fields(shape, seed):
+    return synth.random_fields(shape, seed, lo=(2.0, 1e-3), hi=(90.0, 45.0))
+
+
+def rel3(C, Co):
+    return np.max(np.abs(C[:, :3] - Co[:, :3])) / np.max(np.abs(Co[:, :3]))
+
+
+@pytest.mark.parametrize("shape,seed", SHAPES)
+def test_walls_steps_match_oracle(shape, seed):
+    p = need_gpu()
+    K, G = fields(shape, seed)
+    announce("walls apt_steps", shape, seed)
+    with p.Context() as c:
+        c.set_material(K, G)
+        c.set_boundary("walls")
+        for J in (0, 1, 2):
+            for k in (1, 2, 11):
+                u, up = c.apt_steps(J, k, "fp64", courant=0.95, strouhal=3.0)
+                ref, refp = oracle.apt_disp(J, k, 0.95, 3.0, K=K, G=G, walls=True)
+                sc = np.abs(ref).max()
+                assert np.max(np.abs(u - ref)) <= 1e-11 * sc, (J, k)
+                if k > 1:
+                    assert np.max(np.abs(up - refp)) <= 1e-11 * sc
+        u32, _ = c.apt_steps(2, 9, "mixed", courant=0.95, strouhal=3.0)
+    ref, _ = oracle.apt_disp(2, 9, 0.95, 3.0, K=K, G=G, walls=True)
+    assert np.max(np.abs(u32 - ref)) <= 2e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("shape,seed", SHAPES[:3])
+def test_walls_residual_and_averages_match_oracle(shape, seed):
+    p = need_gpu()
+    K, G = fields(shape, seed)
+    u = np.stack([synth.random_fields(shape, 60 + q, lo=(0.5, 0.5), hi=(2.0, 2.0))[0] - 1.0 for q in range(3)])
+    announce("walls residual", shape)
+    with p.Context() as c:
+        c.set_material(K, G)
+        c.set_boundary("walls")
+        for J in (0, 2):
+            r, n2 = c.residual(J, u, "fp64")
+            ref = oracle.residual_walls(K, G, oracle.unit_strain(J), u)
+            assert np.max(np.abs(r - ref)) <= 1e-12 * np.abs(ref).max()
+            assert n2 == pytest.approx(float(np.sum(ref * ref)), rel=1e-12)
+        for J in range(3):
+            a = c.average_stress(J, u)
+            ref = oracle.average_stress_walls(K, G, oracle.unit_strain(J), u)
+            np.testing.assert_allclose(a, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("use_phases", [False, True])
+def test_walls_ceff_matches_oracle(use_phases):
+    p = need_gpu()
+    m = synth.gaussian_field_three_phase(20, 0xC4)
+    K, G = m.fields()
+    Co, _ = oracle.ceff_walls(K, G, rtol=1e-12)
+    announce("walls ceff", use_phases)
+    with p.Context() as c:
+        if use_phases:
+            c.set_phases(m.phase, m.K_tab, m.G_tab)
+        else:
+            c.set_material(K, G)
+        c.set_boundary("walls")
+        for prec in ("mixed", "fp64"):
+            C, info = c.solve(loads=(0, 1, 2), precision=prec, rtol=1e-9)
+            assert info["status"] == 0 and info["stats"]["fused_loads"] == 0
+            assert rel3(C, Co) <= 1e-6, (prec, rel3(C, Co))
+        # the walls change the result: periodic C* differs
+        c.set_boundary("periodic")
+        Cp, _ = c.solve(loads=(0, 1, 2), precision="fp64", rtol=1e-9)
+    assert rel3(Cp, Co) > 1e-4
+
+
+def test_walls_homogeneous_is_exact():
+    p = need_gpu()
+    m = synth.homogeneous((20, 18, 16))
+    with p.Context() as c:
+        c.set_phases(m.phase, m.K_tab, m.G_tab)
+        c.set_boundary("walls")
+        C, info = c.solve(loads=(0, 1, 2), precision="mixed")
+    np.testing.assert_allclose(C[:, :3], cf.c_iso(70.0, 32.0)[:, :3], rtol=1e-14, atol=1e-12)
+    assert np.all(info["iters"][:3] == 0)
+
+
+def test_walls_paper_layered_model_full_size():
+    """Model 1 at 191^3 with walls: the normal block equals the analytic values to
+    every printed digit.  The paper's numerical column (its own wall
+    implementation) differs by up to 0.4% (C33 30.419, C12 3.720, C13 2.148)."""
+    p = need_gpu()
+    g = json.load(open(os.path.join(GOLD, "table2_layered.json")))
+    geo = g["geometry"]
+    st, so = g["layers"]["stiff"], g["layers"]["soft"]
+    m = synth.laminate_z(191, 191, 191, geo["stiff_layers"], geo["layer_thickness"],
+                         stiff=(st["K"], st["G"]), soft=(so["K"], so["G"]))
+    announce("walls laminate 191^3")
+    with p.Context() as c:
+        c.set_phases(m.phase, m.K_tab, m.G_tab)
+        c.set_boundary("walls")
+        C, info = c.solve(loads=(0, 1, 2), precision="mixed", rtol=1e-8)
+    assert info["status"] == 0
+    idx = {"C11": (0, 0), "C22": (1, 1), "C33": (2, 2), "C12": (0, 1), "C13": (0, 2), "C23": (1, 2)}
+    for name, (I, J) in idx.items():
+        assert round(C[I, J], 3) == pytest.approx(g["analytic_GPa"][name], abs=1e-12), name
+
+
+def test_walls_errors():
+    p = need_gpu()
+    from paper_2410_20441_amd import _lib
+    K, G = fields((8, 8, 8), 9)
+    with p.Context() as c:
+        c.set_material(K, G)
+        with pytest.raises(p.CeffError) as e:
+            p.ceff_set_boundary(c.h, 7)
+        assert e.value.status == _lib.CEFF_EINVAL
+        c.set_boundary("walls")
+        with pytest.raises(p.CeffError) as e:
+            c.solve(loads=(0, 3), precision="fp64")
+        assert e.value.status == _lib.CEFF_EINVAL
+        c.solve(loads=(0, 1, 2), precision="fp64", keep_fields=True)
+        with pytest.raises(p.CeffError) as e:
+            c.gradient(np.diag([1.0, 0, 0, 0, 0, 0]))
+        assert e.value.status == _lib.CEFF_EUNSUPPORTED
+        c.set_stiffness(oracle.iso_to_c9(K, G))
+        with pytest.raises(p.CeffError) as e:
+            c.solve(loads=(0,), precision="fp64")
+        assert e.value.status == _lib.CEFF_EUNSUPPORTED
