@@ -27,12 +27,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the iteration kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_hbm_counters.md),
 # valid only for the kernel source they were taken on.
-MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "cbcbc94ecbd5bdb2", "bytes_per_launch": 3.266316e+08,
+MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "987916c01cbf2513", "bytes_per_launch": 3.273298e+08,
                     # (loads per block, kernel variant, loads fused, moduli from the phase image)
                     "launch_signature": (1, 3, 0, 1),
                     # mean algorithmic bytes per launch of the profiled solve: fixes its mix of
                     # macroscopic-strain and body-force launches
-                    "algorithmic_bytes_per_launch": 2.990866e+08,
+                    "algorithmic_bytes_per_launch": 2.995948e+08,
                     "launch": "step_kernel_b<float,1,PAL>, mean over all launches of a full solve"}
 
 
@@ -80,7 +80,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=191, help="grid size of the sphere pack")
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--strouhal", type=float, default=2.0)
+    # St is a numerical parameter of the APT iteration; its best value depends on the microstructure
+    # (the library default is 2.0).  For the 191^3 random 10% pore packs a sweep over St in [1.5, 5]
+    # (two seeds) gave the fewest iterations at 3.0-3.5 and the most robust counts at 3.0, so that is
+    # this workload's value; the other workloads keep the library default unless given.
+    ap.add_argument("--strouhal", type=float, default=None,
+                    help="APT Strouhal number (default: 3.0 for spheres191, the library's 2.0 otherwise)")
     ap.add_argument("--check-every", type=int, default=200)
     ap.add_argument("--no-fp64-baseline", action="store_true", help="skip the FP64 one-load-at-a-time solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -118,7 +123,11 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     if a.workload != "spheres191":
+        if a.strouhal is None:
+            a.strouhal = 2.0
         return other_workload(a, torch, synth, ceff, dev)
+    if a.strouhal is None:
+        a.strouhal = 3.0
     m = synth.workload_spheres191(n=a.n)
     N = m.phase.size
     print(f"# workload {m.info}", file=sys.stderr, flush=True)

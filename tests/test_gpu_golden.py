@@ -5,8 +5,9 @@ sphere pack (Jacobi-PCG to rtol 1e-11), written by
 tests/golden/make_spheres191_golden.py, which calls only the oracle.  The GPU
 solves the same image in the benchmark's configuration (mixed precision, the library's own choice of
 load fusion -- one load after another at this size -- with the moduli read
-from the phase image, rtol 1e-8), with the six loads forced into one launch,
-and in the plain FP64 one-load-at-a-time configuration."""
+from the phase image, rtol 1e-8, Strouhal number 3.0), with the library's
+default Strouhal number, with the six loads forced into one launch, and in
+the plain FP64 one-load-at-a-time configuration."""
 import hashlib
 import json
 import os
@@ -31,14 +32,15 @@ def golden():
     return m, g
 
 
-@pytest.mark.parametrize("precision,fuse", [("mixed", "auto"), ("mixed", True), ("fp64", False)])
-def test_spheres191_matches_oracle_columns(golden, precision, fuse):
+@pytest.mark.parametrize("precision,fuse,strouhal", [("mixed", "auto", 3.0), ("mixed", "auto", 2.0),
+                                                     ("mixed", True, 2.0), ("fp64", False, 2.0)])
+def test_spheres191_matches_oracle_columns(golden, precision, fuse, strouhal):
     p = need_gpu()
     m, g = golden
-    announce("spheres191 golden", precision, fuse, sorted(g["columns"]))
+    announce("spheres191 golden", precision, fuse, strouhal, sorted(g["columns"]))
     with p.Context() as c:
         c.set_phases(m.phase, m.K_tab, m.G_tab)
-        C, info = c.solve(precision=precision, fuse_loads=fuse, rtol=1e-8)
+        C, info = c.solve(precision=precision, fuse_loads=fuse, rtol=1e-8, strouhal=strouhal)
     assert info["status"] == 0
     if fuse == "auto":
         assert info["stats"]["fused_loads"] == 0 and info["stats"]["phase_moduli"] == 1
