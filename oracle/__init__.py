@@ -54,9 +54,9 @@ def lib():
         L.or_pcg_ortho.restype = ctypes.c_int64
         L.or_apt_disp.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int64, _dp, _dp]
-        L.or_residual_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp]
-        L.or_average_stress_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp]
-        L.or_pcg_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp]
+        L.or_residual_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
+        L.or_average_stress_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
+        L.or_pcg_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp, ctypes.c_int]
         L.or_pcg_walls.restype = ctypes.c_int64
         _lib = L
     return _lib
@@ -243,7 +243,8 @@ def ceff_ortho(C9, h=(1.0, 1.0, 1.0), rtol=1e-11, loads=range(6), max_iter=1_000
 
 def apt_disp(J, nsteps, courant, strouhal, K=None, G=None, C9=None, h=(1.0, 1.0, 1.0), walls=False):
     """Displacement-form APT iterate u^nsteps and u^(nsteps-1) (each (3, nz, ny, nx)) for
-    isotropic (K, G) or orthotropic (C9) cells, from u^0 = 0; walls: rigid free-slip walls."""
+    isotropic (K, G) or orthotropic (C9) cells, from u^0 = 0; walls: the wall test of
+    load J (normal test for J < 3, simple-shear test for J >= 3)."""
     if C9 is not None:
         C9, dims, hh = _prep9(C9, h)
         sh = C9.shape[1:]
@@ -255,54 +256,70 @@ def apt_disp(J, nsteps, courant, strouhal, K=None, G=None, C9=None, h=(1.0, 1.0,
         Kp, Gp, cp = _d(K), _d(G), None
     u = np.empty((3,) + sh)
     up = np.empty((3,) + sh)
-    lib().or_apt_disp(dims.ctypes.data_as(_ip), _d(hh), Kp, Gp, cp, int(bool(walls)), _d(unit_strain(J)), courant,
+    lib().or_apt_disp(dims.ctypes.data_as(_ip), _d(hh), Kp, Gp, cp, wall_mode(J) if walls else 0, _d(unit_strain(J)), courant,
                       strouhal, nsteps, _d(u), _d(up))
     return u, up
 
 
-# ---- rigid, free-slip walls (the paper's direct tests) ------------------------------
+# ---- wall boundaries (the paper's direct tests) --------------------------------------
 #
 # The box boundary in direction d is the grid plane of index 0 in d: the
-# fluctuation of the d-faces there is held at zero and the edges lying in a
-# boundary plane carry no shear stress.  Only the normal loads (J = 0, 1, 2) make
-# sense with such walls.
+# fluctuation of the d-faces there is held at zero.  Normal test (loads 0..2,
+# mode 1): the edges lying in a boundary plane carry no shear stress.
+# Simple-shear test of the Voigt shear component J (loads 3..5, mode J): the
+# loaded walls also hold the sheared component tangentially, through split half
+# edges (see ceff_oracle.c).
 
-def residual_walls(K, G, E, u, h=(1.0, 1.0, 1.0)):
+def wall_mode(J):
+    """Wall test of load J: 1 (normal test) for J < 3, else J (simple-shear test)."""
+    return 1 if J < 3 else int(J)
+
+
+def _mode_of(E):
+    E = np.asarray(E, np.float64)
+    sh = [s for s in (3, 4, 5) if E[s] != 0.0]
+    return sh[0] if len(sh) == 1 else 1
+
+
+def residual_walls(K, G, E, u, h=(1.0, 1.0, 1.0), mode=None):
+    """Residual under the walls of `mode` (default: the simple-shear test of E's one
+    shear component if it has exactly one, else the normal test)."""
+    mode = _mode_of(E) if mode is None else mode
     K, G, dims, hh = _prep(K, G, h)
     u = np.ascontiguousarray(u, np.float64).reshape((3,) + K.shape)
     out = np.empty((3,) + K.shape)
     lib().or_residual_walls(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(np.asarray(E, np.float64)), _d(u),
-                            _d(out))
+                            _d(out), mode)
     return out
 
 
-def average_stress_walls(K, G, E, u, h=(1.0, 1.0, 1.0)):
+def average_stress_walls(K, G, E, u, h=(1.0, 1.0, 1.0), mode=None):
+    mode = _mode_of(E) if mode is None else mode
     K, G, dims, hh = _prep(K, G, h)
     u = np.ascontiguousarray(u, np.float64).reshape((3,) + K.shape)
     out = np.empty(6)
     lib().or_average_stress_walls(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(np.asarray(E, np.float64)),
-                                  _d(u), _d(out))
+                                  _d(u), _d(out), mode)
     return out
 
 
 def solve_load_walls(K, G, J, h=(1.0, 1.0, 1.0), rtol=1e-11, max_iter=1_000_000):
-    if J > 2:
-        raise ValueError("walls: normal loads only")
     K, G, dims, hh = _prep(K, G, h)
     u = np.zeros((3,) + K.shape)
     rel = np.zeros(1)
     it = lib().or_pcg_walls(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(unit_strain(J)), rtol, max_iter,
-                            _d(u), _d(rel))
+                            _d(u), _d(rel), wall_mode(J))
     return u, int(it), float(rel[0])
 
 
 def ceff_walls(K, G, h=(1.0, 1.0, 1.0), rtol=1e-11, loads=(0, 1, 2)):
-    """Columns J = 0, 1, 2 of C* from the wall tests (other entries NaN)."""
+    """Columns `loads` of C* from the wall tests (other entries NaN): column J < 3 from
+    the normal test of J, column J >= 3 from the simple-shear test of J."""
     C = np.full((6, 6), np.nan)
     info = {}
     for J in loads:
         u, it, rel = solve_load_walls(K, G, J, h, rtol)
-        C[:, J] = average_stress_walls(K, G, unit_strain(J), u, h)
+        C[:, J] = average_stress_walls(K, G, unit_strain(J), u, h, mode=wall_mode(J))
         info[J] = (it, rel)
     return C, info
 

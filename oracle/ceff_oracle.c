@@ -40,7 +40,19 @@
  * the last plane).  The displacement fluctuation of the d-faces there is held at
  * zero, so the total displacement of both walls is the macroscopic strain's, and
  * the shear stress of every edge lying in a boundary plane is zero (free slip;
- * those edges would couple the two sides of the box across the wrap).
+ * those edges would couple the two sides of the box across the wrap).  This is
+ * the normal compression test (walls = 1, normal loads).
+ *
+ * Simple-shear test of the Voigt shear component s (walls = s: 3 yz, 4 xz, 5 xy;
+ * the same appendix): the load shears direction d across the walls normal to e,
+ * (d, e) = (y, z), (x, z), (x, y).  The faces are held as above.  The loaded
+ * e-walls are also held tangentially in d (no slip): each s-edge lying in the
+ * e-boundary plane is split into two half edges, one per side of the box, whose
+ * strain takes the u_d fluctuation across the half cell to the wall, where it is
+ * zero, and whose modulus is the harmonic mean of the two cells on that side;
+ * each half counts for half a node in the volume average.  The s-edges lying in
+ * the d-boundary plane only are computed as in the periodic medium (the walls
+ * normal to d transmit the applied shear).  All other boundary edges are free.
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC (see oracle/build.py).
  * Arrays: x fastest, linear index i + nx*(j + ny*k); vector fields are stored
@@ -58,7 +70,8 @@ typedef struct {
 } grid_t;
 
 /* Material: isotropic K, G per cell, or nine orthotropic constants per cell (c9 != NULL);
- * walls != 0: rigid, free-slip walls instead of periodic boundaries. */
+ * walls: 0 periodic boundaries, 1 the walls of the normal test, 3..5 the walls of the
+ * simple-shear test of that Voigt shear component (see the header). */
 typedef struct {
     const double *K, *G, *c9;
     int walls;
@@ -93,6 +106,49 @@ static double edge_shear(const grid_t *g, const mat_t *m, int plane, int64_t i, 
     const int64_t N = g->nx * g->ny * g->nz;
     const double *C = m->c9 + (plane == 0 ? 8 : (plane == 1 ? 7 : 6)) * N;
     return edge_modulus(g, C, plane, i, j, k);
+}
+
+/* Voigt shear component s = 3, 4, 5 (yz, xz, xy): the direction it shears in the
+ * simple-shear test and the normal of the loaded walls. */
+static const int pair_d[6] = {0, 0, 0, 1, 0, 0}, pair_e[6] = {0, 0, 0, 2, 2, 1};
+
+/* Treatment of the s-edge with index (i, j, k) under the wall conditions:
+ * 0 as in the periodic medium, 1 no shear stress (free slip), 2 split into two
+ * half edges (no slip on the loaded walls of the simple-shear test s). */
+static int wall_edge(const mat_t *m, int s, int64_t i, int64_t j, int64_t k) {
+    if (!m->walls) return 0;
+    const int64_t p[3] = {i, j, k};
+    const int in_d = p[pair_d[s]] == 0, in_e = p[pair_e[s]] == 0;
+    if (!in_d && !in_e) return 0;
+    if (m->walls == s) return in_e ? 2 : 0;
+    return 1;
+}
+
+/* Shear stress of one half of the split s-edge (i, j, k) (index 0 in e) of the
+ * simple-shear test s.  side 0: the half in the cells of index 0 in e; side 1:
+ * the half in the cells of index n_e - 1.  The derivative of u_d across the half
+ * cell to the wall is one-sided, the wall's fluctuation being zero; the
+ * tangential derivative of u_e is taken between the wall faces, as inside. */
+static double half_edge(const grid_t *g, const mat_t *m, int s, const double E[6], const double *u, int64_t i,
+                        int64_t j, int64_t k, int side) {
+    const int64_t N = g->nx * g->ny * g->nz;
+    const int d = pair_d[s], e = pair_e[s];
+    const int64_t n[3] = {g->nx, g->ny, g->nz};
+    const double h[3] = {g->hx, g->hy, g->hz};
+    int64_t p[3] = {i, j, k}, q[3];
+    p[e] = side ? n[e] - 1 : 0;
+    memcpy(q, p, sizeof q);
+    q[d] -= 1;
+    const double *Gs = m->c9 ? m->c9 + (int64_t)(s + 3) * N : m->G;
+    const int64_t c0 = at(g, p[0], p[1], p[2]), c1 = at(g, q[0], q[1], q[2]);
+    const double Gh = 2.0 / (1.0 / Gs[c0] + 1.0 / Gs[c1]);
+    const double dud = (side ? -2.0 : 2.0) * u[d * N + c0] / h[e];
+    int64_t w0[3] = {i, j, k}, w1[3];
+    w0[e] = 0;
+    memcpy(w1, w0, sizeof w1);
+    w1[d] -= 1;
+    const double due = (u[e * N + at(g, w0[0], w0[1], w0[2])] - u[e * N + at(g, w1[0], w1[1], w1[2])]) / h[d];
+    return 2.0 * Gh * (E[s] + 0.5 * (dud + due));
 }
 
 /* Total strain (E + grad u) at every cell and edge.
@@ -144,11 +200,8 @@ static void hooke(const grid_t *g, const mat_t *m, const double *eps, double *si
                 sig[3 * N + c] = 2.0 * edge_shear(g, m, 2, i, j, k) * eps[3 * N + c];
                 sig[4 * N + c] = 2.0 * edge_shear(g, m, 1, i, j, k) * eps[4 * N + c];
                 sig[5 * N + c] = 2.0 * edge_shear(g, m, 0, i, j, k) * eps[5 * N + c];
-                if (m->walls) {  /* edges in a boundary plane carry no shear stress */
-                    if (j == 0 || k == 0) sig[3 * N + c] = 0.0;
-                    if (i == 0 || k == 0) sig[4 * N + c] = 0.0;
-                    if (i == 0 || j == 0) sig[5 * N + c] = 0.0;
-                }
+                for (int s = 3; s < 6; s++)  /* free boundary edges carry no shear stress */
+                    if (wall_edge(m, s, i, j, k) == 1) sig[s * N + c] = 0.0;
             }
 }
 
@@ -183,12 +236,22 @@ static double dot(int64_t n, const double *a, const double *b) {
 
 /* ---- exported entry points ------------------------------------------------ */
 
+/* Loop header over the split edges of the simple-shear test s: the s-edges of
+ * index 0 in e. */
+#define FOR_SPLIT_EDGES(g, s, i, j, k)                                            \
+    for (int64_t k = 0; k < (pair_e[s] == 2 ? 1 : (g)->nz); k++)                   \
+        for (int64_t j = 0; j < (pair_e[s] == 1 ? 1 : (g)->ny); j++)               \
+            for (int64_t i = 0; i < (g)->nx; i++)
+
+/* Stresses; the s-edges split by a simple-shear test hold their side-0 half. */
 static void m_stress(const grid_t *g, const mat_t *m, const double E[6], const double *u, double *sig) {
     const int64_t N = g->nx * g->ny * g->nz;
     double *eps = malloc(sizeof(double) * 6 * N);
     strains(g, E, u, eps);
     hooke(g, m, eps, sig);
     free(eps);
+    const int s = m->walls;
+    if (s >= 3) FOR_SPLIT_EDGES(g, s, i, j, k) sig[s * N + at(g, i, j, k)] = half_edge(g, m, s, E, u, i, j, k, 0);
 }
 
 /* Zero the entries of a face field (3N) that belong to wall faces (held fixed). */
@@ -209,6 +272,18 @@ static void m_residual(const grid_t *g, const mat_t *m, const double E[6], const
     double *sig = malloc(sizeof(double) * 6 * N);
     m_stress(g, m, E, u, sig);
     divergence(g, sig, r);
+    const int s = m->walls;
+    if (s >= 3) {
+        /* the u_d faces of index n_e - 1 meet the split edges from their side-1 half */
+        const int d = pair_d[s], e = pair_e[s];
+        const double he = e == 1 ? g->hy : g->hz;
+        FOR_SPLIT_EDGES(g, s, i, j, k) {
+            int64_t p[3] = {i, j, k};
+            p[e] = (e == 1 ? g->ny : g->nz) - 1;
+            const int64_t ce = at(g, i, j, k), cf = at(g, p[0], p[1], p[2]);
+            r[d * N + cf] += (half_edge(g, m, s, E, u, i, j, k, 1) - sig[s * N + ce]) / he;
+        }
+    }
     if (m->walls) mask_walls(g, r); /* a wall face is held, its out-of-balance force is the reaction */
     free(sig);
 }
@@ -217,6 +292,12 @@ static void m_average_stress(const grid_t *g, const mat_t *m, const double E[6],
     const int64_t N = g->nx * g->ny * g->nz;
     double *sig = malloc(sizeof(double) * 6 * N);
     m_stress(g, m, E, u, sig);
+    const int sw = m->walls;
+    if (sw >= 3) /* each half of a split edge stands for half a node */
+        FOR_SPLIT_EDGES(g, sw, i, j, k) {
+            const int64_t c = at(g, i, j, k);
+            sig[sw * N + c] = 0.5 * (sig[sw * N + c] + half_edge(g, m, sw, E, u, i, j, k, 1));
+        }
     for (int c = 0; c < 6; c++) {
         double s = 0.0;
         for (int64_t t = 0; t < N; t++) s += sig[c * N + t];
@@ -445,25 +526,25 @@ void or_apt_disp(const int64_t dims[3], const double h[3], const double *K, cons
 }
 
 /* Wall-boundary versions (isotropic cells) of the residual, the stress averages
- * and the PCG solve. */
+ * and the PCG solve; mode = 1 (normal test) or 3..5 (simple-shear test). */
 void or_residual_walls(const int64_t dims[3], const double h[3], const double *K, const double *G,
-                       const double E[6], const double *u, double *r) {
+                       const double E[6], const double *u, double *r, int mode) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL, 1};
+    mat_t m = {K, G, NULL, mode};
     m_residual(&g, &m, E, u, r);
 }
 
 void or_average_stress_walls(const int64_t dims[3], const double h[3], const double *K, const double *G,
-                             const double E[6], const double *u, double out[6]) {
+                             const double E[6], const double *u, double out[6], int mode) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL, 1};
+    mat_t m = {K, G, NULL, mode};
     m_average_stress(&g, &m, E, u, out);
 }
 
 int64_t or_pcg_walls(const int64_t dims[3], const double h[3], const double *K, const double *G, const double E[6],
-                     double rtol, int64_t max_iter, double *u, double *relres) {
+                     double rtol, int64_t max_iter, double *u, double *relres, int mode) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL, 1};
+    mat_t m = {K, G, NULL, mode};
     return m_pcg(&g, &m, E, rtol, max_iter, u, relres, NULL, 0);
 }
 

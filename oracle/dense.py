@@ -116,33 +116,78 @@ def _energy_weights(K, G):
     return apply
 
 
-def wall_masks(shape):
-    """Rigid free-slip walls on the periodic layout: (free, edge_keep).  free (3N,
-    bool) marks face displacements that may move (not the d-faces of the plane of
-    index 0 in d); edge_keep (3, N) is 0 for edges lying in a boundary plane
-    (order yz, xz, xy), whose shear stiffness is dropped."""
+# Simple-shear wall test of the Voigt shear component s (3 yz, 4 xz, 5 xy): the
+# direction d it shears and the normal e of the loaded walls.
+SHEAR_PAIR = {3: (1, 2), 4: (0, 2), 5: (0, 1)}
+
+
+def wall_masks(shape, mode=1):
+    """Wall layout on the periodic grid: (free, edge_keep).  free (3N, bool) marks
+    face displacements that may move (not the d-faces of the plane of index 0 in
+    d).  edge_keep (3, N) (order yz, xz, xy) is 0 for edges lying in a boundary
+    plane, whose shear stiffness is dropped (free slip), except, for the
+    simple-shear test mode = s, the s-edges lying in the d-wall plane only, which
+    keep theirs; the s-edges in the loaded e-wall plane are dropped here and
+    replaced by the half edges of split_edge_strains."""
     nz, ny, nx = shape
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    idx = (i, j, k)
     free = np.concatenate([(i != 0).ravel(), (j != 0).ravel(), (k != 0).ravel()])
-    keep = np.stack([((j != 0) & (k != 0)).ravel(), ((i != 0) & (k != 0)).ravel(),
-                     ((i != 0) & (j != 0)).ravel()]).astype(float)
-    return free, keep
+    keep = []
+    for comp, (a, b) in SHEAR_PAIR.items():
+        if mode == comp:
+            keep.append((idx[b] != 0).ravel())
+        else:
+            keep.append(((idx[a] != 0) & (idx[b] != 0)).ravel())
+    return free, np.stack(keep).astype(float)
+
+
+def _planes(shape, e):
+    ae = _AX["xyz"[e]]
+    first = [slice(None)] * 3; first[ae] = slice(0, 1)
+    last = [slice(None)] * 3; last[ae] = slice(shape[ae] - 1, shape[ae])
+    return tuple(first), tuple(last)
+
+
+def split_edge_strains(u, E, s, h=(1.0, 1.0, 1.0)):
+    """Tensor shear strains of the two halves of every s-edge on the loaded wall
+    plane (index 0 in e) of the simple-shear test s: (first, last), the halves in
+    the cells of index 0 and n_e - 1 in e.  The wall holds the u_d fluctuation at
+    zero, so each half differentiates u_d over half a cell; the tangential
+    derivative of u_e is taken between the wall faces."""
+    d, e = SHEAR_PAIR[s]
+    first, last = _planes(u.shape[1:], e)
+    tang = _bwd(u[e], _AX["xyz"[d]])[first] / h[d]
+    return (E[s] + 0.5 * (2.0 * u[d][first] / h[e] + tang),
+            E[s] + 0.5 * (-2.0 * u[d][last] / h[e] + tang))
+
+
+def split_edge_moduli(Gs, s):
+    """Harmonic mean of the shear constant over the two cells of each half edge."""
+    d, e = SHEAR_PAIR[s]
+    first, last = _planes(Gs.shape, e)
+    ad = _AX["xyz"[d]]
+    f, l = 1.0 / Gs[first], 1.0 / Gs[last]
+    return 2.0 / (f + np.roll(f, 1, axis=ad)), 2.0 / (l + np.roll(l, 1, axis=ad))
 
 
 def solve_dense(K, G, E, h=(1.0, 1.0, 1.0), C9=None, walls=False):
     """Displacement fluctuation minimising the discrete strain energy (3, nz, ny, nx).
-    Isotropic (K, G) cells, or orthotropic cells when C9 is given; walls: rigid
-    free-slip walls (pinned wall faces, no shear energy on boundary edges)."""
+    Isotropic (K, G) cells, or orthotropic cells when C9 is given.  walls: False
+    (periodic), True or 1 (normal-test walls: pinned wall faces, no shear energy on
+    boundary edges) or 3..5 (the simple-shear test of that component: as 1, with
+    the half edges of the loaded walls, each of half an edge's volume)."""
     shape = K.shape if C9 is None else C9.shape[1:]
     N = int(np.prod(shape))
     zero = np.zeros(6)
+    mode = 1 if walls is True else int(walls)
     B = np.empty((6 * N, 3 * N))
     for col in range(3 * N):
         u = np.zeros(3 * N); u[col] = 1.0
         B[:, col] = strain_field(u.reshape((3,) + shape), zero, h).reshape(6 * N)
     Dapply0 = _energy_weights(K, G) if C9 is None else _energy_weights_c9(C9)
-    if walls:
-        free, keep = wall_masks(shape)
+    if mode:
+        free, keep = wall_masks(shape, mode)
 
         def Dapply(eps):
             out = Dapply0(eps)
@@ -157,26 +202,46 @@ def solve_dense(K, G, E, h=(1.0, 1.0, 1.0), C9=None, walls=False):
     A = B.T @ DB
     e0 = strain_field(np.zeros((3,) + shape), E, h).reshape(6, N)
     rhs = -B.T @ Dapply(e0).reshape(6 * N)
+    if mode >= 3:
+        # half edges: energy (1/2) * 2 C_h eps^2 each, so weight 2 C_h
+        Gs = G if C9 is None else C9[mode + 3]
+        w = np.concatenate([m.ravel() for m in split_edge_moduli(Gs, mode)]) * 2.0
+        M = w.size
+        Bx = np.empty((M, 3 * N))
+        for col in range(3 * N):
+            u = np.zeros(3 * N); u[col] = 1.0
+            Bx[:, col] = np.concatenate([a.ravel() for a in split_edge_strains(u.reshape((3,) + shape), zero,
+                                                                                 mode, h)])
+        Bx[:, ~free] = 0.0
+        ex = np.concatenate([a.ravel() for a in split_edge_strains(np.zeros((3,) + shape), E, mode, h)])
+        A = A + Bx.T @ (w[:, None] * Bx)
+        rhs = rhs - Bx.T @ (w * ex)
     u, *_ = np.linalg.lstsq(A, rhs, rcond=1e-13)
     return u.reshape((3,) + shape), A
 
 
-def stress_walls(K, G, eps):
-    """Stresses with the boundary edges of the wall layout carrying none."""
-    sig = stress_field(K, G, eps)
-    _, keep = wall_masks(K.shape)
+def average_stress_walls(K, G, u, E, mode, h=(1.0, 1.0, 1.0)):
+    """Volume averages of the six stresses under the walls of `mode`: free boundary
+    edges carry none; a split edge contributes the mean of its two halves."""
+    sig = stress_field(K, G, strain_field(u, E, h))
+    _, keep = wall_masks(K.shape, mode)
     sig[3:] *= keep.reshape((3,) + K.shape)
-    return sig
+    out = sig.reshape(6, -1).sum(axis=1)
+    if mode >= 3:
+        (eb, et), (gb, gt) = split_edge_strains(u, E, mode, h), split_edge_moduli(G, mode)
+        out[mode] += 0.5 * np.sum(2.0 * gb * eb + 2.0 * gt * et)
+    return out / K.size
 
 
-def ceff_dense_walls(K, G, h=(1.0, 1.0, 1.0)):
-    """Columns 0..2 of C* for rigid free-slip walls, by dense energy minimisation."""
+def ceff_dense_walls(K, G, h=(1.0, 1.0, 1.0), loads=(0, 1, 2)):
+    """Columns `loads` of C* from the wall tests by dense energy minimisation: the
+    normal test for J < 3, the simple-shear test of J for J >= 3 (others NaN)."""
     C = np.full((6, 6), np.nan)
-    for J in range(3):
-        E = np.zeros(6); E[J] = 1.0
-        u, _ = solve_dense(K, G, E, h, walls=True)
-        sig = stress_walls(K, G, strain_field(u, E, h))
-        C[:, J] = sig.reshape(6, -1).mean(axis=1)
+    for J in loads:
+        E = np.zeros(6); E[J] = 1.0 if J < 3 else 0.5
+        mode = 1 if J < 3 else J
+        u, _ = solve_dense(K, G, E, h, walls=mode)
+        C[:, J] = average_stress_walls(K, G, u, E, mode, h)
     return C
 
 
