@@ -143,19 +143,28 @@ ceff_status ceff_set_phases(ceff_ctx* ctx, const uint8_t* phase, int where, int 
 ceff_status ceff_set_stiffness(ceff_ctx* ctx, const void* c, int ncomp, int dtype, int where);
 
 /* Boundary conditions of the context's problem (default CEFF_BC_PERIODIC).
- * CEFF_BC_WALLS: the paper's direct tests (appendix on boundary conditions:
- * normal compression and the tests for the off-diagonal constants): every
- * face of the box is a rigid wall in its normal direction and free to slip
- * tangentially.  On the periodic grid layout the box boundary in direction d is
- * the grid plane of index 0 in d; there the displacement fluctuation of the
- * d-faces is held at zero (both walls move with the macroscopic strain, e.g.
- * by E_zz * L_z in z) and edges lying in a boundary plane carry no shear
- * stress.  Only the normal loads (bits 0-2 of ceff_solve's mask) are defined:
- * each gives a column of the confined-compression stiffness, whose upper 3x3
- * block is what the paper's C11, C22, C33 and its formulas for C12, C13, C23
- * compute.  The loads run one after another; orthotropic cells, the batch
- * path and the gradient need periodic boundaries (CEFF_EUNSUPPORTED).  Applies
- * to ceff_solve, ceff_apt_steps, ceff_residual and ceff_average_stress. */
+ * CEFF_BC_WALLS: the paper's direct tests (appendix on boundary conditions).
+ * On the periodic grid layout the box boundary in direction d is the grid
+ * plane of index 0 in d; there the displacement fluctuation of the d-faces is
+ * held at zero, so every face of the box is a rigid wall in its normal
+ * direction that moves with the macroscopic strain (e.g. by E_zz * L_z in z).
+ *   Loads 0-2 (normal compression and the tests for the off-diagonal
+ *   constants): every edge lying in a boundary plane carries no shear stress
+ *   (free slip).  Each load gives a column of the confined-compression
+ *   stiffness, whose upper 3x3 block is what the paper's C11, C22, C33 and its
+ *   formulas for C12, C13, C23 compute.
+ *   Loads 3-5 (simple shear of yz, xz, xy): the load shears direction d = y, x,
+ *   x across the walls normal to e = z, z, y.  Those loaded walls also hold u_d
+ *   (no slip): each of the load's own edges in the e-boundary plane is split
+ *   into two half edges, one per side of the box, with the one-sided
+ *   derivative to the wall and the harmonic mean of that side's two cells,
+ *   each counting as half an edge in the average.  The load's own edges in the
+ *   d-boundary plane are computed as inside; all other boundary edges are free.
+ *   The mean shear strain is then exactly the load's, and C(J, J) is the
+ *   paper's C44, C55, C66.
+ * The loads run one after another; orthotropic cells, the batch path and the
+ * gradient need periodic boundaries (CEFF_EUNSUPPORTED).  Applies to
+ * ceff_solve, ceff_apt_steps, ceff_residual and ceff_average_stress. */
 ceff_status ceff_set_boundary(ceff_ctx* ctx, int mode);
 
 /* Solve the unit loads in load_mask (bit J = Voigt column J, 0..5) and write

@@ -240,8 +240,8 @@ class Context:
         self.h_spacing = tuple(map(float, h))
 
     def set_boundary(self, mode):
-        """"periodic" (default) or "walls" (rigid, free-slip walls: the paper's direct tests;
-        normal loads only)."""
+        """"periodic" (default) or "walls" (the paper's direct tests: loads 0..2 run the
+        normal test with rigid, free-slip walls, loads 3..5 the simple-shear test)."""
         ceff_set_boundary(self.h, {"periodic": _lib.CEFF_BC_PERIODIC, "walls": _lib.CEFF_BC_WALLS}[mode])
 
     def set_phases(self, phase, K_tab, G_tab, h=(1.0, 1.0, 1.0)):

@@ -590,6 +590,7 @@ struct Engine {
       od.walls = s.walls;
       for (int J : Js) {
         const int l = slot_of(J);
+        h_in[si].wshear[l] = od.wshear[l] = s.walls && J >= 3 ? J : 0;
         for (int b = 0; b < 2; ++b) {
           HIPCK(c, ubuf[si][b * kMaxLoads + l].alloc(sizeof(T) * 3 * N));
           HIPCK(c, launch_fill<T>(ubuf[si][b * kMaxLoads + l].as<T>(), 3 * N, T(0), c->s));
@@ -900,7 +901,7 @@ ceff_status stress_average(ceff_ctx* c, const SampleIn& s, int J, const double* 
                                          o6.as<double>(), c->s));
   else
     HIPCK(c, launch_average_stress(s.nx, s.ny, s.nz, s.h, s.K64, s.G64, E, u, part.as<double>(), cap,
-                                   o6.as<double>(), s.walls, c->s));
+                                   o6.as<double>(), s.walls ? (J >= 3 ? J : 1) : 0, c->s));
   HIPCK(c, hipMemcpyAsync(out6, o6.p, sizeof(double) * 6, hipMemcpyDeviceToHost, c->s));
   HIPCK(c, hipStreamSynchronize(c->s));
   for (int q = 0; q < 6; ++q) out6[q] /= (double)N;
@@ -1250,8 +1251,6 @@ ceff_status ceff_solve(ceff_ctx* c, uint32_t load_mask, const ceff_solve_opts* o
   if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(c, CEFF_EINVAL, "bad history buffer");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
   const bool walls = c->boundary == CEFF_BC_WALLS;
-  if (walls && (load_mask & 0x38u))
-    return fail(c, CEFF_EINVAL, "with wall boundaries only the normal loads (bits 0-2) are defined");
   if (walls && c->ortho) return fail(c, CEFF_EUNSUPPORTED, "wall boundaries with orthotropic cells");
   STCK(begin_call(c));
   const auto t0 = std::chrono::steady_clock::now();

@@ -32,10 +32,14 @@ struct SampleDesc {
   // (component-major) or nullptr; when set, K, G and the phase image are unused
   // and the orthotropic kernels run (TileShape::ortho).
   const T* cst;
-  // 1: rigid, free-slip walls instead of periodic boundaries: the d-faces of the
-  // grid plane of index 0 in d are held, and edges lying in such a plane carry
-  // no shear stress (one load per block; TileShape::walls)
+  // 1: rigid walls instead of periodic boundaries: the d-faces of the grid
+  // plane of index 0 in d are held, and edges lying in such a plane carry no
+  // shear stress (one load per block; TileShape::walls).  wshear[l] = 3, 4, 5
+  // makes load slot l the simple-shear test of that Voigt shear component: its
+  // own component's boundary edges are computed as inside on the walls normal
+  // to the sheared direction and split into two half edges on the loaded walls.
   int walls;
+  int wshear[kMaxLoads];
   T E[kMaxLoads][6];          // macroscopic tensor strain per load: xx yy zz yz xz xy
   unsigned active;            // bit l: load l is iterated
   int work_begin, work_end;   // this sample's work items [begin, end)
@@ -98,6 +102,8 @@ hipError_t launch_finalize_norms(const int* d_ranges /* 2 per sample */, int nsa
 
 // FP64 volume averages of the six stresses of u (3N) under strain E: writes
 // block partials (6 per block) then the final 6 sums (not yet divided by N).
+// walls: 0 periodic, 1 the normal-test walls, 3..5 the simple-shear test of
+// that Voigt shear component (see SampleDesc::wshear).
 hipError_t launch_average_stress(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K,
                                  const double* G, const double E[6], const double* u, double* partials,
                                  int nblocks_cap, double* out6, int walls, hipStream_t s);

@@ -280,8 +280,10 @@ step_kernel(const SampleDesc<T>* __restrict__ samples,
     const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
     const int64_t k0 = (int64_t)wi.kz * sd.kc;
     const int64_t k1 = k0 + sd.kc < nz ? k0 + sd.kc : nz;
-    // wall boundaries: this column lies in the x (y) boundary plane
+    // wall boundaries: this column lies in the x (y) boundary plane; wsh: the
+    // Voigt shear component whose simple-shear test this load is (0: none)
     const bool wx = WALLS && wrap_idx(gi, nx) == 0, wy = WALLS && wrap_idx(gj, ny) == 0;
+    const int wsh = WALLS ? sd.wshear[s0] : 0;
 
     const GLOBAL_AS T* __restrict__ Kf = gconst(sd.K);
     const GLOBAL_AS T* __restrict__ Gf = gconst(sd.G);
@@ -419,15 +421,41 @@ step_kernel(const SampleDesc<T>* __restrict__ samples,
         T sxy = G2xy * (E[5] + T(0.5) * ((ux[l] - sUx[ym]) * rhy + (uy[l] - sUy[xm]) * rhx));
         T sxz_n = G2xz * (E[4] + T(0.5) * ((unx[l] - ux[l]) * rhz + (unz[l] - sUz[xm]) * rhx));
         T syz_n = G2yz * (E[3] + T(0.5) * ((uny[l] - uy[l]) * rhz + (unz[l] - sUz[ym]) * rhy));
-        if constexpr (WALLS) {  // edges in a boundary plane: no shear stress
+        // published xy-edge stress and carried xz/yz-edge stresses (they differ
+        // from the thread's own only at the split edges of a simple-shear test)
+        T sxy_s = sxy, sxz_k = sxz_n, syz_k = syz_n;
+        if constexpr (WALLS) {
+          // free-slip boundary edges, the simple-shear test's own component
+          // computed as inside on the walls normal to the sheared direction and
+          // split into one half per side on the loaded walls (one-sided
+          // derivative to the wall, harmonic mean of the half's two cells:
+          // 2 G = 4 / (1/G + 1/G'))
           const bool wzn = k + 1 == nz || k + 1 == 0;  // xz/yz-edges owned here sit between k and k+1
-          if (wx || wy) sxy = T(0);
-          if (wx || wzn) sxz_n = T(0);
-          if (wy || wzn) syz_n = T(0);
+          if ((wx || wy) && wsh != 5) sxy = T(0);
+          if ((wx || wzn) && wsh != 4) sxz_n = T(0);
+          if ((wy || wzn) && wsh != 3) syz_n = T(0);
+          sxy_s = sxy;
+          sxz_k = sxz_n;
+          syz_k = syz_n;
+          if (wsh == 5 && wy) {  // own half in the cells j = 0, published half in j = ny - 1
+            const T t = T(0.5) * (uy[l] - sUy[xm]) * rhx;
+            sxy = T(4) * recip(recip(gk[tid]) + recip(gk[xm])) * (E[5] + ux[l] * rhy + t);
+            sxy_s = T(4) * recip(recip(gk[ym]) + recip(gk[xmym])) * (E[5] - sUx[ym] * rhy + t);
+          }
+          if (wsh == 4 && wzn) {  // upper edge of plane nz - 1, carried as the lower edge of plane 0
+            const T t = T(0.5) * (unz[l] - sUz[xm]) * rhx;
+            sxz_n = T(4) * recip(recip(gk[tid]) + recip(gk[xm])) * (E[4] - ux[l] * rhz + t);
+            sxz_k = T(4) * recip(recip(gn[tid]) + recip(gn[xm])) * (E[4] + unx[l] * rhz + t);
+          }
+          if (wsh == 3 && wzn) {
+            const T t = T(0.5) * (unz[l] - sUz[ym]) * rhy;
+            syz_n = T(4) * recip(recip(gk[tid]) + recip(gk[ym])) * (E[3] - uy[l] * rhz + t);
+            syz_k = T(4) * recip(recip(gn[tid]) + recip(gn[ym])) * (E[3] + uny[l] * rhz + t);
+          }
         }
         sSxx[tid] = sxx;
         sSyy[tid] = syy;
-        sSxy[tid] = sxy;
+        sSxy[tid] = sxy_s;
         sSxz[tid] = sxz_c[l];
         sSyz[tid] = syz_c[l];
         __syncthreads();
@@ -459,8 +487,8 @@ step_kernel(const SampleDesc<T>* __restrict__ samples,
           }
         }
         szz_p[l] = szz;
-        sxz_c[l] = sxz_n;
-        syz_c[l] = syz_n;
+        sxz_c[l] = sxz_k;
+        syz_c[l] = syz_k;
         ux[l] = unx[l];
         uy[l] = uny[l];
         uz[l] = unz[l];
@@ -747,8 +775,10 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
     const int nz32 = (int)nz;
     const int k0 = wi.kz * sd.kc;
     const int k1 = k0 + sd.kc < nz32 ? k0 + sd.kc : nz32;
-    // wall boundaries: this column lies in the x (y) boundary plane
+    // wall boundaries: this column lies in the x (y) boundary plane; wsh: the
+    // Voigt shear component whose simple-shear test this load is (0: none)
     const bool wx = WALLS && wrap_idx(gi, nx) == 0, wy = WALLS && wrap_idx(gj, ny) == 0;
+    const int wsh = WALLS ? sd.wshear[s0] : 0;
 
     // One load per block: every access is a buffer access (descriptor and
     // component/plane offset uniform, the column's 32-bit byte offset per
@@ -888,7 +918,10 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       const T sfx = sfac * tmin(sH[xm], iHh[P]);
       const T sfy = sfac * tmin(sH[ym], iHh[P]);
       const T sfz = sfac * tmin(iHh[Q], iHh[P]);
-      T sxx[L], syy[L], szz[L], sxy[L], sxz_n[L], syz_n[L];
+      // sxy_s: the xy-edge stress published in LDS; sxz_k, syz_k: the ones
+      // carried to the next plane (they differ from the thread's own only at the
+      // split edges of a simple-shear test)
+      T sxx[L], syy[L], szz[L], sxy[L], sxz_n[L], syz_n[L], sxy_s[L], sxz_k[L], syz_k[L];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
         const T ux = Ux[P][l], uy = Uy[P][l], uz = Uz[P][l];
@@ -906,14 +939,43 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
         sxy[l] = G2xy * (E[l][5] + T(0.5) * ((ux - sUx[ym]) * rhy + (uy - sUy[xm]) * rhx));
         sxz_n[l] = G2xz * (E[l][4] + T(0.5) * ((unx - ux) * rhz + (unz - sUz[xm]) * rhx));
         syz_n[l] = G2yz * (E[l][3] + T(0.5) * ((uny - uy) * rhz + (unz - sUz[ym]) * rhy));
-        if constexpr (WALLS) {  // edges in a boundary plane: no shear stress
-          if (wx || wy) sxy[l] = T(0);
-          if (wx || kn == 0) sxz_n[l] = T(0);
-          if (wy || kn == 0) syz_n[l] = T(0);
+        if constexpr (WALLS) {
+          // edges in a boundary plane carry no shear stress (free slip), except
+          // for the simple-shear test's own component: on the walls normal to
+          // the sheared direction it is computed as inside, and on the loaded
+          // walls (normal to z for yz and xz, to y for xy) the edge splits into
+          // two halves, one per side of the box, each with the one-sided
+          // derivative to the wall (where the fluctuation is held at zero) and
+          // the harmonic mean of its own two cells (2 G = 0.5 / (iG8 + iG8'))
+          if ((wx || wy) && wsh != 5) sxy[l] = T(0);
+          if ((wx || kn == 0) && wsh != 4) sxz_n[l] = T(0);
+          if ((wy || kn == 0) && wsh != 3) syz_n[l] = T(0);
+          sxy_s[l] = sxy[l];
+          sxz_k[l] = sxz_n[l];
+          syz_k[l] = syz_n[l];
+          if (wsh == 5 && wy) {  // own half in the cells j = 0, published half in j = ny - 1
+            const T t = T(0.5) * (uy - sUy[xm]) * rhx;
+            sxy[l] = T(0.5) * recip(ik + ikx) * (E[l][5] + ux * rhy + t);
+            sxy_s[l] = T(0.5) * recip(gk[ym] + gk[xmym]) * (E[l][5] - sUx[ym] * rhy + t);
+          }
+          if (wsh == 4 && kn == 0) {  // upper edge of plane nz - 1, carried as the lower edge of plane 0
+            const T t = T(0.5) * (unz - sUz[xm]) * rhx;
+            sxz_n[l] = T(0.5) * recip(ik + ikx) * (E[l][4] - ux * rhz + t);
+            sxz_k[l] = T(0.5) * recip(in + inx) * (E[l][4] + unx * rhz + t);
+          }
+          if (wsh == 3 && kn == 0) {
+            const T t = T(0.5) * (unz - sUz[ym]) * rhy;
+            syz_n[l] = T(0.5) * recip(ik + iky) * (E[l][3] - uy * rhz + t);
+            syz_k[l] = T(0.5) * recip(in + iny) * (E[l][3] + uny * rhz + t);
+          }
+        } else {
+          sxy_s[l] = sxy[l];
+          sxz_k[l] = sxz_n[l];
+          syz_k[l] = syz_n[l];
         }
         S(l, 3)[tid] = sxx[l];
         S(l, 4)[tid] = syy[l];
-        S(l, 5)[tid] = sxy[l];
+        S(l, 5)[tid] = sxy_s[l];
         S(l, 6)[tid] = Sxz[Q][l];
         S(l, 7)[tid] = Syz[Q][l];
       }
@@ -946,8 +1008,8 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
           sto_(l, 2, pc, oc, uz + mom * (uz - uo2[l]) + sfz * rz);
         }
         Szz[P][l] = szz[l];
-        Sxz[P][l] = sxz_n[l];
-        Syz[P][l] = syz_n[l];
+        Sxz[P][l] = sxz_k[l];
+        Syz[P][l] = syz_k[l];
       }
     };
 
@@ -1644,14 +1706,49 @@ __global__ void average_partials_kernel(int64_t nx, int64_t ny, int64_t nz, doub
     double gyz = 8.0 / (gc + 1.0 / G[at(i, jm, k)] + 1.0 / G[at(i, j, km)] + 1.0 / G[at(i, jm, km)]);
     double gxz = 8.0 / (gc + 1.0 / G[at(im, j, k)] + 1.0 / G[at(i, j, km)] + 1.0 / G[at(im, j, km)]);
     double gxy = 8.0 / (gc + 1.0 / G[at(im, j, k)] + 1.0 / G[at(i, jm, k)] + 1.0 / G[at(im, jm, k)]);
-    if (walls) {  // edges in a boundary plane carry no shear stress
-      if (j == 0 || k == 0) gyz = 0.0;
-      if (i == 0 || k == 0) gxz = 0.0;
-      if (i == 0 || j == 0) gxy = 0.0;
+    double syz = gyz * (E3 + 0.5 * ((uy[c] - uy[at(i, j, km)]) * rhz + (uz[c] - uz[at(i, jm, k)]) * rhy));
+    double sxz = gxz * (E4 + 0.5 * ((ux[c] - ux[at(i, j, km)]) * rhz + (uz[c] - uz[at(im, j, k)]) * rhx));
+    double sxy = gxy * (E5 + 0.5 * ((ux[c] - ux[at(i, jm, k)]) * rhy + (uy[c] - uy[at(im, j, k)]) * rhx));
+    if (walls) {
+      // walls = 1 (normal test): every edge in a boundary plane carries no shear
+      // stress.  walls = 3, 4, 5 (simple-shear test of yz, xz, xy): so do the
+      // other components' boundary edges; the test's own component is computed
+      // as inside on the walls normal to the sheared direction and, on the
+      // loaded walls, is the mean of the two half edges (one per side of the
+      // box: one-sided derivative to the wall, harmonic mean of the half's two
+      // cells, 2 G = 4 / (1/G + 1/G'))
+      const int64_t kt = nz - 1, jt = ny - 1;
+      if (walls == 3) {
+        if (k == 0) {
+          const double t = 0.5 * (uz[c] - uz[at(i, jm, 0)]) * rhy;
+          syz = 0.5 * (4.0 / (gc + 1.0 / G[at(i, jm, 0)]) * (E3 + uy[c] * rhz + t) +
+                       4.0 / (1.0 / G[at(i, j, kt)] + 1.0 / G[at(i, jm, kt)]) * (E3 - uy[at(i, j, kt)] * rhz + t));
+        }
+      } else if (j == 0 || k == 0) {
+        syz = 0.0;
+      }
+      if (walls == 4) {
+        if (k == 0) {
+          const double t = 0.5 * (uz[c] - uz[at(im, j, 0)]) * rhx;
+          sxz = 0.5 * (4.0 / (gc + 1.0 / G[at(im, j, 0)]) * (E4 + ux[c] * rhz + t) +
+                       4.0 / (1.0 / G[at(i, j, kt)] + 1.0 / G[at(im, j, kt)]) * (E4 - ux[at(i, j, kt)] * rhz + t));
+        }
+      } else if (i == 0 || k == 0) {
+        sxz = 0.0;
+      }
+      if (walls == 5) {
+        if (j == 0) {
+          const double t = 0.5 * (uy[c] - uy[at(im, 0, k)]) * rhx;
+          sxy = 0.5 * (4.0 / (gc + 1.0 / G[at(im, 0, k)]) * (E5 + ux[c] * rhy + t) +
+                       4.0 / (1.0 / G[at(i, jt, k)] + 1.0 / G[at(im, jt, k)]) * (E5 - ux[at(i, jt, k)] * rhy + t));
+        }
+      } else if (i == 0 || j == 0) {
+        sxy = 0.0;
+      }
     }
-    acc[3] += gyz * (E3 + 0.5 * ((uy[c] - uy[at(i, j, km)]) * rhz + (uz[c] - uz[at(i, jm, k)]) * rhy));
-    acc[4] += gxz * (E4 + 0.5 * ((ux[c] - ux[at(i, j, km)]) * rhz + (uz[c] - uz[at(im, j, k)]) * rhx));
-    acc[5] += gxy * (E5 + 0.5 * ((ux[c] - ux[at(i, jm, k)]) * rhy + (uy[c] - uy[at(im, j, k)]) * rhx));
+    acc[3] += syz;
+    acc[4] += sxz;
+    acc[5] += sxy;
   }
   for (int q = 0; q < 6; ++q) {
     const double s = block_sum(acc[q], red);
