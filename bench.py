@@ -47,7 +47,8 @@ VARIANT_KERNEL = {0: "step_kernel", 1: "step_kernel", 2: "step_kernel_u2", 3: "s
 #   cracks479:  St 2.0 / 2.5 / 3.0 / 4.0 / 5.0 / 6.5 / 8.0 -> 152 / 125 / 103 / 76 / 61 / 58 / 78 s (5.0: even
 #               counts over the six loads)
 #   batch48:    St 2.0 / 2.5 / 3.0 / 3.5 -> 15.4 / 13.1 / 12.6 / 13.7 s
-STROUHAL_BY_WORKLOAD = {"spheres191": 3.0, "cracks479": 5.0, "batch48": 3.0}
+#   spheres703: St 5.0 / 6.5 / 8.0 / 11.5 -> 12000 / 9200 / 7400 / 9200 iterations of load 0
+STROUHAL_BY_WORKLOAD = {"spheres191": 3.0, "cracks479": 5.0, "batch48": 3.0, "spheres703": 8.0}
 
 
 def kernel_source_hash():
@@ -102,12 +103,13 @@ def parse():
     ap.add_argument("--fuse", default="auto", choices=["auto", "on", "off"],
                     help="load fusion: library choice (auto), one launch for all loads (on), one load at a time (off)")
     ap.add_argument("--max-iter", type=int, default=400000)
+    ap.add_argument("--loads", default="012345", help="other single-image workloads: the loads to solve")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for counter collection: allow stopping at --max-iter")
     ap.add_argument("--workload", default="spheres191",
-                    choices=["spheres191", "batch48", "cracks479", "sizing703", "hsweep"],
+                    choices=["spheres191", "batch48", "cracks479", "spheres703", "hsweep"],
                     help="spheres191 (default bench line); batch48: 48 uneven three-phase samples in one solve; "
-                         "cracks479: 479^3 cracked solid; sizing703: 703^3 sphere pack (memory sizing run); "
+                         "cracks479: 479^3 cracked solid; spheres703: 703^3 sphere pack (the largest grid; --fuse off solves the loads one after another and reports each); "
                          "hsweep: contribution tensors of single spheroids, aspect ratio x contrast, one batch")
     ap.add_argument("--hsweep-r", type=int, default=12, help="hsweep: largest semi-axis of the coarse spheroids")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -312,7 +314,8 @@ def other_workload(a, torch, synth, ceff, dev):
     if a.workload == "hsweep":
         return hsweep(a, torch, synth, ceff, dev)
     opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, max_iter=a.max_iter,
-                allow_unconverged=a.profile_run, autotune=a.autotune)
+                allow_unconverged=a.profile_run, autotune=a.autotune,
+                fuse_loads={"auto": "auto", "on": True, "off": False}[a.fuse])
     t0 = time.perf_counter()
     if a.workload == "batch48":
         ms = synth.workload_batch()
@@ -341,17 +344,37 @@ def other_workload(a, torch, synth, ceff, dev):
               flush=True)
         ctx = ceff.Context(0)
         ctx.set_phases(m.phase, m.K_tab, m.G_tab)
+        loads = [int(q) for q in a.loads]
+        # one load at a time (--fuse off): one solve call per load, each reported as it ends
+        groups = [[J] for J in loads] if a.fuse == "off" else [loads]
+        C = np.full((6, 6), np.nan)
+        iters = np.zeros(6, np.int64)
+        relres = {}
+        status, step_bytes, step_ms, launches = 0, 0.0, 0.0, 0
         torch.cuda.synchronize(dev)
         t1 = time.perf_counter()
-        C, info = ctx.solve(**opts)
+        for grp in groups:
+            tg = time.perf_counter()
+            Cg, info = ctx.solve(loads=grp, **opts)
+            for J in grp:
+                C[:, J] = Cg[:, J]
+                iters[J] = info["iters"][J]
+                h = info["hist"]
+                hj = h[h[:, 1] == J]
+                relres[J] = float(hj[-1, 2]) if len(hj) else 0.0
+            status = status or info["status"]
+            st = info["stats"]
+            step_bytes += st["step_bytes"]; step_ms += st["step_time_ms"]; launches += st["step_launches"]
+            print(f"# loads {grp}: status {info['status']}, iterations {[int(iters[J]) for J in grp]}, "
+                  f"final relative residual {[relres[J] for J in grp]}, {time.perf_counter() - tg:.1f} s",
+                  file=sys.stderr, flush=True)
         wall = time.perf_counter() - t1
-        st = info["stats"]
-        free, total = torch.cuda.mem_get_info(dev)
         ctx.close()
-        res = {"workload": a.workload, "voxels": N, "info": m.info, "status": info["status"], "time_s": wall,
-               "iterations": info["iters"].tolist(), "gvu_s": N * float(info["iters"].sum()) / wall / 1e9,
-               "kernel_GB_s": st["step_bytes"] / (st["step_time_ms"] * 1e-3) / 1e9,
-               "avg_launch_ms": st["step_time_ms"] / max(st["step_launches"], 1),
+        res = {"workload": a.workload, "voxels": N, "info": m.info, "status": status, "time_s": wall,
+               "loads": loads, "iterations": iters.tolist(), "final_relres": relres, "strouhal": a.strouhal,
+               "gvu_s": N * float(iters.sum()) / wall / 1e9,
+               "kernel_GB_s": step_bytes / (step_ms * 1e-3) / 1e9 if step_ms > 0 else None,
+               "avg_launch_ms": step_ms / max(launches, 1),
                "C_eff_GPa": np.round(C, 5).tolist()}
     print(json.dumps(res), flush=True)
 

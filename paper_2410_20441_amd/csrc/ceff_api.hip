@@ -246,6 +246,9 @@ struct Prob {
   std::vector<double> recent;
 };
 
+// MI355X's Infinity Cache (the memory-side last-level cache in front of HBM).
+constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
+
 TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single) {
   TileShape t;
   // CEFF_TILE="bx,by[,kc[,group[,variant[,order[,occ]]]]]" overrides the launch shape (the iterates
@@ -470,6 +473,28 @@ struct Engine {
     return CEFF_OK;
   }
 
+  // When the sweep's working set (all loads of this launch and the phase image)
+  // exceeds the Infinity Cache, every iteration streams from HBM and the shapes
+  // tuned on cache-resident grids lose to wider rows and longer z-chunks.
+  // Measured on a 703^3 sphere pack with the phase table: one load per launch,
+  // 18 x 14 with 12-plane chunks 3.84 ms, 66 x 7 with 48-plane chunks and the
+  // high-occupancy variant 3.11 ms; six loads fused, two per block, 66 x 7 with
+  // 12-plane chunks 3.19 ms and with 48-plane chunks 3.08 ms per load.  Applied
+  // to single-image FP32 solves with the phase table whose grid still yields
+  // at least 2048 (tile, chunk) items at that shape.
+  void large_grid_shape() {
+    if (sizeof(T) != 4 || in.size() != 1 || !ts.pal || ts.ortho || ts.walls) return;
+    const SampleIn& s = in[0];
+    const double ws = (double)s.nx * s.ny * s.nz * (6.0 * sizeof(T) * (double)Js.size() + 1.0);
+    if (ws <= kInfinityCacheBytes) return;
+    const int64_t items = ((s.nx + 63) / 64) * ((s.ny + 4) / 5) * ((s.nz + 47) / 48);
+    if (items < 2048) return;
+    ts.bx = 66;
+    ts.by = 7;
+    ts.kc = 48;
+    ts.occ = single() ? 1 : 0;
+  }
+
   // Pick the launch shape: block extent, loads per block and prefetch.  With
   // autotune, time each candidate over a few iterations on this problem (the
   // iterates do not depend on the shape; only speed does) and cache the best.
@@ -486,6 +511,7 @@ struct Engine {
       return CEFF_OK;
     }
     ts = with_moduli(default_tile(in[0].nx, in[0].ny, fp64, single()));
+    large_grid_shape();
     if (!o.autotune || ts.ortho || ts.walls) return CEFF_OK;
     std::vector<TileShape> cand;
     const int bxs[] = {18, 34, 66};
@@ -1007,8 +1033,6 @@ bool invert6(const double* A, double* X) {
   return true;
 }
 
-// MI355X's Infinity Cache (the memory-side last-level cache in front of HBM).
-constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 
 // Automatic load fusion.  One iteration touches, per cell, both displacement
 // buffers of every load it advances plus the material.  When that working set
