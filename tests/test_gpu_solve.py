@@ -253,3 +253,28 @@ def test_automatic_load_fusion(n, fused):
         C, info = c.solve(precision="mixed")
     assert info["stats"]["fused_loads"] == fused
     np.testing.assert_allclose(C, cf.c_iso(70.0, 32.0), rtol=1e-14, atol=1e-12)
+
+
+@pytest.mark.parametrize("fuse", [False, True])
+def test_large_grid_launch_shape(monkeypatch, fuse):
+    """Beyond the Infinity Cache (a 320^3 pore pack: 0.8 GB for one load) the library
+    switches to 66 x 7 blocks with 48-plane chunks (and the high-occupancy variant
+    for one load per block); the iterate is the one of the cache-resident shape."""
+    p = need_gpu()
+    m = synth.random_spheres(320, 0.10, 0x320)
+    monkeypatch.delenv("CEFF_TILE", raising=False)
+    announce("large-grid shape 320^3, fused", fuse)
+    opts = dict(loads=range(6) if fuse else [0], precision="mixed", max_iter=400, check_every=200,
+                allow_unconverged=True, fuse_loads=fuse)
+    with p.Context() as c:
+        c.set_phases(m.phase, m.K_tab, m.G_tab)
+        C, info = c.solve(**opts)
+        st = info["stats"]
+        assert (st["tile_bx"], st["tile_by"], st["tile_kc"]) == (66, 7, 48)
+        assert st["tile_group"] == (2 if fuse else 1)
+        monkeypatch.setenv("CEFF_TILE", "18,14,12,1,3,1,0" if not fuse else "66,7,12,2,3,1,0")
+        C2, info2 = c.solve(**opts)
+        assert info2["stats"]["tile_kc"] == 12
+    cols = list(opts["loads"])
+    assert np.max(np.abs(C[:, cols] - C2[:, cols])) <= 1e-12 * np.abs(C[:, cols]).max()
+    assert np.array_equal(info["iters"], info2["iters"])
