@@ -529,7 +529,7 @@ struct Engine {
           for (int pf = 1; pf < 6; ++pf)
             for (int kc : {0, 12})
               for (int occ = 0; occ < 2; ++occ) {
-                if (occ && pf < 4) continue;
+                if (occ && pf < 3) continue;
                 if (pf == 5 && groups[gi] != 1) continue;
                 if (pf == 5 && (bx - 2) * (by - 2) < 64) continue;
                 const int grp = single() ? 1 : groups[gi];
