@@ -500,9 +500,15 @@ struct Engine {
   // iterates do not depend on the shape; only speed does) and cache the best.
   ceff_status tune() {
     const bool fp64 = sizeof(T) == 8;
+    // the default block spans the largest sample (a batch's first sample may be small)
+    int64_t nxm = 0, nym = 0;
+    for (const SampleIn& s : in) {
+      nxm = std::max(nxm, s.nx);
+      nym = std::max(nym, s.ny);
+    }
     const auto key = std::make_tuple((int)sizeof(T), (int)Js.size(), in[0].nx, in[0].ny, in[0].nz);
     if (std::getenv("CEFF_TILE")) {
-      ts = with_moduli(default_tile(in[0].nx, in[0].ny, fp64, single()));
+      ts = with_moduli(default_tile(nxm, nym, fp64, single()));
       return CEFF_OK;
     }
     auto it = c->tuned.find(key);
@@ -510,7 +516,7 @@ struct Engine {
       ts = with_moduli(it->second);
       return CEFF_OK;
     }
-    ts = with_moduli(default_tile(in[0].nx, in[0].ny, fp64, single()));
+    ts = with_moduli(default_tile(nxm, nym, fp64, single()));
     large_grid_shape();
     if (!o.autotune || ts.ortho || ts.walls) return CEFF_OK;
     std::vector<TileShape> cand;
