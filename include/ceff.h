@@ -187,6 +187,18 @@ ceff_status ceff_solve_batch(ceff_ctx* ctx, int nsamples, const int64_t* dims, c
                              const void* const* K, const void* const* G, int dtype, int where, uint32_t load_mask,
                              const ceff_solve_opts* opts, double* C_out, int64_t* iters_out);
 
+/* As ceff_solve_batch for phase images that share one phase table: phase[s]
+ * is sample s's uint8 image (N_s values, host or device per `where`), K_tab
+ * and G_tab the per-phase moduli (host doubles, nphase entries, finite and
+ * > 0; every phase id < nphase, else CEFF_EINVAL).  The FP32 iteration then
+ * reads one byte per voxel and the moduli from an on-chip copy of the table,
+ * as for ceff_set_phases; the results equal those of ceff_solve_batch on the
+ * expanded K and G fields.  Does not change the context's grid or material. */
+ceff_status ceff_solve_batch_phases(ceff_ctx* ctx, int nsamples, const int64_t* dims, const double* h,
+                                    const uint8_t* const* phase, int where, int nphase, const double* K_tab,
+                                    const double* G_tab, uint32_t load_mask, const ceff_solve_opts* opts,
+                                    double* C_out, int64_t* iters_out);
+
 /* Gradient of J = sum_IJ W[I*6+J] C_IJ with respect to the per-voxel K and G
  * of the current material, from the displacements kept by the last
  * ceff_solve (keep_fields = 1, all loads that W touches; isotropic materials

@@ -29,7 +29,7 @@ _L = _lib.load()
 
 __all__ = ["ceff_default_opts", "ceff_create", "ceff_destroy", "ceff_last_error", "ceff_set_grid",
            "ceff_set_isotropic", "ceff_set_phases", "ceff_set_stiffness", "ceff_set_boundary", "ceff_solve",
-           "ceff_solve_batch",
+           "ceff_solve_batch", "ceff_solve_batch_phases", "solve_batch_phases",
            "ceff_gradient", "ceff_apt_steps", "ceff_residual", "ceff_average_stress", "ceff_get_stats",
            "ceff_contribution_tensors", "CeffError", "Context", "solve", "solve_batch", "contribution_tensors",
            "EffectiveStiffness", "library_path"]
@@ -101,6 +101,12 @@ def ceff_solve(ctx, load_mask, opts, C_out, hist, hist_cap, hist_len, iters_out,
 def ceff_solve_batch(ctx, nsamples, dims, h, K, G, dtype, where, load_mask, opts, C_out, iters_out, allow=()):
     return _check(ctx, _L.ceff_solve_batch(ctx, nsamples, dims, h, K, G, dtype, where, load_mask, opts, C_out,
                                            iters_out), allow)
+
+
+def ceff_solve_batch_phases(ctx, nsamples, dims, h, phase, where, nphase, K_tab, G_tab, load_mask, opts, C_out,
+                            iters_out, allow=()):
+    return _check(ctx, _L.ceff_solve_batch_phases(ctx, nsamples, dims, h, phase, where, nphase, K_tab, G_tab,
+                                                  load_mask, opts, C_out, iters_out), allow)
 
 
 def ceff_gradient(ctx, W, dK, dG, dtype, where):
@@ -367,6 +373,38 @@ def solve_batch(samples, h=None, loads=range(6), device=0, allow_unconverged=Fal
         st = ceff_solve_batch(c.h, ns, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(hh), Kp, Gp, dt,
                               wh, mask, ctypes.byref(o), _dptr(C), it.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                               allow)
+        stats = c.stats()
+    return C.reshape(ns, 6, 6), it.reshape(ns, 6), {"status": st, "stats": stats}
+
+
+def solve_batch_phases(phases, K_tab, G_tab, h=None, loads=range(6), device=0, allow_unconverged=False, **kw):
+    """phases: list of uint8 phase images (numpy, host) sharing the table (K_tab, G_tab).
+    Returns C (nsamples, 6, 6), iterations (nsamples, 6), stats."""
+    ns = len(phases)
+    dims = np.zeros(3 * ns, np.int64)
+    hh = np.ones(3 * ns)
+    ptrs = (ctypes.c_void_p * ns)()
+    keep = []
+    for s, ph in enumerate(phases):
+        a = np.ascontiguousarray(ph, np.uint8)
+        dims[3 * s:3 * s + 3] = _shape3(a)
+        if h is not None:
+            hh[3 * s:3 * s + 3] = h[s]
+        ptrs[s] = ctypes.c_void_p(a.ctypes.data)
+        keep.append(a)
+    Kt = np.ascontiguousarray(K_tab, np.float64)
+    Gt = np.ascontiguousarray(G_tab, np.float64)
+    o = make_opts(**kw)
+    mask = 0
+    for J in loads:
+        mask |= 1 << int(J)
+    C = np.full(36 * ns, np.nan)
+    it = np.zeros(6 * ns, np.int64)
+    with Context(device) as c:
+        allow = (_lib.CEFF_ENOTCONV, _lib.CEFF_EDIVERGED) if allow_unconverged else ()
+        st = ceff_solve_batch_phases(c.h, ns, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(hh), ptrs,
+                                     CEFF_HOST, len(Kt), _dptr(Kt), _dptr(Gt), mask, ctypes.byref(o), _dptr(C),
+                                     it.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), allow)
         stats = c.stats()
     return C.reshape(ns, 6, 6), it.reshape(ns, 6), {"status": st, "stats": stats}
 

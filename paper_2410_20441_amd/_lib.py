@@ -59,6 +59,8 @@ SIGNATURES = {
     "ceff_solve": (_st, [_vp, ctypes.c_uint32, ctypes.POINTER(ceff_solve_opts), _dp, _dp, _i64, _i64p, _i64p]),
     "ceff_solve_batch": (_st, [_vp, ctypes.c_int, _i64p, _dp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int,
                                ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ceff_solve_opts), _dp, _i64p]),
+    "ceff_solve_batch_phases": (_st, [_vp, ctypes.c_int, _i64p, _dp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int,
+                                      _dp, _dp, ctypes.c_uint32, ctypes.POINTER(ceff_solve_opts), _dp, _i64p]),
     "ceff_gradient": (_st, [_vp, _dp, _vp, _vp, ctypes.c_int, ctypes.c_int]),
     "ceff_apt_steps": (_st, [_vp, ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp]),
     "ceff_residual": (_st, [_vp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),

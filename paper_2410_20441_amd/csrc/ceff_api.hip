@@ -322,7 +322,11 @@ struct Engine {
     t.ortho = in[0].c64 != nullptr ? 1 : 0;
     t.walls = in[0].walls;
     if (t.walls) t.pf = 3;  // the wall-boundary kernels are variant 3, one load per block
-    t.pal = !t.ortho && in.size() == 1 && in[0].phase != nullptr && t.pf == 3 && !fields ? 1 : 0;
+    // the phase table is staged once per block from the first sample, so every
+    // sample of the launch must use that same table
+    bool shared = true;
+    for (const SampleIn& s : in) shared = shared && s.phase != nullptr && s.ptab64 == in[0].ptab64;
+    t.pal = !t.ortho && shared && t.pf == 3 && !fields ? 1 : 0;
     return t;
   }
 
@@ -1366,6 +1370,108 @@ ceff_status ceff_solve_batch(ceff_ctx* c, int nsamples, const int64_t* dims, con
                      K64[s].as<double>(), G64[s].as<double>(), mixed ? K32[s].as<float>() : nullptr,
                      mixed ? G32[s].as<float>() : nullptr};
   }
+  std::vector<int> Js;
+  for (int J = 0; J < 6; ++J)
+    if (load_mask & (1u << J)) Js.push_back(J);
+  std::vector<std::array<double, 36>> C(nsamples);
+  std::vector<std::array<int64_t, 6>> it(nsamples);
+  for (int s = 0; s < nsamples; ++s) {
+    for (int q = 0; q < 36; ++q) C[s][q] = C_out[36 * s + q];
+    for (int q = 0; q < 6; ++q) it[s][q] = 0;
+  }
+  ceff_status worst = CEFF_OK;
+  const int Lk = Js.size() == 1 ? 1 : 6;
+  if (mixed)
+    STCK(run_engine<float>(c, in, Js, o, Lk, C, it, nullptr, false, worst));
+  else
+    STCK(run_engine<double>(c, in, Js, o, Lk, C, it, nullptr, false, worst));
+  for (int s = 0; s < nsamples; ++s) {
+    for (int J : Js)
+      for (int I = 0; I < 6; ++I) C_out[36 * s + I * 6 + J] = C[s][I * 6 + J];
+    if (iters_out)
+      for (int q = 0; q < 6; ++q) iters_out[6 * s + q] = (load_mask & (1u << q)) ? it[s][q] : 0;
+  }
+  c->stats.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (worst != CEFF_OK) return fail(c, worst, worst == CEFF_ENOTCONV ? "max_iter reached" : "iteration diverged");
+  return CEFF_OK;
+}
+
+ceff_status ceff_solve_batch_phases(ceff_ctx* c, int nsamples, const int64_t* dims, const double* h,
+                                    const uint8_t* const* phase, int where, int nphase, const double* K_tab,
+                                    const double* G_tab, uint32_t load_mask, const ceff_solve_opts* opts,
+                                    double* C_out, int64_t* iters_out) {
+  if (!c) return CEFF_EINVAL;
+  ceff_solve_opts o;
+  ceff_default_opts(&o);
+  if (opts) o = *opts;
+  STCK(validate_opts(c, o));
+  if (nsamples < 1 || nsamples > 100000) return fail(c, CEFF_EINVAL, "nsamples out of range");
+  if (!dims || !h || !phase || !K_tab || !G_tab || !C_out) return fail(c, CEFF_EINVAL, "null argument");
+  if (nphase < 1 || nphase > 256) return fail(c, CEFF_EINVAL, "nphase must be in [1, 256]");
+  if (where != CEFF_HOST && where != CEFF_DEVICE) return fail(c, CEFF_EINVAL, "where must be CEFF_HOST or CEFF_DEVICE");
+  if (load_mask == 0 || (load_mask & ~0x3Fu)) return fail(c, CEFF_EINVAL, "load_mask must be a nonzero 6-bit mask");
+  for (int p = 0; p < nphase; ++p)
+    if (!(K_tab[p] > 0.0) || !(G_tab[p] > 0.0) || !std::isfinite(K_tab[p]) || !std::isfinite(G_tab[p]))
+      return fail(c, CEFF_EINVAL, "phase moduli must be finite and > 0");
+  for (int s = 0; s < nsamples; ++s) {
+    STCK(validate_grid(c, dims[3 * s], dims[3 * s + 1], dims[3 * s + 2], h + 3 * s));
+    if (!phase[s]) return fail(c, CEFF_EINVAL, "null phase image for sample %d", s);
+  }
+  STCK(begin_call(c));
+  const auto t0 = std::chrono::steady_clock::now();
+  c->stats = ceff_stats{};
+  const bool mixed = o.precision == CEFF_PREC_MIXED;
+  // one table for all samples, in both precisions ((float)x rounds as the
+  // device conversion of the FP64 fields does)
+  std::vector<double> t64(2 * nphase);
+  std::vector<float> t32(2 * nphase);
+  for (int p = 0; p < nphase; ++p) {
+    t64[p] = K_tab[p];
+    t64[nphase + p] = G_tab[p];
+  }
+  for (int q = 0; q < 2 * nphase; ++q) t32[q] = (float)t64[q];
+  DevBuf tab64, tab32;
+  HIPCK(c, tab64.alloc(sizeof(double) * 2 * nphase));
+  HIPCK(c, tab32.alloc(sizeof(float) * 2 * nphase));
+  HIPCK(c, hipMemcpyAsync(tab64.p, t64.data(), sizeof(double) * 2 * nphase, hipMemcpyHostToDevice, c->s));
+  HIPCK(c, hipMemcpyAsync(tab32.p, t32.data(), sizeof(float) * 2 * nphase, hipMemcpyHostToDevice, c->s));
+  std::vector<DevBuf> ph(nsamples), K64(nsamples), G64(nsamples), K32(nsamples), G32(nsamples);
+  std::vector<SampleIn> in(nsamples);
+  std::vector<uint8_t> host;
+  for (int s = 0; s < nsamples; ++s) {
+    const int64_t N = dims[3 * s] * dims[3 * s + 1] * dims[3 * s + 2];
+    const uint8_t* hp = phase[s];
+    if (where == CEFF_DEVICE) {
+      host.resize(N);
+      HIPCK(c, hipMemcpy(host.data(), phase[s], N, hipMemcpyDeviceToHost));
+      hp = host.data();
+    }
+    for (int64_t t = 0; t < N; ++t)
+      if (hp[t] >= nphase)
+        return fail(c, CEFF_EINVAL, "sample %d: phase id %d at voxel %lld >= nphase", s, hp[t], (long long)t);
+    HIPCK(c, ph[s].alloc(N));
+    HIPCK(c, hipMemcpyAsync(ph[s].p, hp, N, hipMemcpyHostToDevice, c->s));
+    HIPCK(c, K64[s].alloc(sizeof(double) * N));
+    HIPCK(c, G64[s].alloc(sizeof(double) * N));
+    HIPCK(c, launch_phase_to_fields<double>(ph[s].as<uint8_t>(), N, tab64.as<double>(), tab64.as<double>() + nphase,
+                                            nphase, K64[s].as<double>(), G64[s].as<double>(), c->s));
+    if (mixed) {  // FP32 fields for launch shapes that do not read the table
+      HIPCK(c, K32[s].alloc(sizeof(float) * N));
+      HIPCK(c, G32[s].alloc(sizeof(float) * N));
+      HIPCK(c, launch_convert<double, float>(K64[s].as<double>(), K32[s].as<float>(), N, c->s));
+      HIPCK(c, launch_convert<double, float>(G64[s].as<double>(), G32[s].as<float>(), N, c->s));
+    }
+    // the host copy is reused by the next sample: finish this one's upload first
+    if (where == CEFF_DEVICE) HIPCK(c, hipStreamSynchronize(c->s));
+    in[s] = SampleIn{dims[3 * s], dims[3 * s + 1], dims[3 * s + 2], {h[3 * s], h[3 * s + 1], h[3 * s + 2]},
+                     K64[s].as<double>(), G64[s].as<double>(), mixed ? K32[s].as<float>() : nullptr,
+                     mixed ? G32[s].as<float>() : nullptr};
+    in[s].phase = ph[s].as<uint8_t>();
+    in[s].ptab64 = tab64.as<double>();
+    in[s].ptab32 = tab32.as<float>();
+    in[s].nphase = nphase;
+  }
+  HIPCK(c, hipStreamSynchronize(c->s));
   std::vector<int> Js;
   for (int J = 0; J < 6; ++J)
     if (load_mask & (1u << J)) Js.push_back(J);
