@@ -141,6 +141,28 @@ def test_batch_block_spans_largest_sample():
         assert matrix_rel(C[s], Co) <= 1e-6, s
 
 
+def test_batch_of_phase_images_equals_field_batch():
+    """ceff_solve_batch_phases (one shared table, the phase-table kernel) gives
+    the iterates of ceff_solve_batch on the expanded fields, and the oracle's C*."""
+    p = need_gpu()
+    ms = [synth.gaussian_field_three_phase(n, 0xC4 + i) for i, n in enumerate((16, 22, 19))]
+    announce("batch of phase images", [m.phase.shape for m in ms])
+    Cp, itp, infop = p.solve_batch_phases([m.phase for m in ms], ms[0].K_tab, ms[0].G_tab, precision="mixed",
+                                          rtol=1e-9)
+    assert infop["stats"]["phase_moduli"] == 1
+    Cf, itf, infof = p.solve_batch([m.fields() for m in ms], precision="mixed", rtol=1e-9)
+    assert infof["stats"]["phase_moduli"] == 0
+    assert np.array_equal(itp, itf)
+    assert np.max(np.abs(Cp - Cf)) <= 1e-12 * np.abs(Cf).max()
+    for s, m in enumerate(ms):
+        Co, _ = oracle.ceff(*m.fields(), rtol=1e-12)
+        assert matrix_rel(Cp[s], Co) <= 1e-6, s
+    bad = ms[0].phase.copy()
+    bad[0, 0, 0] = 7
+    with pytest.raises(p.CeffError):
+        p.solve_batch_phases([bad, ms[1].phase], ms[0].K_tab, ms[0].G_tab, precision="mixed")
+
+
 def test_gradient_matches_oracle():
     p = need_gpu()
     m = synth.workload_grad16()
