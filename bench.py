@@ -277,13 +277,18 @@ def hsweep(a, torch, synth, ceff, dev):
             for r in (r0, 2 * r0):
                 cases.append((al, name, r, shape))
                 ms.append(synth.centred_spheroid(8 * r, tuple(r * f for f in shape), matrix=host, inclusion=inc))
-    samples = [tuple(torch.from_numpy(x).to(dev) for x in m.fields(np.float32)) for m in ms]
+    # one table for the whole batch: the host, then the three inclusions; each image's
+    # inclusion voxels (phase 1) take the id of its own inclusion
+    names = list(incs)
+    Ktab = np.array([host[0]] + [incs[q][0] for q in names])
+    Gtab = np.array([host[1]] + [incs[q][1] for q in names])
+    phases = [np.where(m.phase == 1, 1 + names.index(cs[1]), 0).astype(np.uint8) for m, cs in zip(ms, cases)]
     N = sum(m.phase.size for m in ms)
     print(f"# hsweep: {len(ms)} samples, {N} voxels", file=sys.stderr, flush=True)
     torch.cuda.synchronize(dev)
     t1 = time.perf_counter()
-    C, it, info = ceff.solve_batch(samples, precision="mixed", rtol=a.rtol, check_every=a.check_every,
-                                   max_iter=a.max_iter)
+    C, it, info = ceff.solve_batch_phases(phases, Ktab, Gtab, precision="mixed", rtol=a.rtol,
+                                          check_every=a.check_every, max_iter=a.max_iter)
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t1
     K1, G1 = host
