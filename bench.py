@@ -109,7 +109,7 @@ def parse():
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for counter collection: allow stopping at --max-iter")
     ap.add_argument("--workload", default="spheres191",
-                    choices=["spheres191", "batch48", "cracks479", "spheres703", "hsweep"],
+                    choices=["spheres191", "batch48", "cracks479", "spheres703", "hsweep", "grad128"],
                     help="spheres191 (default bench line); batch48: 48 uneven three-phase samples in one solve; "
                          "cracks479: 479^3 cracked solid; spheres703: 703^3 sphere pack (the largest grid; --fuse off solves the loads one after another and reports each); "
                          "hsweep: contribution tensors of single spheroids, aspect ratio x contrast, one batch")
@@ -316,10 +316,50 @@ def hsweep(a, torch, synth, ceff, dev):
     print(json.dumps(res), flush=True)
 
 
+def grad128(a, torch, synth, ceff, dev):
+    """Adjoint gradients of C11, C44 and trace(C) with respect to K(x) and G(x) on the
+    128^3 15%-pore pack: one solve keeping the FP64 fields, then each gradient sweep
+    timed (device outputs, FP32)."""
+    m = synth.workload_grad128()
+    K, G = m.fields()
+    N = K.size
+    ctx = ceff.Context(0)
+    ctx.set_material(K, G)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    C, info = ctx.solve(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every,
+                        keep_fields=True)
+    torch.cuda.synchronize(dev)
+    solve_s = time.perf_counter() - t0
+    print(f"# grad128: solve {solve_s:.3f} s, iterations {info['iters'].tolist()}", file=sys.stderr, flush=True)
+    Ws = {"C11": (np.diag([1.0, 0, 0, 0, 0, 0]), 1), "C44": (np.diag([0, 0, 0, 1.0, 0, 0]), 1),
+          "trace": (np.eye(6), 6)}
+    out = {}
+    for name, (W, nl) in Ws.items():
+        ctx.gradient(W, device=dev)
+        torch.cuda.synchronize(dev)
+        reps = 20
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            ctx.gradient(W, device=dev)
+        torch.cuda.synchronize(dev)
+        ms = (time.perf_counter() - t1) / reps * 1e3
+        # FP64 displacements of the loads W touches, K and G (FP64), two FP32 outputs
+        nbytes = N * (24.0 * nl + 16.0 + 8.0)
+        out[name] = {"ms": ms, "loads_read": nl, "bytes": nbytes, "GB_s": nbytes / (ms * 1e-3) / 1e9,
+                     "share_of_solve": ms * 1e-3 / solve_s}
+    ctx.close()
+    res = {"workload": "grad128", "voxels": N, "info": m.info, "solve_s": solve_s,
+           "iterations": info["iters"].tolist(), "gradients": out}
+    print(json.dumps(res), flush=True)
+
+
 def other_workload(a, torch, synth, ceff, dev):
     """Measurement runs of the other workloads (one solve each, not the bench line)."""
     if a.workload == "hsweep":
         return hsweep(a, torch, synth, ceff, dev)
+    if a.workload == "grad128":
+        return grad128(a, torch, synth, ceff, dev)
     opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, max_iter=a.max_iter,
                 allow_unconverged=a.profile_run, autotune=a.autotune,
                 fuse_loads={"auto": "auto", "on": True, "off": False}[a.fuse])

@@ -1508,22 +1508,19 @@ ceff_status ceff_gradient(ceff_ctx* c, const double W[36], void* dK, void* dG, i
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
   if (c->ortho) return fail(c, CEFF_EUNSUPPORTED, "the gradient is defined for isotropic (K, G) materials only");
   if (c->boundary != CEFF_BC_PERIODIC) return fail(c, CEFF_EUNSUPPORTED, "the gradient needs periodic boundaries");
-  const double* u6[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  GradLoads g{};
+  for (int q = 0; q < 36; ++q) g.W[q] = W[q];
   for (int I = 0; I < 6; ++I)
     for (int J = 0; J < 6; ++J)
       if (W[I * 6 + J] != 0.0) {
         if (!c->kept[I] || !c->kept[J])
           return fail(c, CEFF_ESTATE, "gradient needs the fields of loads %d and %d (solve with keep_fields=1)", I, J);
-        u6[I] = c->keep[I].as<double>();
-        u6[J] = c->keep[J].as<double>();
+        g.u[I] = c->keep[I].as<double>();
+        g.u[J] = c->keep[J].as<double>();
       }
   STCK(begin_call(c));
   const int64_t N = c->nx * c->ny * c->nz;
-  DevBuf du6, dW, oK, oG;
-  HIPCK(c, du6.alloc(sizeof u6));
-  HIPCK(c, dW.alloc(sizeof(double) * 36));
-  HIPCK(c, hipMemcpyAsync(du6.p, u6, sizeof u6, hipMemcpyHostToDevice, c->s));
-  HIPCK(c, hipMemcpyAsync(dW.p, W, sizeof(double) * 36, hipMemcpyHostToDevice, c->s));
+  DevBuf oK, oG;
   const size_t es = dtype == CEFF_F64 ? sizeof(double) : sizeof(float);
   void* tK = dK;
   void* tG = dG;
@@ -1535,10 +1532,10 @@ ceff_status ceff_gradient(ceff_ctx* c, const double W[36], void* dK, void* dG, i
   }
   if (dtype == CEFF_F64)
     HIPCK(c, launch_gradient<double>(c->nx, c->ny, c->nz, c->h, c->K64.as<double>(), c->G64.as<double>(),
-                                     du6.as<const double*>(), dW.as<double>(), (double*)tK, (double*)tG, c->s));
+                                     g, (double*)tK, (double*)tG, c->s));
   else
     HIPCK(c, launch_gradient<float>(c->nx, c->ny, c->nz, c->h, c->K64.as<double>(), c->G64.as<double>(),
-                                    du6.as<const double*>(), dW.as<double>(), (float*)tK, (float*)tG, c->s));
+                                    g, (float*)tK, (float*)tG, c->s));
   if (where == CEFF_HOST) {
     HIPCK(c, hipMemcpyAsync(dK, tK, es * N, hipMemcpyDeviceToHost, c->s));
     HIPCK(c, hipMemcpyAsync(dG, tG, es * N, hipMemcpyDeviceToHost, c->s));

@@ -114,10 +114,15 @@ hipError_t launch_average_stress_ortho(int64_t nx, int64_t ny, int64_t nz, const
                                        double* out6, hipStream_t s);
 
 // Gradient of sum W_IJ C_IJ with respect to per-voxel K and G from six FP64
-// displacement fields.
+// displacement fields.  The field pointers (nullptr for loads W does not
+// touch) and W travel as a kernel argument, so a call allocates nothing.
+struct GradLoads {
+  const double* u[6];
+  double W[36];
+};
 template <typename R>
 hipError_t launch_gradient(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K, const double* G,
-                           const double* const* u6, const double* W36, R* dK, R* dG, hipStream_t s);
+                           const GradLoads& g, R* dK, R* dG, hipStream_t s);
 
 // Elementwise helpers.
 template <typename T>

@@ -1832,8 +1832,7 @@ __global__ void average_finalize_kernel(const double* __restrict__ partials, int
 
 template <typename R>
 __global__ void gradient_kernel(int64_t nx, int64_t ny, int64_t nz, double rhx, double rhy, double rhz,
-                                const double* __restrict__ K, const double* __restrict__ G,
-                                const double* const* __restrict__ u6, const double* __restrict__ W,
+                                const double* __restrict__ K, const double* __restrict__ G, const GradLoads g,
                                 R* __restrict__ dK, R* __restrict__ dG) {
   const int64_t N = nx * ny * nz;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1863,8 +1862,8 @@ __global__ void gradient_kernel(int64_t nx, int64_t ny, int64_t nz, double rhx, 
   }
   double th[6], dv[6][3], es[6][12];
   for (int J = 0; J < 6; ++J) {
-    if (u6[J] == nullptr) continue;
-    const GLOBAL_AS double* u = gconst(u6[J]);
+    if (g.u[J] == nullptr) continue;
+    const GLOBAL_AS double* u = gconst(g.u[J]);
     const GLOBAL_AS double* ux = u;
     const GLOBAL_AS double* uy = u + N;
     const GLOBAL_AS double* uz = u + 2 * N;
@@ -1892,10 +1891,10 @@ __global__ void gradient_kernel(int64_t nx, int64_t ny, int64_t nz, double rhx, 
   }
   double gk = 0.0, gg = 0.0;
   for (int I = 0; I < 6; ++I) {
-    if (u6[I] == nullptr) continue;
+    if (g.u[I] == nullptr) continue;
     for (int J = 0; J < 6; ++J) {
-      const double w = W[I * 6 + J];
-      if (w == 0.0 || u6[J] == nullptr) continue;
+      const double w = g.W[I * 6 + J];
+      if (w == 0.0 || g.u[J] == nullptr) continue;
       gk += w * th[I] * th[J];
       double dev = dv[I][0] * dv[J][0] + dv[I][1] * dv[J][1] + dv[I][2] * dv[J][2];
       double ed = 0.0;
@@ -2089,10 +2088,10 @@ hipError_t launch_average_stress_ortho(int64_t nx, int64_t ny, int64_t nz, const
 
 template <typename R>
 hipError_t launch_gradient(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K, const double* G,
-                           const double* const* u6, const double* W36, R* dK, R* dG, hipStream_t s) {
+                           const GradLoads& g, R* dK, R* dG, hipStream_t s) {
   const int64_t N = nx * ny * nz;
   hipLaunchKernelGGL((gradient_kernel<R>), dim3((unsigned)((N + 127) / 128)), dim3(128), 0, s, nx, ny, nz,
-                     1.0 / h[0], 1.0 / h[1], 1.0 / h[2], K, G, u6, W36, dK, dG);
+                     1.0 / h[0], 1.0 / h[1], 1.0 / h[2], K, G, g, dK, dG);
   return hipGetLastError();
 }
 
@@ -2172,9 +2171,9 @@ CEFF_INST_RES(double, double, 6)
 CEFF_INST_RES(float, float, 1)
 CEFF_INST_RES(float, float, 6)
 template hipError_t launch_gradient<float>(int64_t, int64_t, int64_t, const double*, const double*, const double*,
-                                           const double* const*, const double*, float*, float*, hipStream_t);
+                                           const GradLoads&, float*, float*, hipStream_t);
 template hipError_t launch_gradient<double>(int64_t, int64_t, int64_t, const double*, const double*, const double*,
-                                            const double* const*, const double*, double*, double*, hipStream_t);
+                                            const GradLoads&, double*, double*, hipStream_t);
 template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
 template hipError_t launch_fill<double>(double*, int64_t, double, hipStream_t);
 template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
