@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the iteration kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_hbm_counters.md),
 # valid only for the kernel source they were taken on.
-MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "1a50e8c720121f7c", "bytes_per_launch": 3.278428e+08,
+MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "e9eb9a7d0a6ce754", "bytes_per_launch": 3.277046e+08,
                     # (loads per block, kernel variant, loads fused, moduli from the phase image)
                     "launch_signature": (1, 3, 0, 1),
                     # mean algorithmic bytes per launch of the profiled solve: fixes its mix of
