@@ -247,6 +247,22 @@ ceff_status ceff_get_stats(const ceff_ctx* ctx, ceff_stats* out);
 ceff_status ceff_contribution_tensors(const double C_eff[36], const double C_host[36], double phi, double H_out[36],
                                       double N_out[36]);
 
+/* The paper's direct test for the off-diagonal constants (appendix on boundary
+ * conditions, eqs. D1-D5): from a triaxial wall test (all three pairs of walls
+ * moved at once) with volume-averaged normal stresses sig_mean = (<s11>, <s22>,
+ * <s33>) and normal strains eps_mean = (<e11>, <e22>, <e33>), and the diagonal
+ * constants C_diag = (C11, C22, C33) of the three normal tests, form
+ *   sbar_ii = sig_mean_i - C_ii eps_mean_i,   ebar_ii = eps_mean_i
+ * and solve  ebar22 C12 + ebar33 C13 = sbar11,  ebar11 C12 + ebar33 C23 = sbar22,
+ *            ebar11 C13 + ebar22 C23 = sbar33
+ * for out = (C12, C13, C23).  Under CEFF_BC_WALLS the solve is linear and the
+ * walls impose the normal strains exactly, so the triaxial test with unit
+ * strains is the sum of the columns of loads 0-2 (sig_mean = their summed
+ * upper three rows, eps_mean = (1, 1, 1)).  Host FP64; needs no device.
+ * CEFF_EINVAL if an input is not finite or a strain is zero. */
+ceff_status ceff_triaxial_offdiagonals(const double sig_mean[3], const double eps_mean[3], const double C_diag[3],
+                                       double out[3]);
+
 #ifdef __cplusplus
 }
 #endif

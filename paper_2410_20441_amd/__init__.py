@@ -31,7 +31,7 @@ __all__ = ["ceff_default_opts", "ceff_create", "ceff_destroy", "ceff_last_error"
            "ceff_set_isotropic", "ceff_set_phases", "ceff_set_stiffness", "ceff_set_boundary", "ceff_solve",
            "ceff_solve_batch", "ceff_solve_batch_phases", "solve_batch_phases",
            "ceff_gradient", "ceff_apt_steps", "ceff_residual", "ceff_average_stress", "ceff_get_stats",
-           "ceff_contribution_tensors", "CeffError", "Context", "solve", "solve_batch", "contribution_tensors",
+           "ceff_contribution_tensors", "ceff_triaxial_offdiagonals", "triaxial_offdiagonals", "CeffError", "Context", "solve", "solve_batch", "contribution_tensors",
            "EffectiveStiffness", "library_path"]
 
 library_path = _lib.LIB_PATH
@@ -127,6 +127,13 @@ def ceff_average_stress(ctx, J, u, out6):
 
 def ceff_get_stats(ctx, out):
     return _check(ctx, _L.ceff_get_stats(ctx, out))
+
+
+def ceff_triaxial_offdiagonals(sig_mean, eps_mean, C_diag, out):
+    st = _L.ceff_triaxial_offdiagonals(sig_mean, eps_mean, C_diag, out)
+    if st != 0:
+        raise CeffError(st, "inputs must be finite and every mean strain nonzero")
+    return st
 
 
 def ceff_contribution_tensors(C_eff, C_host, phi, H_out, N_out):
@@ -337,6 +344,19 @@ def contribution_tensors(C_eff, C_host, phi):
     N = np.empty(36)
     ceff_contribution_tensors(_dptr(Ce), _dptr(Ch), float(phi), _dptr(H), _dptr(N))
     return H.reshape(6, 6), N.reshape(6, 6)
+
+
+def triaxial_offdiagonals(C_walls):
+    """(C12, C13, C23) by the paper's triaxial direct test from the normal wall-test
+    columns of C_walls (loads 0-2 solved with walls): the triaxial test with unit
+    strains is their sum, and C11, C22, C33 are their diagonal (see ceff.h)."""
+    C = np.asarray(C_walls, np.float64).reshape(6, 6)
+    sig = np.ascontiguousarray(C[:3, 0] + C[:3, 1] + C[:3, 2])
+    eps = np.ones(3)
+    Cd = np.ascontiguousarray(np.diag(C)[:3])
+    out = np.empty(3)
+    ceff_triaxial_offdiagonals(_dptr(sig), _dptr(eps), _dptr(Cd), _dptr(out))
+    return out
 
 
 def solve_batch(samples, h=None, loads=range(6), device=0, allow_unconverged=False, **kw):

@@ -67,6 +67,7 @@ SIGNATURES = {
     "ceff_average_stress": (_st, [_vp, ctypes.c_int, _dp, _dp]),
     "ceff_get_stats": (_st, [_vp, ctypes.POINTER(ceff_stats)]),
     "ceff_contribution_tensors": (_st, [_dp, _dp, ctypes.c_double, _dp, _dp]),
+    "ceff_triaxial_offdiagonals": (_st, [_dp, _dp, _dp, _dp]),
 }
 
 _lib = None

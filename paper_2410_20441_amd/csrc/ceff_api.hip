@@ -1699,4 +1699,22 @@ ceff_status ceff_contribution_tensors(const double C_eff[36], const double C_hos
   return CEFF_OK;
 }
 
+ceff_status ceff_triaxial_offdiagonals(const double sig_mean[3], const double eps_mean[3], const double C_diag[3],
+                                       double out[3]) {
+  if (!sig_mean || !eps_mean || !C_diag || !out) return CEFF_EINVAL;
+  double sb[3], eb[3];
+  for (int d = 0; d < 3; ++d) {
+    if (!std::isfinite(sig_mean[d]) || !std::isfinite(eps_mean[d]) || !std::isfinite(C_diag[d]) ||
+        eps_mean[d] == 0.0)
+      return CEFF_EINVAL;
+    eb[d] = eps_mean[d];
+    sb[d] = sig_mean[d] - C_diag[d] * eps_mean[d];
+  }
+  // each combination below isolates one unknown of the three equations
+  out[0] = (eb[0] * sb[0] + eb[1] * sb[1] - eb[2] * sb[2]) / (2.0 * eb[0] * eb[1]);
+  out[1] = (eb[0] * sb[0] - eb[1] * sb[1] + eb[2] * sb[2]) / (2.0 * eb[0] * eb[2]);
+  out[2] = (-eb[0] * sb[0] + eb[1] * sb[1] + eb[2] * sb[2]) / (2.0 * eb[1] * eb[2]);
+  return CEFF_OK;
+}
+
 }  // extern "C"

@@ -134,6 +134,10 @@ def test_walls_paper_layered_model_full_size():
            "C66": (5, 5)}
     for name, (I, J) in idx.items():
         assert round(C[I, J], 3) == pytest.approx(g["analytic_GPa"][name], abs=1e-12), name
+    # the paper's own route to the off-diagonal constants: triaxial test + D1-D5
+    C12, C13, C23 = p.triaxial_offdiagonals(C)
+    for name, v in (("C12", C12), ("C13", C13), ("C23", C23)):
+        assert round(v, 3) == pytest.approx(g["analytic_GPa"][name], abs=1e-12), name
     slab = synth.laminate_z(1, 191, 191, geo["stiff_layers"], geo["layer_thickness"],
                             stiff=(st["K"], st["G"]), soft=(so["K"], so["G"]))
     Co, _ = oracle.ceff_walls(*slab.fields(), rtol=1e-12, loads=(3,))
@@ -160,3 +164,22 @@ def test_walls_errors():
         with pytest.raises(p.CeffError) as e:
             c.solve(loads=(0,), precision="fp64")
         assert e.value.status == _lib.CEFF_EUNSUPPORTED
+
+
+def test_triaxial_offdiagonals_formula():
+    """D1-D5 recover the off-diagonal constants of any symmetric normal block from a
+    triaxial test with arbitrary nonzero strains; zero or non-finite input is rejected."""
+    p = need_gpu()
+    from paper_2410_20441_amd import _lib
+    import ctypes
+    Cn = np.array([[80.0, 31.0, 27.0], [31.0, 66.0, 22.0], [27.0, 22.0, 51.0]])
+    eps = np.array([0.7, -1.3, 2.1])
+    sig = Cn @ eps
+    out = np.empty(3)
+    dp = ctypes.POINTER(ctypes.c_double)
+    a = lambda x: np.ascontiguousarray(x, np.float64).ctypes.data_as(dp)
+    p.ceff_triaxial_offdiagonals(a(sig), a(eps), a(np.diag(Cn)), out.ctypes.data_as(dp))
+    np.testing.assert_allclose(out, [31.0, 27.0, 22.0], rtol=1e-13)
+    for bad in ([0.7, 0.0, 2.1], [0.7, np.nan, 2.1]):
+        assert p._L.ceff_triaxial_offdiagonals(a(sig), a(bad), a(np.diag(Cn)), out.ctypes.data_as(dp)) == \
+            _lib.CEFF_EINVAL
