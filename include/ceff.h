@@ -76,6 +76,14 @@ typedef struct {
   int autotune;         /* 1: time candidate tile shapes first (cached per shape) */
   double fold_ratio;    /* MIXED: fold the FP32 correction into the FP64 displacement when
                            the residual fell by this factor since the last fold */
+  const double* warm_u; /* optional initial displacement fluctuation (host FP64, 6 x 3N,
+                           load-major: load J's u_x, u_y, u_z at warm_u + J*3N, component-
+                           major like ceff_residual's u), or NULL for the zero start.  MIXED:
+                           it becomes the FP64 displacement and the FP32 sweeps start on a
+                           zero correction with its residual as the body force (as after a
+                           fold); FP64: it is the first iterate.  Relative residuals stay
+                           normalised by the zero start's ||div(C:E)||.  ceff_solve only,
+                           periodic boundaries (CEFF_EUNSUPPORTED with walls). */
 } ceff_solve_opts;
 
 /* Execution counters of the most recent solve (for roofline accounting). */
@@ -102,7 +110,7 @@ typedef struct {
 
 /* Fill *o with the defaults: MIXED, rtol 1e-8, max_iter 2e6, check_every 100,
  * courant 0.95, strouhal 2.0, fuse_loads CEFF_FUSE_AUTO, use_graph 1, keep_fields 0,
- * autotune 0, fold_ratio 1e-3. */
+ * autotune 0, fold_ratio 1e-3, warm_u NULL. */
 void ceff_default_opts(ceff_solve_opts* o);
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t the

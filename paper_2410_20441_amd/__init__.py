@@ -267,8 +267,15 @@ class Context:
         self.shape = (nz, ny, nx)
         self.h_spacing = tuple(map(float, h))
 
-    def solve(self, loads=range(6), hist_cap=100000, allow_unconverged=False, **kw):
+    def solve(self, loads=range(6), hist_cap=100000, allow_unconverged=False, warm_u=None, **kw):
+        """warm_u: optional initial displacement fluctuation, (6, 3, nz, ny, nx) FP64 (entries of
+        loads not solved are ignored), see ceff_solve_opts::warm_u."""
         o = make_opts(**kw)
+        if warm_u is not None:
+            warm = np.ascontiguousarray(warm_u, np.float64)
+            if warm.size != 6 * 3 * int(np.prod(self.shape)):
+                raise ValueError("warm_u must hold 6 x 3N values")
+            o.warm_u = warm.ctypes.data  # `warm` stays referenced until the call returns
         mask = 0
         for J in loads:
             mask |= 1 << int(J)

@@ -27,7 +27,7 @@ class ceff_solve_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int64),
                 ("check_every", ctypes.c_int), ("courant", ctypes.c_double), ("strouhal", ctypes.c_double),
                 ("fuse_loads", ctypes.c_int), ("use_graph", ctypes.c_int), ("keep_fields", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("fold_ratio", ctypes.c_double)]
+                ("autotune", ctypes.c_int), ("fold_ratio", ctypes.c_double), ("warm_u", ctypes.c_void_p)]
 
 
 class ceff_stats(ctypes.Structure):

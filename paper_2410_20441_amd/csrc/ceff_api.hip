@@ -788,6 +788,47 @@ struct Engine {
     }
   }
 
+  // Initial guess (ceff_solve_opts::warm_u, one image).  MIXED: the guess becomes
+  // the FP64 displacement and each problem starts as right after a fold: zero FP32
+  // correction, the FP64 residual of the guess as body force, no macroscopic
+  // strain in the sweep.  FP64: the guess is the first iterate.
+  ceff_status apply_warm() {
+    const int64_t N = in[0].nx * in[0].ny * in[0].nz;
+    std::vector<Prob*> warm;
+    for (auto& p : probs) {
+      if (!p.active) continue;
+      const double* src = o.warm_u + (int64_t)p.J * 3 * N;
+      if (mixed) {
+        HIPCK(c, hipMemcpyAsync(base[p.s][p.slot].p, src, sizeof(double) * 3 * N, hipMemcpyHostToDevice, c->s));
+        h_out[p.s].active |= 1u << p.slot;
+        warm.push_back(&p);
+      } else {
+        HIPCK(c, hipMemcpyAsync(h_in[p.s].u[0][p.slot], src, sizeof(double) * 3 * N, hipMemcpyHostToDevice, c->s));
+      }
+    }
+    if (!mixed) return CEFF_OK;
+    std::vector<double> n64;
+    STCK(outer_pass(true, n64));
+    for (auto& d : h_out) d.active = 0;
+    for (Prob* p : warm) {
+      const double rr = std::sqrt(n64[(size_t)p->s * kMaxLoads + p->slot]) / p->r0;
+      p->relres = rr;
+      record(0, p->J, rr);
+      if (!std::isfinite(rr) || rr <= o.rtol) {
+        p->active = false;
+        p->iters = 0;
+        p->st = std::isfinite(rr) ? CEFF_OK : CEFF_EDIVERGED;
+        h_in[p->s].active &= ~(1u << p->slot);
+        continue;
+      }
+      p->relres_base = rr;
+      p->phase = 1;
+      for (int q = 0; q < 6; ++q) h_in[p->s].E[p->slot][q] = T(0);
+      h_in[p->s].force[p->slot] = (const T*)force[p->s][p->slot].as<float>();
+    }
+    return CEFF_OK;
+  }
+
   ceff_status solve() {
     STCK(setup());
     // initial residual norms ||div(C:E)|| in FP64 (all displacements are zero)
@@ -814,11 +855,12 @@ struct Engine {
       }
     }
     for (auto& d : h_out) d.active = 0;
+    if (o.warm_u) STCK(apply_warm());
     bool any = false;
     for (auto& p : probs) any |= p.active;
     if (any) {
       STCK(upload_desc());
-      // first iteration: u^1 from u^0 = 0 without momentum
+      // first iteration: u^1 from u^0 (zero, or the initial guess) without momentum
       const double bpl = bytes_per_launch() * 6.0 / 9.0, vpl = vu_per_launch();
       HIPCK(c, hipEventRecord(c->ev0, c->s));
       parity = 0;
@@ -1099,6 +1141,7 @@ void ceff_default_opts(ceff_solve_opts* o) {
   o->keep_fields = 0;
   o->autotune = 0;
   o->fold_ratio = 1e-3;
+  o->warm_u = nullptr;
 }
 
 ceff_status ceff_create(int device, void* hip_stream, ceff_ctx** out) {
@@ -1286,6 +1329,7 @@ ceff_status ceff_solve(ceff_ctx* c, uint32_t load_mask, const ceff_solve_opts* o
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
   const bool walls = c->boundary == CEFF_BC_WALLS;
   if (walls && c->ortho) return fail(c, CEFF_EUNSUPPORTED, "wall boundaries with orthotropic cells");
+  if (walls && o.warm_u) return fail(c, CEFF_EUNSUPPORTED, "an initial guess with wall boundaries");
   STCK(begin_call(c));
   const auto t0 = std::chrono::steady_clock::now();
   c->stats = ceff_stats{};
@@ -1341,6 +1385,7 @@ ceff_status ceff_solve_batch(ceff_ctx* c, int nsamples, const int64_t* dims, con
   if (opts) o = *opts;
   STCK(validate_opts(c, o));
   if (nsamples < 1 || nsamples > 100000) return fail(c, CEFF_EINVAL, "nsamples out of range");
+  if (o.warm_u) return fail(c, CEFF_EINVAL, "warm_u applies to ceff_solve only");
   if (!dims || !h || !K || !G || !C_out) return fail(c, CEFF_EINVAL, "null argument");
   if (dtype != CEFF_F32 && dtype != CEFF_F64) return fail(c, CEFF_EINVAL, "dtype must be CEFF_F32 or CEFF_F64");
   if (where != CEFF_HOST && where != CEFF_DEVICE) return fail(c, CEFF_EINVAL, "where must be CEFF_HOST or CEFF_DEVICE");
@@ -1406,6 +1451,7 @@ ceff_status ceff_solve_batch_phases(ceff_ctx* c, int nsamples, const int64_t* di
   if (opts) o = *opts;
   STCK(validate_opts(c, o));
   if (nsamples < 1 || nsamples > 100000) return fail(c, CEFF_EINVAL, "nsamples out of range");
+  if (o.warm_u) return fail(c, CEFF_EINVAL, "warm_u applies to ceff_solve only");
   if (!dims || !h || !phase || !K_tab || !G_tab || !C_out) return fail(c, CEFF_EINVAL, "null argument");
   if (nphase < 1 || nphase > 256) return fail(c, CEFF_EINVAL, "nphase must be in [1, 256]");
   if (where != CEFF_HOST && where != CEFF_DEVICE) return fail(c, CEFF_EINVAL, "where must be CEFF_HOST or CEFF_DEVICE");

@@ -313,3 +313,33 @@ def test_large_grid_launch_shape(monkeypatch, fuse):
     cols = list(opts["loads"])
     assert np.max(np.abs(C[:, cols] - C2[:, cols])) <= 1e-12 * np.abs(C[:, cols]).max()
     assert np.array_equal(info["iters"], info2["iters"])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_warm_start(precision):
+    """An initial guess (ceff_solve_opts::warm_u): the oracle's converged fields need no
+    iterations in mixed precision (their residual is already below rtol) and at most one
+    check interval in FP64; 90% of them needs fewer iterations than the zero start; C*
+    keeps the oracle's value.  With walls the option is refused."""
+    p = need_gpu()
+    from paper_2410_20441_amd import _lib
+    K, G = synth.random_fields((12, 10, 9), 77, lo=(2.0, 1.0), hi=(90.0, 45.0))
+    U = np.stack([oracle.solve_load(K, G, J, rtol=1e-13)[0] for J in range(6)])
+    Co, _ = oracle.ceff(K, G, rtol=1e-12)
+    announce("warm start", precision)
+    with p.Context() as c:
+        c.set_material(K, G)
+        C0, i0 = c.solve(precision=precision, rtol=1e-9)
+        C1, i1 = c.solve(precision=precision, rtol=1e-9, warm_u=U)
+        C2, i2 = c.solve(precision=precision, rtol=1e-9, warm_u=0.9 * U)
+        if precision == "mixed":
+            assert np.all(i1["iters"] == 0)
+        else:
+            assert i1["iters"].max() <= 100
+        assert np.all(i2["iters"] < i0["iters"]), (i2["iters"], i0["iters"])
+        for C in (C0, C1, C2):
+            assert matrix_rel(C, Co) <= 1e-6
+        c.set_boundary("walls")
+        with pytest.raises(p.CeffError) as e:
+            c.solve(loads=(0,), precision=precision, warm_u=U)
+        assert e.value.status == _lib.CEFF_EUNSUPPORTED
