@@ -123,7 +123,7 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the design notes describe how the solve would shard)", file=sys.stderr)
         sys.exit(2)
     import torch
