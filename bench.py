@@ -222,7 +222,13 @@ def main():
                      "kernel": "%s<float,%s> (heavy-ball APT iteration, loads per block = %s)" % (
                          VARIANT_KERNEL[st["tile_variant"]], st["tile_group"], st["tile_group"]),
                      "avg_launch_ms": tot["step_ms"] / max(tot["launches"], 1),
-                     "bytes_per_launch": tot["step_bytes"] / max(tot["launches"], 1)},
+                     "bytes_per_launch": tot["step_bytes"] / max(tot["launches"], 1),
+                     # the launch's distinct data: per voxel and load the two FP32 displacement
+                     # buffers (u^n, and the one u^{n-1} is read from and u^{n+1} written to) and the
+                     # body force, 12 B each, plus the 1-byte phase image; when it fits in the 256 MiB
+                     # Infinity Cache, part of the traffic is served there rather than by HBM
+                     "working_set_bytes": float(N) * (36.0 * (6 if st["fused_loads"] else 1) + 1.0),
+                     "infinity_cache_bytes": 256 * 2 ** 20},
         "C_eff_GPa": np.round(C, 6).tolist(),
     }
 
