@@ -113,6 +113,15 @@ typedef struct {
  * autotune 0, fold_ratio 1e-3, warm_u NULL. */
 void ceff_default_opts(ceff_solve_opts* o);
 
+/* Check a grid against this build's limits without a context or a device: each
+ * dimension in [2, 2^20], one z-plane nx*ny of at most 2^28 cells (2 GiB of
+ * FP64), spacings finite and > 0.  Returns CEFF_OK or CEFF_EINVAL.  The same
+ * check guards ceff_set_grid and the batch calls.  There is no limit on the
+ * total number of cells beyond device memory: the iteration kernels address a
+ * field one z-plane at a time, with a 32-bit offset within the plane.  Host
+ * only; needs no device. */
+ceff_status ceff_check_grid(int64_t nx, int64_t ny, int64_t nz, double hx, double hy, double hz);
+
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t the
  * caller orders its device inputs on (NULL = the null stream).  The library
  * runs its own work on an internal stream of default priority. */
@@ -122,7 +131,9 @@ void ceff_destroy(ceff_ctx* ctx);
 const char* ceff_last_error(const ceff_ctx* ctx);
 
 /* Grid dimensions (each in [2, 2^20], with nx*ny <= 2^28) and voxel spacings
- * (> 0).  Clears material and kept fields. */
+ * (> 0), the cells of the paper's staggered grid ("Discretization").  Clears
+ * material and kept fields.  CEFF_EINVAL for a grid outside the limits (see
+ * ceff_check_grid). */
 ceff_status ceff_set_grid(ceff_ctx* ctx, int64_t nx, int64_t ny, int64_t nz, double hx, double hy, double hz);
 
 /* Per-voxel isotropic moduli K(x), G(x) (paper: each voxel carries the bulk
@@ -234,7 +245,7 @@ ceff_status ceff_residual(ceff_ctx* ctx, int J, int precision, const double* u, 
  * unit load J, Voigt order (paper: the volume-averaged stress). */
 ceff_status ceff_average_stress(ceff_ctx* ctx, int J, const double* u, double out6[6]);
 
-/* Counters of the most recent solve. */
+/* Counters of the most recent solve (ceff_apt_steps: the launch shape only). */
 ceff_status ceff_get_stats(const ceff_ctx* ctx, ceff_stats* out);
 
 /* ---- property contribution tensors (host arithmetic, no context) ------------ */

@@ -27,7 +27,7 @@ from ._lib import (CEFF_DEVICE, CEFF_F32, CEFF_F64, CEFF_FUSE_AUTO, CEFF_HOST, C
 
 _L = _lib.load()
 
-__all__ = ["ceff_default_opts", "ceff_create", "ceff_destroy", "ceff_last_error", "ceff_set_grid",
+__all__ = ["ceff_default_opts", "ceff_check_grid", "ceff_create", "ceff_destroy", "ceff_last_error", "ceff_set_grid",
            "ceff_set_isotropic", "ceff_set_phases", "ceff_set_stiffness", "ceff_set_boundary", "ceff_solve",
            "ceff_solve_batch", "ceff_solve_batch_phases", "solve_batch_phases",
            "ceff_gradient", "ceff_apt_steps", "ceff_residual", "ceff_average_stress", "ceff_get_stats",
@@ -49,6 +49,11 @@ def ceff_default_opts(o=None):
     o = o if o is not None else ceff_solve_opts()
     _L.ceff_default_opts(ctypes.byref(o))
     return o
+
+
+def ceff_check_grid(nx, ny, nz, hx=1.0, hy=1.0, hz=1.0):
+    """Status of the grid against the library's limits (host only, no device)."""
+    return _L.ceff_check_grid(nx, ny, nz, hx, hy, hz)
 
 
 def ceff_create(device=0, hip_stream=None):

@@ -48,6 +48,7 @@ _st = ctypes.c_int
 # name -> (restype, argtypes); every symbol of include/ceff.h
 SIGNATURES = {
     "ceff_default_opts": (None, [ctypes.POINTER(ceff_solve_opts)]),
+    "ceff_check_grid": (_st, [_i64, _i64, _i64, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "ceff_create": (_st, [ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "ceff_destroy": (None, [_vp]),
     "ceff_last_error": (ctypes.c_char_p, [_vp]),

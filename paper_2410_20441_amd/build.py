@@ -1,4 +1,9 @@
-"""Build libceff.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libceff.so (HIP, gfx950) in-tree with hipcc.
+
+The kernel source compiles as four parts (CEFF_KPART = 0..3, each emitting a
+share of the kernel instantiations) and the host driver as one object, all in
+parallel; the objects then link into one library.
+"""
 import os
 import subprocess
 import sys
@@ -8,9 +13,10 @@ ROOT = os.path.dirname(HERE)
 SRCS = [os.path.join(HERE, "csrc", f) for f in ("ceff_kernels.hip", "ceff_api.hip")]
 HDRS = [os.path.join(HERE, "csrc", "ceff_internal.h"), os.path.join(ROOT, "include", "ceff.h")]
 LIB = os.path.join(HERE, "libceff.so")
+OBJDIR = os.path.join(HERE, "_build")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions: scalar/float2 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
@@ -30,10 +36,25 @@ def build(force: bool = True, verbose: bool = False) -> str:
         t = os.path.getmtime(LIB)
         if all(os.path.getmtime(f) <= t for f in SRCS + HDRS):
             return LIB
-    cmd = [hipcc()] + FLAGS + ["-o", LIB + ".tmp"] + SRCS
+    os.makedirs(OBJDIR, exist_ok=True)
+    quiet = ["-Wno-unused-function", "-Wno-unneeded-internal-declaration"]
+    units = [(SRCS[0], ["-DCEFF_KPART=%d" % k] + quiet, "ceff_kernels_%d.o" % k) for k in range(4)]
+    units.append((SRCS[1], [], "ceff_api.o"))
+    objs, procs = [], []
+    for src, defs, name in units:
+        obj = os.path.join(OBJDIR, name)
+        cmd = [hipcc()] + FLAGS + defs + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+        objs.append(obj)
+    for p, cmd in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
+    link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

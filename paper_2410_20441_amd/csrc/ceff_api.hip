@@ -33,6 +33,10 @@
 
 using namespace ceff;
 
+// Block partials of the stress averages: the kernel strides over the cells
+// with at most this many blocks, whatever the grid.
+constexpr int kAvgBlocks = 4096;
+
 namespace {
 
 struct DevBuf {
@@ -137,10 +141,13 @@ ceff_status validate_opts(ceff_ctx* c, const ceff_solve_opts& o) {
   return CEFF_OK;
 }
 
+// The grid limits of every entry point.  The iteration kernels address a field
+// through a view of one z-plane of one component and a thread's 32-bit byte
+// offset within it, so the only size limit is that of a plane (below 2 GiB of
+// FP64); the total size of a field is limited by device memory alone.
 ceff_status validate_grid(ceff_ctx* c, int64_t nx, int64_t ny, int64_t nz, const double* h) {
   if (nx < 2 || ny < 2 || nz < 2) return fail(c, CEFF_EINVAL, "grid dimensions must be >= 2");
   if (nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20)) return fail(c, CEFF_EINVAL, "grid dimension too large");
-  // the iteration kernels address a column within a z-plane with a 32-bit byte offset
   if (nx * ny * (int64_t)sizeof(double) > ((int64_t)1 << 31)) return fail(c, CEFF_EINVAL, "z-plane too large");
   for (int d = 0; d < 3; ++d)
     if (!(h[d] > 0.0) || !std::isfinite(h[d])) return fail(c, CEFF_EINVAL, "spacings must be finite and > 0");
@@ -966,24 +973,42 @@ struct Engine {
   }
 };
 
-ceff_status stress_average(ceff_ctx* c, const SampleIn& s, int J, const double* u, double out6[6]) {
+// FP64 volume averages of the six stresses of u under unit load J, with the
+// kernel's block partials (6 per block, at most cap blocks) in `part` and the
+// six sums in `o6` (device memory).
+ceff_status stress_average_into(ceff_ctx* c, const SampleIn& s, int J, const double* u, double* part, int cap,
+                                double* o6, double out6[6]) {
   const int64_t N = s.nx * s.ny * s.nz;
-  DevBuf part, o6;
-  const int cap = 4096;
-  HIPCK(c, part.alloc(sizeof(double) * 6 * cap));
-  HIPCK(c, o6.alloc(sizeof(double) * 6));
   double E[6];
   unit_strain(J, E);
   if (s.c64)
-    HIPCK(c, launch_average_stress_ortho(s.nx, s.ny, s.nz, s.h, s.c64, E, u, part.as<double>(), cap,
-                                         o6.as<double>(), c->s));
+    HIPCK(c, launch_average_stress_ortho(s.nx, s.ny, s.nz, s.h, s.c64, E, u, part, cap, o6, c->s));
   else
-    HIPCK(c, launch_average_stress(s.nx, s.ny, s.nz, s.h, s.K64, s.G64, E, u, part.as<double>(), cap,
-                                   o6.as<double>(), s.walls ? (J >= 3 ? J : 1) : 0, c->s));
-  HIPCK(c, hipMemcpyAsync(out6, o6.p, sizeof(double) * 6, hipMemcpyDeviceToHost, c->s));
+    HIPCK(c, launch_average_stress(s.nx, s.ny, s.nz, s.h, s.K64, s.G64, E, u, part, cap, o6,
+                                   s.walls ? (J >= 3 ? J : 1) : 0, c->s));
+  HIPCK(c, hipMemcpyAsync(out6, o6, sizeof(double) * 6, hipMemcpyDeviceToHost, c->s));
   HIPCK(c, hipStreamSynchronize(c->s));
   for (int q = 0; q < 6; ++q) out6[q] /= (double)N;
   return CEFF_OK;
+}
+
+
+ceff_status stress_average(ceff_ctx* c, const SampleIn& s, int J, const double* u, double out6[6]) {
+  DevBuf part, o6;
+  HIPCK(c, part.alloc(sizeof(double) * 6 * kAvgBlocks));
+  HIPCK(c, o6.alloc(sizeof(double) * 6));
+  return stress_average_into(c, s, J, u, part.as<double>(), kAvgBlocks, o6.as<double>(), out6);
+}
+
+// The launch shape an engine ran with, into the context's counters.
+template <typename T>
+void record_shape(ceff_ctx* c, const Engine<T>& e) {
+  c->stats.tile_bx = e.ts.bx;
+  c->stats.tile_by = e.ts.by;
+  c->stats.tile_kc = e.h_in.empty() ? 0 : e.h_in[0].kc;
+  c->stats.tile_group = e.group();
+  c->stats.tile_variant = e.ts.pf;
+  c->stats.phase_moduli = e.ts.pal;
 }
 
 template <typename T>
@@ -1018,12 +1043,7 @@ ceff_status run_engine(ceff_ctx* c, std::vector<SampleIn> samples, std::vector<i
   c->stats.step_bytes += e.step_bytes;
   c->stats.voxel_updates += e.vu;
   c->stats.outer_checks += e.outer;
-  c->stats.tile_bx = e.ts.bx;
-  c->stats.tile_by = e.ts.by;
-  c->stats.tile_kc = e.h_in.empty() ? 0 : e.h_in[0].kc;
-  c->stats.tile_group = e.group();
-  c->stats.tile_variant = e.ts.pf;
-  c->stats.phase_moduli = e.ts.pal;
+  record_shape(c, e);
   return CEFF_OK;
 }
 
@@ -1142,6 +1162,11 @@ void ceff_default_opts(ceff_solve_opts* o) {
   o->autotune = 0;
   o->fold_ratio = 1e-3;
   o->warm_u = nullptr;
+}
+
+ceff_status ceff_check_grid(int64_t nx, int64_t ny, int64_t nz, double hx, double hy, double hz) {
+  const double h[3] = {hx, hy, hz};
+  return validate_grid(nullptr, nx, ny, nz, h);
 }
 
 ceff_status ceff_create(int device, void* hip_stream, ceff_ctx** out) {
@@ -1616,6 +1641,8 @@ ceff_status ceff_apt_steps(ceff_ctx* c, int J, int64_t nsteps, int precision, do
     e.Lk = 1;
     e.Js = {J};
     STCK(e.setup());
+    c->stats = ceff_stats{};
+    record_shape(c, e);
     e.h_in[0].active = 1u;
     STCK(e.upload_desc());
     e.parity = 0;

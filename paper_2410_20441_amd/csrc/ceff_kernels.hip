@@ -30,6 +30,15 @@
 
 #include <type_traits>
 
+// The build compiles this file several times, with CEFF_KPART = 0, 1, 2, 3, in
+// parallel; each compilation emits one share of the launch wrappers (0: all but
+// the iteration kernels, 1: FP32 iteration with 1 or 2 loads per block, 2: FP32
+// with 3 or 6, 3: FP64).  Without CEFF_KPART one compilation emits everything.
+#ifndef CEFF_KPART
+#define CEFF_KPART -1
+#endif
+#define CEFF_IN_PART(n) (CEFF_KPART < 0 || CEFF_KPART == (n))
+
 namespace ceff {
 
 namespace {
@@ -127,38 +136,39 @@ __device__ __forceinline__ float tmin(float a, float b) {
 }
 __device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
 
-// Raw buffer view of a device array (at most 4 GiB - 1 bytes).  Accesses take
-// a per-thread 32-bit byte offset (here: the column within a z-plane, fixed for
-// the whole march) plus a uniform 32-bit byte offset (component and plane), and
-// the descriptor sits in scalar registers, so no per-access address arithmetic
-// runs on the vector ALU.  Reads outside the range return 0.
-struct BufView {
+// Raw buffer view of one z-plane of one field component: the descriptor (base
+// address of the component's plane, byte range of one plane) is formed on the
+// scalar unit from uniform values, and an access takes the thread's 32-bit byte
+// offset of its column within the plane.  The vector ALU then does no address
+// arithmetic, and no offset spans more than one plane (the host keeps a plane
+// below 2 GiB), whatever the size of the field.  Reads outside the plane's
+// range return 0.
+struct PlaneBuf {
   __amdgpu_buffer_rsrc_t r;
-  __device__ __forceinline__ BufView() {}
-  __device__ __forceinline__ BufView(const void* p, uint32_t bytes)
+  __device__ __forceinline__ PlaneBuf(const void* p, uint32_t bytes)
       : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
-  __device__ __forceinline__ float ldf(uint32_t v, uint32_t s) const {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, 0));
+  __device__ __forceinline__ float ldf(uint32_t v) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, 0, 0));
   }
-  __device__ __forceinline__ double ldd(uint32_t v, uint32_t s) const {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, 0));
+  __device__ __forceinline__ double ldd(uint32_t v) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, 0, 0));
   }
-  __device__ __forceinline__ uint32_t ldb(uint32_t v, uint32_t s) const {
-    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)v, (int)s, 0);
+  __device__ __forceinline__ uint32_t ldb(uint32_t v) const {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)v, 0, 0);
   }
-  __device__ __forceinline__ void st(uint32_t v, uint32_t s, float x) const {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, (int)v, (int)s, 0);
+  __device__ __forceinline__ void st(uint32_t v, float x) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, (int)v, 0, 0);
   }
-  __device__ __forceinline__ void st(uint32_t v, uint32_t s, double x) const {
+  __device__ __forceinline__ void st(uint32_t v, double x) const {
     using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, (int)v, (int)s, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, (int)v, 0, 0);
   }
   template <typename T>
-  __device__ __forceinline__ T ld(uint32_t v, uint32_t s) const {
+  __device__ __forceinline__ T ld(uint32_t v) const {
     if constexpr (sizeof(T) == 4)
-      return ldf(v, s);
+      return ldf(v);
     else
-      return ldd(v, s);
+      return ldd(v);
   }
 };
 
@@ -167,52 +177,38 @@ struct BufView {
 // returned into coefficients.  PAL = false: from the K and G fields (2 words per
 // cell).  PAL = true: from the 1-byte phase id and a per-phase coefficient table
 // staged in LDS; the table entries come from the same cell_coef on the same
-// values, so both give identical results.
-// BUF: buffer accesses (see BufView); otherwise pointer plus 64-bit index.
-template <typename T, bool PAL, bool BUF>
+// values, so both give identical results.  pk: element offset of the z-plane;
+// col, colb: the column's element and byte offset within it.
+template <typename T, bool PAL>
 struct Moduli {
   struct Raw {
     T K, G;
   };
-  BufView Kb, Gb;
-  const GLOBAL_AS T* Kf;
-  const GLOBAL_AS T* Gf;
-  __device__ Moduli(const SampleDesc<T>& sd, const CellCoef<T>*) : Kf(gconst(sd.K)), Gf(gconst(sd.G)) {
-    if constexpr (BUF) {
-      Kb = BufView(sd.K, (uint32_t)(sd.N * sizeof(T)));
-      Gb = BufView(sd.G, (uint32_t)(sd.N * sizeof(T)));
-    }
-  }
-  // cell of column col (byte offset colb = col * sizeof(T)) in the plane starting at element pk
-  __device__ __forceinline__ Raw load(int64_t pk, int64_t o, uint32_t col, uint32_t colb) const {
+  const T* Kf;
+  const T* Gf;
+  uint32_t pbytes;  // bytes of one plane of K (or G)
+  __device__ Moduli(const SampleDesc<T>& sd, const CellCoef<T>*)
+      : Kf(sd.K), Gf(sd.G), pbytes((uint32_t)(sd.nx * sd.ny * (int64_t)sizeof(T))) {}
+  __device__ __forceinline__ Raw load(int64_t pk, uint32_t col, uint32_t colb) const {
     (void)col;
-    if constexpr (BUF) {
-      const uint32_t so = (uint32_t)(pk * (int64_t)sizeof(T));
-      return Raw{Kb.template ld<T>(colb, so), Gb.template ld<T>(colb, so)};
-    } else {
-      return Raw{Kf[o], Gf[o]};
-    }
+    return Raw{PlaneBuf(Kf + pk, pbytes).template ld<T>(colb), PlaneBuf(Gf + pk, pbytes).template ld<T>(colb)};
   }
   __device__ __forceinline__ CellCoef<T> coef(Raw r) const { return cell_coef(r.K, r.G); }
 };
 
-template <typename T, bool BUF>
-struct Moduli<T, true, BUF> {
+template <typename T>
+struct Moduli<T, true> {
   struct Raw {
     uint32_t p;
   };
-  BufView pb;
-  const GLOBAL_AS uint8_t* ph;
+  const uint8_t* ph;
   const CellCoef<T>* tab;
-  __device__ Moduli(const SampleDesc<T>& sd, const CellCoef<T>* t) : ph(gconst(sd.phase)), tab(t) {
-    if constexpr (BUF) pb = BufView(sd.phase, (uint32_t)sd.N);
-  }
-  __device__ __forceinline__ Raw load(int64_t pk, int64_t o, uint32_t col, uint32_t colb) const {
+  uint32_t pbytes;  // bytes of one plane of the phase image
+  __device__ Moduli(const SampleDesc<T>& sd, const CellCoef<T>* t)
+      : ph(sd.phase), tab(t), pbytes((uint32_t)(sd.nx * sd.ny)) {}
+  __device__ __forceinline__ Raw load(int64_t pk, uint32_t col, uint32_t colb) const {
     (void)colb;
-    if constexpr (BUF)
-      return Raw{pb.ldb(col, (uint32_t)pk)};
-    else
-      return Raw{ph[o]};
+    return Raw{PlaneBuf(ph + pk, pbytes).ldb(col)};
   }
   __device__ __forceinline__ CellCoef<T> coef(Raw r) const { return tab[r.p]; }
 };
@@ -780,63 +776,29 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
     const bool wx = WALLS && wrap_idx(gi, nx) == 0, wy = WALLS && wrap_idx(gj, ny) == 0;
     const int wsh = WALLS ? sd.wshear[s0] : 0;
 
-    // One load per block: every access is a buffer access (descriptor and
-    // component/plane offset uniform, the column's 32-bit byte offset per
-    // thread; the host keeps each 3N-element field below 4 GiB for this).  With
-    // several loads the descriptors would crowd the scalar registers, so those
-    // use pointers and 64-bit element indices.
-    constexpr bool BUF = L == 1;
-    const Moduli<T, PAL, BUF> mod(sd, tab);
+    // every field access: a buffer view of the component's z-plane (see PlaneBuf)
+    const Moduli<T, PAL> mod(sd, tab);
     const uint32_t col32 = (uint32_t)col, colb = (uint32_t)col * (uint32_t)sizeof(T);
-    const uint32_t fb = (uint32_t)(3 * N * (int64_t)sizeof(T));
-    const int64_t cN = N * (int64_t)sizeof(T);  // byte stride between components
-    BufView ucur[L], uold[L], frc[L];
-    const GLOBAL_AS T* pcur[L];
-    GLOBAL_AS T* pold[L];
-    const GLOBAL_AS T* pfrc[L];
+    const uint32_t pbytes = (uint32_t)(plane * (int64_t)sizeof(T));
+    const T* pcur[L];
+    T* pold[L];
+    const T* pfrc[L];
     bool hasf[L];
     T E[L][6];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       hasf[l] = sd.force[s0 + l] != nullptr;
-      if constexpr (BUF) {
-        ucur[l] = BufView(sd.u[parity][s0 + l], fb);
-        uold[l] = BufView(sd.u[parity ^ 1][s0 + l], fb);
-        frc[l] = BufView(sd.force[s0 + l], hasf[l] ? fb : 0u);
-      } else {
-        pcur[l] = gconst(sd.u[parity][s0 + l]);
-        pold[l] = gmut(sd.u[parity ^ 1][s0 + l]);
-        pfrc[l] = gconst(sd.force[s0 + l]);
-      }
+      pcur[l] = sd.u[parity][s0 + l];
+      pold[l] = sd.u[parity ^ 1][s0 + l];
+      pfrc[l] = sd.force[s0 + l];
 #pragma unroll
       for (int q = 0; q < 6; ++q) E[l][q] = sd.E[s0 + l][q];
     }
-    // component c of load l's fields at plane element offset pk; o = col + pk
-    // is the cell's element index (used by the pointer form)
-    auto ldu = [&](int l, int c, int64_t pk, int64_t o) -> T {
-      if constexpr (BUF)
-        return ucur[l].template ld<T>(colb, (uint32_t)(c * cN + pk * (int64_t)sizeof(T)));
-      else
-        return pcur[l][c * N + o];
-    };
-    auto ldo_ = [&](int l, int c, int64_t pk, int64_t o) -> T {
-      if constexpr (BUF)
-        return uold[l].template ld<T>(colb, (uint32_t)(c * cN + pk * (int64_t)sizeof(T)));
-      else
-        return pold[l][c * N + o];
-    };
-    auto ldf = [&](int l, int c, int64_t pk, int64_t o) -> T {
-      if constexpr (BUF)
-        return frc[l].template ld<T>(colb, (uint32_t)(c * cN + pk * (int64_t)sizeof(T)));
-      else
-        return pfrc[l][c * N + o];
-    };
-    auto sto_ = [&](int l, int c, int64_t pk, int64_t o, T v) {
-      if constexpr (BUF)
-        uold[l].st(colb, (uint32_t)(c * cN + pk * (int64_t)sizeof(T)), v);
-      else
-        pold[l][c * N + o] = v;
-    };
+    // component c of load l's fields in the z-plane at element offset pk
+    auto ldu = [&](int l, int c, int64_t pk) -> T { return PlaneBuf(pcur[l] + (c * N + pk), pbytes).template ld<T>(colb); };
+    auto ldo_ = [&](int l, int c, int64_t pk) -> T { return PlaneBuf(pold[l] + (c * N + pk), pbytes).template ld<T>(colb); };
+    auto ldf = [&](int l, int c, int64_t pk) -> T { return PlaneBuf(pfrc[l] + (c * N + pk), pbytes).template ld<T>(colb); };
+    auto sto_ = [&](int l, int c, int64_t pk, T v) { PlaneBuf(pold[l] + (c * N + pk), pbytes).st(colb, v); };
 
     T Ux[2][L], Uy[2][L], Uz[2][L], Szz[2][L], Sxz[2][L], Syz[2][L], iHh[2];
     CellCoef<T> Cc[2];
@@ -848,14 +810,14 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       for (int l = 0; l < L; ++l) {
         Ux[0][l] = Uy[0][l] = Uz[0][l] = T(0);
         if (act & (1u << l)) {
-          Ux[0][l] = ldu(l, 0, po, col + po);
-          Uy[0][l] = ldu(l, 1, po, col + po);
-          Uz[0][l] = ldu(l, 2, po, col + po);
+          Ux[0][l] = ldu(l, 0, po);
+          Uy[0][l] = ldu(l, 1, po);
+          Uz[0][l] = ldu(l, 2, po);
         }
         Szz[1][l] = Sxz[1][l] = Syz[1][l] = T(0);
         nsum[l] = 0.0;
       }
-      Cc[0] = mod.coef(mod.load(po, col + po, col32, colb));
+      Cc[0] = mod.coef(mod.load(po, col32, colb));
       iHh[1] = T(1);
       sG[0][tid] = Cc[0].iG8;
     }
@@ -868,9 +830,8 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       const int kw = k < 0 ? k + nz32 : k;
       const int kn = k + 1 >= nz32 ? k + 1 - nz32 : k + 1;
       const int64_t pc = plane * kw, pn = plane * kn;
-      const int64_t oc = col + pc, on = col + pn;
       const bool face = k >= k0 && interior;
-      const auto mr = mod.load(pn, on, col32, colb);
+      const auto mr = mod.load(pn, col32, colb);
       // u^{n-1} and the force only where a face is updated (ghost threads
       // reading them costs more memory requests than the masking costs ALU)
       T uo0[L], uo1[L], uo2[L], f0[L], f1[L], f2[L];
@@ -878,19 +839,19 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       for (int l = 0; l < L; ++l) {
         Ux[Q][l] = Uy[Q][l] = Uz[Q][l] = uo0[l] = uo1[l] = uo2[l] = f0[l] = f1[l] = f2[l] = T(0);
         if (act & (1u << l)) {
-          Ux[Q][l] = ldu(l, 0, pn, on);
-          Uy[Q][l] = ldu(l, 1, pn, on);
-          Uz[Q][l] = ldu(l, 2, pn, on);
+          Ux[Q][l] = ldu(l, 0, pn);
+          Uy[Q][l] = ldu(l, 1, pn);
+          Uz[Q][l] = ldu(l, 2, pn);
           if (face) {
             if (!first) {
-              uo0[l] = ldo_(l, 0, pc, oc);
-              uo1[l] = ldo_(l, 1, pc, oc);
-              uo2[l] = ldo_(l, 2, pc, oc);
+              uo0[l] = ldo_(l, 0, pc);
+              uo1[l] = ldo_(l, 1, pc);
+              uo2[l] = ldo_(l, 2, pc);
             }
             if (hasf[l]) {
-              f0[l] = ldf(l, 0, pc, oc);
-              f1[l] = ldf(l, 1, pc, oc);
-              f2[l] = ldf(l, 2, pc, oc);
+              f0[l] = ldf(l, 0, pc);
+              f1[l] = ldf(l, 1, pc);
+              f2[l] = ldf(l, 2, pc);
             }
           }
         }
@@ -1003,9 +964,9 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
           if (NORM && (L == 1 || partials != nullptr))
             nsum[l] += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
           const T ux = Ux[P][l], uy = Uy[P][l], uz = Uz[P][l];
-          sto_(l, 0, pc, oc, ux + mom * (ux - uo0[l]) + sfx * rx);
-          sto_(l, 1, pc, oc, uy + mom * (uy - uo1[l]) + sfy * ry);
-          sto_(l, 2, pc, oc, uz + mom * (uz - uo2[l]) + sfz * rz);
+          sto_(l, 0, pc, ux + mom * (ux - uo0[l]) + sfx * rx);
+          sto_(l, 1, pc, uy + mom * (uy - uo1[l]) + sfy * ry);
+          sto_(l, 2, pc, uz + mom * (uz - uo2[l]) + sfz * rz);
         }
         Szz[P][l] = szz[l];
         Sxz[P][l] = sxz_k[l];
@@ -2050,6 +2011,7 @@ hipError_t launch_residual_ortho(const SampleDesc<T>* d_samples, const WorkItem*
   return hipGetLastError();
 }
 
+#if CEFF_IN_PART(0)
 size_t ortho_lds_bytes(TileShape ts, size_t elem) {
   return (size_t)kOrthoArrays * (((ts.bx * ts.by + 63) / 64) * 64) * elem;
 }
@@ -2086,6 +2048,8 @@ hipError_t launch_average_stress_ortho(int64_t nx, int64_t ny, int64_t nz, const
   return hipGetLastError();
 }
 
+#endif
+
 template <typename R>
 hipError_t launch_gradient(int64_t nx, int64_t ny, int64_t nz, const double h[3], const double* K, const double* G,
                            const GradLoads& g, R* dK, R* dG, hipStream_t s) {
@@ -2107,6 +2071,7 @@ hipError_t launch_convert(const A* src, B* dst, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+#if CEFF_IN_PART(0)
 hipError_t launch_fold(double* base, float* cur, float* prev, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fold_kernel, dim3(grid_for(n)), dim3(256), 0, s, base, cur, prev, n);
   return hipGetLastError();
@@ -2116,6 +2081,8 @@ hipError_t launch_axpy1(double* dst, const double* src, int64_t n, hipStream_t s
   hipLaunchKernelGGL(axpy1_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n);
   return hipGetLastError();
 }
+
+#endif
 
 template <typename T>
 hipError_t launch_phase_to_fields(const uint8_t* phase, int64_t n, const double* Ktab, const double* Gtab, int nphase,
@@ -2132,6 +2099,7 @@ hipError_t launch_check_moduli(const T* K, const T* G, int64_t n, int* bad, int*
   return hipGetLastError();
 }
 
+#if CEFF_IN_PART(0)
 hipError_t launch_check_ortho(const double* c, int64_t n, int* bad, int* nblocks, hipStream_t s) {
   const int g = grid_for(n);
   *nblocks = g;
@@ -2139,7 +2107,27 @@ hipError_t launch_check_ortho(const double* c, int64_t n, int* bad, int* nblocks
   return hipGetLastError();
 }
 
+#endif
+
 // explicit instantiations
+#define CEFF_INST_STEP(T, L)                                                                                       \
+  template hipError_t launch_step<T, L>(const SampleDesc<T>*, const WorkItem*, int, TileShape, int, int, double*, \
+                                        hipStream_t);
+#if CEFF_IN_PART(1)
+CEFF_INST_STEP(float, 1)
+CEFF_INST_STEP(float, 2)
+#endif
+#if CEFF_IN_PART(2)
+CEFF_INST_STEP(float, 3)
+CEFF_INST_STEP(float, 6)
+#endif
+#if CEFF_IN_PART(3)
+CEFF_INST_STEP(double, 1)
+CEFF_INST_STEP(double, 2)
+CEFF_INST_STEP(double, 3)
+CEFF_INST_STEP(double, 6)
+#endif
+#if CEFF_IN_PART(0)
 template hipError_t launch_step_ortho<float>(const SampleDesc<float>*, const WorkItem*, int, TileShape, int, int,
                                              double*, hipStream_t);
 template hipError_t launch_step_ortho<double>(const SampleDesc<double>*, const WorkItem*, int, TileShape, int, int,
@@ -2150,17 +2138,6 @@ template hipError_t launch_residual_ortho<double, double>(const SampleDesc<doubl
                                                           int, double* const*, double*, hipStream_t);
 template hipError_t launch_residual_ortho<float, float>(const SampleDesc<float>*, const WorkItem*, int, TileShape,
                                                         int, float* const*, double*, hipStream_t);
-#define CEFF_INST_STEP(T, L)                                                                                       \
-  template hipError_t launch_step<T, L>(const SampleDesc<T>*, const WorkItem*, int, TileShape, int, int, double*, \
-                                        hipStream_t);
-CEFF_INST_STEP(float, 1)
-CEFF_INST_STEP(float, 2)
-CEFF_INST_STEP(float, 3)
-CEFF_INST_STEP(float, 6)
-CEFF_INST_STEP(double, 1)
-CEFF_INST_STEP(double, 2)
-CEFF_INST_STEP(double, 3)
-CEFF_INST_STEP(double, 6)
 #define CEFF_INST_RES(T, R, L)                                                                              \
   template hipError_t launch_residual<T, R, L>(const SampleDesc<T>*, const WorkItem*, int, TileShape, int, \
                                                R* const*, double*, hipStream_t);
@@ -2184,5 +2161,7 @@ template hipError_t launch_phase_to_fields<float>(const uint8_t*, int64_t, const
                                                   float*, hipStream_t);
 template hipError_t launch_check_moduli<double>(const double*, const double*, int64_t, int*, int*, hipStream_t);
 template hipError_t launch_check_moduli<float>(const float*, const float*, int64_t, int*, int*, hipStream_t);
+
+#endif
 
 }  // namespace ceff

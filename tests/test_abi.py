@@ -65,3 +65,23 @@ def test_create_without_device_fails_cleanly():
     h = ctypes.c_void_p()
     assert L.ceff_create(0, None, ctypes.byref(h)) == _lib.CEFF_EDEVICE
     assert not h.value
+
+
+def test_grid_limits_without_a_device():
+    """The host-side grid check: fields larger than 4 GiB are accepted (the
+    iteration kernels address one z-plane at a time), the limits that remain
+    are the dimension range and the 2 GiB z-plane."""
+    from paper_2410_20441_amd import _lib
+    L = _lib.load()
+    ok, bad = _lib.CEFF_OK, _lib.CEFF_EINVAL
+    # FP64 one-load fields (3N doubles) beyond 4 GiB from 564^3 on, FP32 from 711^3
+    for n in (563, 564, 566, 703, 711, 1024, 2048):
+        assert L.ceff_check_grid(n, n, n, 1.0, 1.0, 1.0) == ok, n
+    assert L.ceff_check_grid(16384, 16384, 2, 1.0, 1.0, 1.0) == ok           # plane of exactly 2 GiB FP64
+    assert L.ceff_check_grid(16384, 16385, 2, 1.0, 1.0, 1.0) == bad          # plane beyond 2 GiB
+    assert L.ceff_check_grid(1 << 20, 2, 2, 1.0, 1.0, 1.0) == ok
+    assert L.ceff_check_grid((1 << 20) + 1, 2, 2, 1.0, 1.0, 1.0) == bad
+    assert L.ceff_check_grid(1, 8, 8, 1.0, 1.0, 1.0) == bad
+    assert L.ceff_check_grid(8, 8, 8, 0.0, 1.0, 1.0) == bad
+    assert L.ceff_check_grid(8, 8, 8, 1.0, float("inf"), 1.0) == bad
+    assert L.ceff_check_grid(8, 8, 8, 1.0, 1.0, float("nan")) == bad
