@@ -245,6 +245,19 @@ ceff_status ceff_residual(ceff_ctx* ctx, int J, int precision, const double* u, 
  * unit load J, Voigt order (paper: the volume-averaged stress). */
 ceff_status ceff_average_stress(ceff_ctx* ctx, int J, const double* u, double out6[6]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): ceff_average_stress
+ * of a displacement u that is already on the device (FP64, 3N values,
+ * component-major, on the context's device, ordered on its stream), with no
+ * allocation in the call.  The kernel's partial sums go to a fixed scratch
+ * array of 196,672 bytes that each GPU holds for the life of the process
+ * (partials of at most 4096 blocks, enough for every grid, so no grid size is
+ * rejected).  All calls on one GPU share that array: calls that overlap on one
+ * GPU (several threads, contexts or streams) race and must be serialised by the
+ * caller.  Argument and state errors as ceff_average_stress; the result equals
+ * ceff_average_stress's on the same u. */
+ceff_status ceff_average_stress_noalloc(ceff_ctx* ctx, int J, const double* u, double out6[6]);
+
 /* Counters of the most recent solve (ceff_apt_steps: the launch shape only). */
 ceff_status ceff_get_stats(const ceff_ctx* ctx, ceff_stats* out);
 

@@ -30,7 +30,7 @@ _L = _lib.load()
 __all__ = ["ceff_default_opts", "ceff_check_grid", "ceff_create", "ceff_destroy", "ceff_last_error", "ceff_set_grid",
            "ceff_set_isotropic", "ceff_set_phases", "ceff_set_stiffness", "ceff_set_boundary", "ceff_solve",
            "ceff_solve_batch", "ceff_solve_batch_phases", "solve_batch_phases",
-           "ceff_gradient", "ceff_apt_steps", "ceff_residual", "ceff_average_stress", "ceff_get_stats",
+           "ceff_gradient", "ceff_apt_steps", "ceff_residual", "ceff_average_stress", "ceff_average_stress_noalloc", "ceff_get_stats",
            "ceff_contribution_tensors", "ceff_triaxial_offdiagonals", "triaxial_offdiagonals", "CeffError", "Context", "solve", "solve_batch", "contribution_tensors",
            "EffectiveStiffness", "library_path"]
 
@@ -128,6 +128,11 @@ def ceff_residual(ctx, J, precision, u, r_out, norm2):
 
 def ceff_average_stress(ctx, J, u, out6):
     return _check(ctx, _L.ceff_average_stress(ctx, J, u, out6))
+
+
+def ceff_average_stress_noalloc(ctx, J, u, out6):
+    """u: device pointer (int or c_void_p) to 3N FP64 values on the context's device."""
+    return _check(ctx, _L.ceff_average_stress_noalloc(ctx, J, u, out6))
 
 
 def ceff_get_stats(ctx, out):

@@ -66,6 +66,7 @@ SIGNATURES = {
     "ceff_apt_steps": (_st, [_vp, ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp]),
     "ceff_residual": (_st, [_vp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]),
     "ceff_average_stress": (_st, [_vp, ctypes.c_int, _dp, _dp]),
+    "ceff_average_stress_noalloc": (_st, [_vp, ctypes.c_int, _vp, _dp]),
     "ceff_get_stats": (_st, [_vp, ctypes.POINTER(ceff_stats)]),
     "ceff_contribution_tensors": (_st, [_dp, _dp, ctypes.c_double, _dp, _dp]),
     "ceff_triaxial_offdiagonals": (_st, [_dp, _dp, _dp, _dp]),

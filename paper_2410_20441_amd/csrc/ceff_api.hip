@@ -27,6 +27,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -36,6 +37,15 @@ using namespace ceff;
 // Block partials of the stress averages: the kernel strides over the cells
 // with at most this many blocks, whatever the grid.
 constexpr int kAvgBlocks = 4096;
+
+// Scratch of the allocation-free entry point (ceff_average_stress_noalloc):
+// the stress-average kernel's block partials (6 x kAvgBlocks) and the six sums
+// at the end, 196,672 bytes.  Each GPU the library runs on holds its own copy
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// not a device address: kernels get the per-device address that ceff_create
+// looks up with hipGetSymbolAddress (scratch_addr below).
+constexpr int kScratchDoubles = 6 * kAvgBlocks + 8;
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
@@ -993,6 +1003,25 @@ ceff_status stress_average_into(ceff_ctx* c, const SampleIn& s, int J, const dou
 }
 
 
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;  // device ordinal -> address of that GPU's `scratch`
+
+// Look up this GPU's copy of `scratch` once (the device must be current).
+ceff_status init_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr.count(device)) return CEFF_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return CEFF_EDEVICE;
+  g_scratch_addr[device] = static_cast<double*>(p);
+  return CEFF_OK;
+}
+
+double* scratch_addr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  return it == g_scratch_addr.end() ? nullptr : it->second;
+}
+
 ceff_status stress_average(ceff_ctx* c, const SampleIn& s, int J, const double* u, double out6[6]) {
   DevBuf part, o6;
   HIPCK(c, part.alloc(sizeof(double) * 6 * kAvgBlocks));
@@ -1180,6 +1209,7 @@ ceff_status ceff_create(int device, void* hip_stream, ceff_ctx** out) {
   c->device = device;
   c->user = static_cast<hipStream_t>(hip_stream);
   if (hipSetDevice(device) != hipSuccess) return CEFF_EDEVICE;
+  if (init_scratch(device) != CEFF_OK) return CEFF_EDEVICE;
   if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess) return CEFF_EDEVICE;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) return CEFF_EDEVICE;
   *out = c.release();
@@ -1748,6 +1778,18 @@ ceff_status ceff_average_stress(ceff_ctx* c, int J, const double* u, double out6
   HIPCK(c, d.alloc(sizeof(double) * 3 * N));
   HIPCK(c, hipMemcpyAsync(d.p, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice, c->s));
   return stress_average(c, ctx_sample(c), J, d.as<double>(), out6);
+}
+
+ceff_status ceff_average_stress_noalloc(ceff_ctx* c, int J, const double* u, double out6[6]) {
+  if (!c) return CEFF_EINVAL;
+  if (J < 0 || J > 5) return fail(c, CEFF_EINVAL, "load index must be in [0, 5]");
+  if (!u || !out6) return fail(c, CEFF_EINVAL, "null argument");
+  if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  double* sc = scratch_addr(c->device);
+  if (!sc) return fail(c, CEFF_EDEVICE, "no scratch address for device %d", c->device);
+  STCK(begin_call(c));
+  // partials of at most kAvgBlocks blocks, then the six sums: the whole scratch, for any grid
+  return stress_average_into(c, ctx_sample(c), J, u, sc, kAvgBlocks, sc + 6 * kAvgBlocks, out6);
 }
 
 ceff_status ceff_get_stats(const ceff_ctx* c, ceff_stats* out) {
