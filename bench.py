@@ -42,7 +42,7 @@ VARIANT_KERNEL = {0: "step_kernel", 1: "step_kernel", 2: "step_kernel_u2", 3: "s
 
 
 # Swept Strouhal numbers per workload family (six loads, mixed precision, rtol 1e-8):
-#   spheres191: St 3.0 / 3.25 / 3.5 / 3.75 -> 32400 / 30000 / 28200 / 28000, 32400 / 30200 / 29800 / 30800 and
+#   spheres191 (now run with the automatic St 3.48): St 3.0 / 3.25 / 3.5 / 3.75 -> 32400 / 30000 / 28200 / 28000, 32400 / 30200 / 29800 / 30800 and
 #               32400 / 30200 / 29600 / 31800 load-iterations for three seeds (checks every 200); 3.5 is the
 #               lowest on average and below 3.25 for each seed; St 4.0 gave 34600 for the third
 #   (the sweeps below ran with checks every 200 iterations)
@@ -50,7 +50,9 @@ VARIANT_KERNEL = {0: "step_kernel", 1: "step_kernel", 2: "step_kernel_u2", 3: "s
 #               counts over the six loads)
 #   batch48:    St 2.0 / 2.5 / 3.0 / 3.5 -> 15.4 / 13.1 / 12.6 / 13.7 s
 #   spheres703: St 5.0 / 6.5 / 8.0 / 11.5 -> 12000 / 9200 / 7400 / 9200 iterations of load 0
-STROUHAL_BY_WORKLOAD = {"spheres191": 3.5, "cracks479": 5.0, "batch48": 3.0, "spheres703": 8.0}
+# The 191^3 benchmark runs with the library's automatic choice (strouhal = 0: St 3.48 at 191^3, next to the
+# swept 3.5); the other workloads keep their swept values.
+STROUHAL_BY_WORKLOAD = {"cracks479": 5.0, "batch48": 3.0, "spheres703": 8.0}
 
 
 def kernel_source_hash():
@@ -85,6 +87,62 @@ def stream_ceiling(torch, dev, mib=1024):
     return out
 
 
+def calibrate_copy(torch, dev, mib):
+    """Copy a buffer of `mib` MiB three times: a plain copy kernel of known size against which
+    rocprofv3's HBM byte counters are scaled."""
+    nb = mib * (1 << 20)
+    src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize(dev)
+    print(f"# copy calibration: {nb} bytes read and {nb} bytes written per copy kernel", file=sys.stderr, flush=True)
+    del src, dst
+    torch.cuda.empty_cache()
+
+
+def hbm_roofline(a, torch, synth, ceff, dev):
+    """The iteration kernel where its working set far exceeds the 256 MiB Infinity Cache: one load of
+    an n^3 sphere pack (10% fluid pores, the benchmark's recipe; 480^3 by default, 4.1 GB of
+    displacements, body-force slot and phase image), a fixed number of iterations timed by the
+    library's HIP events on its stream.  Same kernel family as the headline roofline, at the launch
+    shape the library picks for grids beyond the cache."""
+    t0 = time.perf_counter()
+    m = synth.random_spheres(a.hbm_n, 0.10, 0xC2)
+    N = m.phase.size
+    print(f"# hbm roofline: {a.hbm_n}^3 sphere pack generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    ctx = ceff.Context(0)
+    ctx.set_phases(m.phase, m.K_tab, m.G_tab)
+    opts = dict(loads=[0], precision="mixed", rtol=1e-8, strouhal=a.strouhal, check_every=100,
+                max_iter=a.hbm_iters, allow_unconverged=True)
+    ctx.solve(**dict(opts, max_iter=20, check_every=10))  # warm-up (allocation, graph, code objects)
+    C, info = ctx.solve(**opts)
+    st = info["stats"]
+    ctx.close()
+    achieved = st["step_bytes"] / (st["step_time_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "%s<float,%s> (heavy-ball APT iteration, loads per block = %s)" % (
+                VARIANT_KERNEL[st["tile_variant"]], st["tile_group"], st["tile_group"]),
+            "workload": f"{a.hbm_n}^3 sphere pack (10% fluid pores), load 0, {st['step_launches']} iterations",
+            "launch_shape": f"{st['tile_bx']}x{st['tile_by']}x{st['tile_kc']} variant {st['tile_variant']}",
+            "avg_launch_ms": st["step_time_ms"] / max(st["step_launches"], 1),
+            "launches": st["step_launches"],
+            "bytes_per_launch": st["step_bytes"] / max(st["step_launches"], 1),
+            "working_set_bytes": float(N) * 37.0, "infinity_cache_bytes": 256 * 2 ** 20}
+
+
+def oracle_time_to_ceff(threads):
+    """Oracle time to C* on the 32^3 single sphere (six loads), in a child process with
+    `threads` OpenMP threads."""
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    r = subprocess.run([sys.executable, "-m", "oracle.timing"], cwd=here, capture_output=True, text=True,
+                       env=dict(os.environ, OMP_NUM_THREADS=str(threads)), timeout=900, check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,13 +151,18 @@ def parse():
     ap.add_argument("--n", type=int, default=191, help="grid size of the sphere pack")
     ap.add_argument("--rtol", type=float, default=1e-8)
     # St is a numerical parameter of the APT iteration; its best value depends on the microstructure
-    # and the box size (the library default is 2.0).  Each workload family below runs at the value a
-    # sweep found best (most robust among the near-optimal ones); see STROUHAL_BY_WORKLOAD.
+    # and the box size (the library picks it from the box when it is 0).  The workload families of
+    # STROUHAL_BY_WORKLOAD run at the value a sweep found best for them.
     ap.add_argument("--strouhal", type=float, default=None,
-                    help="APT Strouhal number (default: the swept value of the workload, else 2.0)")
+                    help="APT Strouhal number (default: the swept value of the workload, else the library's "
+                         "automatic choice)")
     ap.add_argument("--check-every", type=int, default=100, help="iterations between residual checks (library default)")
     ap.add_argument("--no-fp64-baseline", action="store_true", help="skip the FP64 one-load-at-a-time solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm-roofline", action="store_true",
+                    help="skip the second roofline measurement on a grid beyond the Infinity Cache")
+    ap.add_argument("--hbm-n", type=int, default=480, help="grid of the HBM-resident roofline measurement")
+    ap.add_argument("--hbm-iters", type=int, default=200, help="iterations of that measurement")
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle APT iterations timed for the CPU baseline")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--fuse", default="auto", choices=["auto", "on", "off"],
@@ -109,10 +172,11 @@ def parse():
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for counter collection: allow stopping at --max-iter")
     ap.add_argument("--workload", default="spheres191",
-                    choices=["spheres191", "batch48", "cracks479", "spheres703", "hsweep", "grad128"],
+                    choices=["spheres191", "batch48", "cracks479", "spheres703", "hsweep", "grad128", "hbm480"],
                     help="spheres191 (default bench line); batch48: 48 uneven three-phase samples in one solve; "
                          "cracks479: 479^3 cracked solid; spheres703: 703^3 sphere pack (the largest grid; --fuse off solves the loads one after another and reports each); "
-                         "hsweep: contribution tensors of single spheroids, aspect ratio x contrast, one batch")
+                         "hsweep: contribution tensors of single spheroids, aspect ratio x contrast, one batch; "
+                         "hbm480: only the HBM-resident roofline measurement (for profiling)")
     ap.add_argument("--hsweep-r", type=int, default=12, help="hsweep: largest semi-axis of the coarse spheroids")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a buffer of this many MiB three times (a plain copy kernel of known size "
@@ -135,7 +199,7 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     if a.strouhal is None:
-        a.strouhal = STROUHAL_BY_WORKLOAD.get(a.workload, 2.0)
+        a.strouhal = STROUHAL_BY_WORKLOAD.get(a.workload, 0.0)
     if a.workload != "spheres191":
         return other_workload(a, torch, synth, ceff, dev)
     m = synth.workload_spheres191(n=a.n)
@@ -143,15 +207,7 @@ def main():
     print(f"# workload {m.info}", file=sys.stderr, flush=True)
 
     if a.calibrate_copy:
-        nb = a.calibrate_copy * (1 << 20)
-        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize(dev)
-        print(f"# copy calibration: {nb} bytes read and {nb} bytes written per copy kernel", file=sys.stderr,
-              flush=True)
-        del src, dst
+        calibrate_copy(torch, dev, a.calibrate_copy)
 
     ctx = ceff.Context(0)
     ctx.set_phases(m.phase, m.K_tab, m.G_tab)
@@ -214,7 +270,9 @@ def main():
                                f"residuals, folds and averages; rtol {a.rtol:g}",
                    "n": a.n, "voxels": N, "loads": 6, "rtol": a.rtol, "precision": "mixed",
                    "fused_loads": bool(st["fused_loads"]), "moduli": "phase image" if st["phase_moduli"] else "fields",
-                   "strouhal": a.strouhal, "porosity": m.info["porosity"]},
+                   "strouhal": a.strouhal if a.strouhal > 0 else ceff.ceff_auto_strouhal(a.n, a.n, a.n),
+                   "strouhal_choice": "explicit" if a.strouhal > 0 else "automatic",
+                   "porosity": m.info["porosity"]},
         "time_to_ceff_s": wall / a.steps,
         "iterations_per_solve": tot["iters"] / a.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -233,6 +291,22 @@ def main():
     }
 
     out["stream_ceiling"] = stream_ceiling(torch, dev)
+
+    # time to C* including the upload of the material from host memory (a new context: the phase
+    # image and table go host -> device, the FP64 K and G fields are expanded on the device)
+    torch.cuda.synchronize(dev)
+    t3 = time.perf_counter()
+    ctx_u = ceff.Context(0)
+    ctx_u.set_phases(m.phase, m.K_tab, m.G_tab)
+    Cu, info_u = ctx_u.solve(**opts)
+    torch.cuda.synchronize(dev)
+    out["time_to_ceff_with_upload_s"] = time.perf_counter() - t3
+    ctx_u.close()
+    if not np.array_equal(Cu, C):
+        print("# warning: the solve after a fresh upload differs from the timed ones", file=sys.stderr, flush=True)
+
+    if not a.no_hbm_roofline:
+        out["roofline_hbm"] = hbm_roofline(a, torch, synth, ceff, dev)
 
     if not a.no_fp64_baseline:
         t1 = time.perf_counter()
@@ -263,6 +337,21 @@ def main():
                                "kind": "oracle",
                                "sample": f"{a.cpu_steps} APT iterations of one load on the same {a.n}^3 grid "
                                          f"(oracle, paper-form variables), {tc:.1f} s"}
+        # the oracle's own solve (Jacobi-PCG to rtol 1e-11) to C* on the 32^3 single sphere, all cores and
+        # one thread; the 191^3 figure is the recorded run that wrote the stored oracle columns
+        ttc = {"workload": "32^3 single sphere (r = 8, fluid), six loads, Jacobi-PCG to rtol 1e-11"}
+        for t in (threads, 1):
+            r = oracle_time_to_ceff(t)
+            ttc[f"seconds_{t}_threads"] = r["seconds"]
+            ttc["iterations"] = r["iterations"]
+        out["cpu_baseline"]["time_to_ceff_32"] = ttc
+        gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "spheres191_oracle.json")
+        if os.path.exists(gold):
+            g = json.load(open(gold))
+            out["cpu_baseline"]["time_to_ceff_191_recorded"] = {
+                "seconds": sum(c["seconds"] for c in g["columns"].values()), "threads": 6,
+                "host": "8-core build container (not this host); the run that wrote tests/golden/spheres191_oracle.json",
+                "iterations": [g["columns"][str(J)]["iterations"] for J in range(6)]}
     print(json.dumps(out), flush=True)
 
 
@@ -366,6 +455,11 @@ def other_workload(a, torch, synth, ceff, dev):
         return hsweep(a, torch, synth, ceff, dev)
     if a.workload == "grad128":
         return grad128(a, torch, synth, ceff, dev)
+    if a.workload == "hbm480":
+        if a.calibrate_copy:
+            calibrate_copy(torch, dev, a.calibrate_copy)
+        print(json.dumps(hbm_roofline(a, torch, synth, ceff, dev)), flush=True)
+        return
     opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, max_iter=a.max_iter,
                 allow_unconverged=a.profile_run, autotune=a.autotune,
                 fuse_loads={"auto": "auto", "on": True, "off": False}[a.fuse])

@@ -64,7 +64,9 @@ typedef struct {
   int64_t max_iter;     /* iteration cap per load */
   int check_every;      /* iterations between residual checks (rounded up to even) */
   double courant;       /* CFL number in (0, 1]: ell = courant / sqrt(sum 1/h^2) */
-  double strouhal;      /* St of the paper's numerical parameters, > 0 */
+  double strouhal;      /* St of the paper's numerical parameters: > 0, or 0 (the default) for
+                           the automatic choice of ceff_auto_strouhal, per sample.  St sets
+                           only the damping of the iteration, never its fixed point. */
   int fuse_loads;       /* 1: all requested loads advance in one launch per iteration;
                            0: one load after another;
                            CEFF_FUSE_AUTO: one after another when the iteration working set of
@@ -73,7 +75,13 @@ typedef struct {
                            fused otherwise.  Results do not depend on this choice. */
   int use_graph;        /* 1: replay each block of check_every iterations as a HIP graph */
   int keep_fields;      /* 1: keep the converged FP64 displacements for ceff_gradient */
-  int autotune;         /* 1: time candidate tile shapes first (cached per shape) */
+  int autotune;         /* 1: time candidate launch shapes (block extent, z-chunk, loads per
+                           block, kernel variant, occupancy) on the problem first and use the
+                           fastest; the iterates do not depend on the shape.  The choice is
+                           cached per context by precision, loads, phase-table use, sample
+                           dimensions and kernel build, and, when the environment variable
+                           CEFF_TUNE_CACHE names a file, appended to that file and read back
+                           by later processes.  0: the built-in shapes (no cache lookup). */
   double fold_ratio;    /* MIXED: fold the FP32 correction into the FP64 displacement when
                            the residual fell by this factor since the last fold */
   const double* warm_u; /* optional initial displacement fluctuation (host FP64, 6 x 3N,
@@ -109,9 +117,22 @@ typedef struct {
 } ceff_stats;
 
 /* Fill *o with the defaults: MIXED, rtol 1e-8, max_iter 2e6, check_every 100,
- * courant 0.95, strouhal 2.0, fuse_loads CEFF_FUSE_AUTO, use_graph 1, keep_fields 0,
+ * courant 0.95, strouhal 0 (automatic), fuse_loads CEFF_FUSE_AUTO, use_graph 1, keep_fields 0,
  * autotune 0, fold_ratio 1e-3, warm_u NULL. */
 void ceff_default_opts(ceff_solve_opts* o);
+
+/* The Strouhal number that strouhal = 0 selects for a box of nx x ny x nz cells
+ * of size hx x hy x hz and the given Courant number (paper, "Solution of the
+ * system of equations": St sets the damping of the iteration; the paper's
+ * optimum is derived for a homogeneous medium).  With ell = courant /
+ * sqrt(sum 1/h^2) and Lx = max n_d h_d the damping is c = ell St / Lx, and
+ *   St = min(max(0.010 Lx / ell, 2), 8.3),
+ * i.e. c = 0.010 (the best damping measured for fluid-filled pore images, which
+ * stays nearly constant from 64^3 to 256^3), St at least 2 in small boxes and at
+ * most 8.3 (a box-scale mode limits large ones: 703^3 pores converge fastest
+ * near St 8).  Host only; CEFF_EINVAL for a bad grid or courant outside (0, 1]. */
+ceff_status ceff_auto_strouhal(int64_t nx, int64_t ny, int64_t nz, double hx, double hy, double hz, double courant,
+                               double* st_out);
 
 /* Check a grid against this build's limits without a context or a device: each
  * dimension in [2, 2^20], one z-plane nx*ny of at most 2^28 cells (2 GiB of
@@ -122,9 +143,10 @@ void ceff_default_opts(ceff_solve_opts* o);
  * only; needs no device. */
 ceff_status ceff_check_grid(int64_t nx, int64_t ny, int64_t nz, double hx, double hy, double hz);
 
-/* Create a context on HIP device `device`.  hip_stream: a hipStream_t the
- * caller orders its device inputs on (NULL = the null stream).  The library
- * runs its own work on an internal stream of default priority. */
+/* Create a context on HIP device `device` (runtime plumbing with no paper
+ * counterpart).  hip_stream: a hipStream_t the caller orders its device inputs
+ * on (NULL = the null stream).  The library runs its own work on an internal
+ * stream of default priority.  CEFF_EDEVICE if the device is not usable. */
 ceff_status ceff_create(int device, void* hip_stream, ceff_ctx** out);
 void ceff_destroy(ceff_ctx* ctx);
 /* Message of the last failure (context-owned; valid until the next call). */
@@ -219,7 +241,8 @@ ceff_status ceff_solve_batch_phases(ceff_ctx* ctx, int nsamples, const int64_t* 
                                     double* C_out, int64_t* iters_out);
 
 /* Gradient of J = sum_IJ W[I*6+J] C_IJ with respect to the per-voxel K and G
- * of the current material, from the displacements kept by the last
+ * of the current material (the building block of inverse problems that the
+ * paper's "Future perspectives", item 5, names for this solver), from the displacements kept by the last
  * ceff_solve (keep_fields = 1, all loads that W touches; isotropic materials
  * only, else CEFF_EUNSUPPORTED).  The solution is
  * stationary, so only the explicit dependence of the strain energy on the
@@ -230,6 +253,7 @@ ceff_status ceff_gradient(ceff_ctx* ctx, const double W[36], void* dK, void* dG,
 /* ---- single-step entry points (for step-level checks) --------------------- */
 
 /* Run the first nsteps iterations of load J from the affine initial state
+ * (strouhal = 0: the automatic choice)
  * (FP64 or MIXED = FP32 arithmetic, no defect correction) and return the
  * displacement iterate u^nsteps and u^(nsteps-1) as host doubles (3N each,
  * component-major; u_prev_out may be NULL). */
@@ -294,6 +318,15 @@ ceff_status ceff_contribution_tensors(const double C_eff[36], const double C_hos
  * CEFF_EINVAL if an input is not finite or a strain is zero. */
 ceff_status ceff_triaxial_offdiagonals(const double sig_mean[3], const double eps_mean[3], const double C_diag[3],
                                        double out[3]);
+
+/* The same from the columns of the three normal wall tests: C_walls is a 6x6
+ * row-major matrix (as ceff_solve writes under CEFF_BC_WALLS) whose columns 0-2
+ * hold loads 0-2.  The triaxial test with unit strains is their sum (linear
+ * solve, strains imposed by the walls), so sig_mean_i = sum_J C_walls[i][J]
+ * over J = 0..2, eps_mean = (1, 1, 1) and C_diag = (C_walls[0][0],
+ * C_walls[1][1], C_walls[2][2]); out = (C12, C13, C23) as above.  Host FP64;
+ * needs no device.  CEFF_EINVAL if an input entry used is not finite. */
+ceff_status ceff_triaxial_from_walls(const double C_walls[36], double out[3]);
 
 #ifdef __cplusplus
 }

@@ -27,11 +27,11 @@ from ._lib import (CEFF_DEVICE, CEFF_F32, CEFF_F64, CEFF_FUSE_AUTO, CEFF_HOST, C
 
 _L = _lib.load()
 
-__all__ = ["ceff_default_opts", "ceff_check_grid", "ceff_create", "ceff_destroy", "ceff_last_error", "ceff_set_grid",
+__all__ = ["ceff_default_opts", "ceff_check_grid", "ceff_auto_strouhal", "ceff_create", "ceff_destroy", "ceff_last_error", "ceff_set_grid",
            "ceff_set_isotropic", "ceff_set_phases", "ceff_set_stiffness", "ceff_set_boundary", "ceff_solve",
            "ceff_solve_batch", "ceff_solve_batch_phases", "solve_batch_phases",
            "ceff_gradient", "ceff_apt_steps", "ceff_residual", "ceff_average_stress", "ceff_average_stress_noalloc", "ceff_get_stats",
-           "ceff_contribution_tensors", "ceff_triaxial_offdiagonals", "triaxial_offdiagonals", "CeffError", "Context", "solve", "solve_batch", "contribution_tensors",
+           "ceff_contribution_tensors", "ceff_triaxial_offdiagonals", "ceff_triaxial_from_walls", "triaxial_offdiagonals", "CeffError", "Context", "solve", "solve_batch", "contribution_tensors",
            "EffectiveStiffness", "library_path"]
 
 library_path = _lib.LIB_PATH
@@ -54,6 +54,15 @@ def ceff_default_opts(o=None):
 def ceff_check_grid(nx, ny, nz, hx=1.0, hy=1.0, hz=1.0):
     """Status of the grid against the library's limits (host only, no device)."""
     return _L.ceff_check_grid(nx, ny, nz, hx, hy, hz)
+
+
+def ceff_auto_strouhal(nx, ny, nz, hx=1.0, hy=1.0, hz=1.0, courant=0.95):
+    """The Strouhal number the solver picks when strouhal = 0 (host only, no device)."""
+    st = ctypes.c_double()
+    rc = _L.ceff_auto_strouhal(nx, ny, nz, hx, hy, hz, courant, ctypes.byref(st))
+    if rc != 0:
+        raise CeffError(rc, "bad grid or courant number")
+    return st.value
 
 
 def ceff_create(device=0, hip_stream=None):
@@ -146,6 +155,13 @@ def ceff_triaxial_offdiagonals(sig_mean, eps_mean, C_diag, out):
     return st
 
 
+def ceff_triaxial_from_walls(C_walls, out):
+    st = _L.ceff_triaxial_from_walls(C_walls, out)
+    if st != 0:
+        raise CeffError(st, "the wall columns must be finite")
+    return st
+
+
 def ceff_contribution_tensors(C_eff, C_host, phi, H_out, N_out):
     st = _L.ceff_contribution_tensors(C_eff, C_host, phi, H_out, N_out)
     if st != 0:
@@ -194,10 +210,11 @@ def _torch_stream():
     return None
 
 
-def make_opts(precision="mixed", rtol=1e-8, max_iter=2_000_000, check_every=100, courant=0.95, strouhal=2.0,
+def make_opts(precision="mixed", rtol=1e-8, max_iter=2_000_000, check_every=100, courant=0.95, strouhal=0.0,
               fuse_loads="auto", use_graph=True, keep_fields=False, autotune=False, fold_ratio=1e-3):
     """Solve options.  fuse_loads: True (one launch per iteration for all loads), False (one load
-    after another) or "auto" (the library decides from the working set and the cache size)."""
+    after another) or "auto" (the library decides from the working set and the cache size).
+    strouhal: 0 picks it from the box (ceff_auto_strouhal)."""
     o = ceff_default_opts()
     o.precision = CEFF_PREC_MIXED if precision == "mixed" else CEFF_PREC_FP64
     o.rtol = rtol
@@ -367,12 +384,9 @@ def triaxial_offdiagonals(C_walls):
     """(C12, C13, C23) by the paper's triaxial direct test from the normal wall-test
     columns of C_walls (loads 0-2 solved with walls): the triaxial test with unit
     strains is their sum, and C11, C22, C33 are their diagonal (see ceff.h)."""
-    C = np.asarray(C_walls, np.float64).reshape(6, 6)
-    sig = np.ascontiguousarray(C[:3, 0] + C[:3, 1] + C[:3, 2])
-    eps = np.ones(3)
-    Cd = np.ascontiguousarray(np.diag(C)[:3])
+    C = np.ascontiguousarray(np.asarray(C_walls, np.float64).reshape(36))
     out = np.empty(3)
-    ceff_triaxial_offdiagonals(_dptr(sig), _dptr(eps), _dptr(Cd), _dptr(out))
+    ceff_triaxial_from_walls(_dptr(C), _dptr(out))
     return out
 
 

@@ -49,6 +49,8 @@ _st = ctypes.c_int
 SIGNATURES = {
     "ceff_default_opts": (None, [ctypes.POINTER(ceff_solve_opts)]),
     "ceff_check_grid": (_st, [_i64, _i64, _i64, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "ceff_auto_strouhal": (_st, [_i64, _i64, _i64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, _dp]),
     "ceff_create": (_st, [ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "ceff_destroy": (None, [_vp]),
     "ceff_last_error": (ctypes.c_char_p, [_vp]),
@@ -70,6 +72,7 @@ SIGNATURES = {
     "ceff_get_stats": (_st, [_vp, ctypes.POINTER(ceff_stats)]),
     "ceff_contribution_tensors": (_st, [_dp, _dp, ctypes.c_double, _dp, _dp]),
     "ceff_triaxial_offdiagonals": (_st, [_dp, _dp, _dp, _dp]),
+    "ceff_triaxial_from_walls": (_st, [_dp, _dp]),
 }
 
 _lib = None

@@ -31,6 +31,17 @@ def hipcc():
     return "hipcc"
 
 
+def kernel_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the kernel source and its internal header: part of
+    the key of autotuned launch shapes, so a changed kernel is tuned again."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in (SRCS[0], HDRS[0]):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(force: bool = True, verbose: bool = False) -> str:
     if not force and os.path.exists(LIB):
         t = os.path.getmtime(LIB)
@@ -39,7 +50,7 @@ def build(force: bool = True, verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     quiet = ["-Wno-unused-function", "-Wno-unneeded-internal-declaration"]
     units = [(SRCS[0], ["-DCEFF_KPART=%d" % k] + quiet, "ceff_kernels_%d.o" % k) for k in range(4)]
-    units.append((SRCS[1], [], "ceff_api.o"))
+    units.append((SRCS[1], ['-DCEFF_KERNEL_HASH="%s"' % kernel_hash()], "ceff_api.o"))
     objs, procs = [], []
     for src, defs, name in units:
         obj = os.path.join(OBJDIR, name)

@@ -108,7 +108,7 @@ struct ceff_ctx {
   bool kept[6] = {false, false, false, false, false, false};
   std::string err;
   ceff_stats stats{};
-  std::map<std::tuple<int, int, int64_t, int64_t, int64_t>, TileShape> tuned;
+  std::map<std::string, TileShape> tuned;  // autotuned launch shapes of this context, by tune_key
   PinnedBuf pinned;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
@@ -146,7 +146,8 @@ ceff_status validate_opts(ceff_ctx* c, const ceff_solve_opts& o) {
   if (o.max_iter < 1) return fail(c, CEFF_EINVAL, "max_iter must be >= 1");
   if (o.check_every < 1 || o.check_every > 1000000) return fail(c, CEFF_EINVAL, "check_every out of range");
   if (!(o.courant > 0.0) || !(o.courant <= 1.0)) return fail(c, CEFF_EINVAL, "courant must be in (0, 1]");
-  if (!(o.strouhal > 0.0) || !std::isfinite(o.strouhal)) return fail(c, CEFF_EINVAL, "strouhal must be > 0");
+  if (!(o.strouhal >= 0.0) || !std::isfinite(o.strouhal))
+    return fail(c, CEFF_EINVAL, "strouhal must be > 0, or 0 for the automatic choice");
   if (!(o.fold_ratio > 0.0) || !(o.fold_ratio < 1.0)) return fail(c, CEFF_EINVAL, "fold_ratio must be in (0, 1)");
   return CEFF_OK;
 }
@@ -173,9 +174,25 @@ struct Params {
   double mom, sfac, sfac_first;
 };
 
+// Automatic Strouhal number (strouhal = 0).  St only sets the damping c =
+// ell St / Lx of the iteration (momentum 1/(1+c)), never its fixed point.  Below
+// the best damping the iteration count grows as 1/c (the heavy-ball decay rate
+// of the underdamped regime), above it faster.  Sweeps on pore, crack and
+// three-phase images from 64^3 to 256^3 put the best c near a constant of the
+// microstructure family (about 0.010 for fluid-filled pores, 0.008 for penny
+// cracks, 0.015 for the three-phase field), and a 703^3 pore image at St 8
+// (a box-scale mode then limits it).  Hence c = 0.010, with St kept within
+// [2, 8.3]: small boxes keep the previous default St 2.
+constexpr double kAutoDamping = 0.010, kAutoStMin = 2.0, kAutoStMax = 8.3;
+
+double auto_strouhal(double Lx, double ell) {
+  return std::min(std::max(kAutoDamping * Lx / ell, kAutoStMin), kAutoStMax);
+}
+
 Params make_params(int64_t nx, int64_t ny, int64_t nz, const double h[3], double courant, double strouhal) {
   const double Lx = std::max({nx * h[0], ny * h[1], nz * h[2]});
   const double ell = courant / std::sqrt(1.0 / (h[0] * h[0]) + 1.0 / (h[1] * h[1]) + 1.0 / (h[2] * h[2]));
+  if (strouhal == 0.0) strouhal = auto_strouhal(Lx, ell);
   const double c = ell * strouhal / Lx;
   const double beta = ell * Lx / strouhal;
   return Params{1.0 / (1.0 + c), c / (1.0 + c) * beta, beta};
@@ -290,6 +307,54 @@ TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single) {
   t.order = 1;
   t.occ = 0;
   return t;
+}
+
+#ifndef CEFF_KERNEL_HASH
+#define CEFF_KERNEL_HASH "unknown"
+#endif
+
+// Autotuned launch shapes: kept per context, and in the file named by the
+// environment variable CEFF_TUNE_CACHE when it is set (one line per entry:
+// key bx by kc group variant order occ), so they survive the process.
+bool lookup_tuned(ceff_ctx* c, const std::string& key, TileShape& out) {
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) {
+    out = it->second;
+    return true;
+  }
+  const char* path = std::getenv("CEFF_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512], k[400];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    TileShape t{};
+    if (std::sscanf(line, "%399s %d %d %d %d %d %d %d", k, &t.bx, &t.by, &t.kc, &t.group, &t.pf, &t.order, &t.occ) !=
+        8)
+      continue;
+    const int nt = ((t.bx * t.by + 63) / 64) * 64;
+    const bool valid = t.bx >= 3 && t.by >= 3 && nt <= 512 && t.kc >= 0 && t.pf >= 0 && t.pf <= 5 &&
+                       (t.group == 1 || t.group == 2 || t.group == 3 || t.group == 6) && (t.order == 0 || t.order == 1) &&
+                       (t.occ == 0 || t.occ == 1);
+    if (valid && key == k) {  // the last valid entry of a key wins
+      out = t;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  if (found) c->tuned[key] = out;
+  return found;
+}
+
+void remember_tuned(ceff_ctx* c, const std::string& key, const TileShape& t) {
+  c->tuned[key] = t;
+  const char* path = std::getenv("CEFF_TUNE_CACHE");
+  if (!path || !*path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%s %d %d %d %d %d %d %d\n", key.c_str(), t.bx, t.by, t.kc, t.group, t.pf, t.order, t.occ);
+    std::fclose(f);
+  }
 }
 
 template <typename T>
@@ -527,19 +592,19 @@ struct Engine {
       nxm = std::max(nxm, s.nx);
       nym = std::max(nym, s.ny);
     }
-    const auto key = std::make_tuple((int)sizeof(T), (int)Js.size(), in[0].nx, in[0].ny, in[0].nz);
     if (std::getenv("CEFF_TILE")) {
       ts = with_moduli(default_tile(nxm, nym, fp64, single()));
-      return CEFF_OK;
-    }
-    auto it = c->tuned.find(key);
-    if (it != c->tuned.end()) {
-      ts = with_moduli(it->second);
       return CEFF_OK;
     }
     ts = with_moduli(default_tile(nxm, nym, fp64, single()));
     large_grid_shape();
     if (!o.autotune || ts.ortho || ts.walls) return CEFF_OK;
+    const std::string key = tune_key();
+    TileShape cached{};
+    if (lookup_tuned(c, key, cached)) {
+      ts = with_moduli(cached);
+      return CEFF_OK;
+    }
     std::vector<TileShape> cand;
     const int bxs[] = {18, 34, 66};
     const int bys[] = {6, 7, 10, 14};
@@ -607,8 +672,31 @@ struct Engine {
     }
     for (size_t si = 0; si < in.size(); ++si) h_in[si].active = saved[si];
     ts = bt;
-    c->tuned[key] = ts;
+    remember_tuned(c, key, ts);
     return CEFF_OK;
+  }
+
+  // What the best launch shape depends on: the precision, which loads advance
+  // together, whether the moduli can come from a shared phase table, the
+  // samples' dimensions, and the kernels themselves (a hash of their source,
+  // fixed at build time).  Wall boundaries and orthotropic cells are not tuned.
+  std::string tune_key() const {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over every sample's dimensions
+    for (const SampleIn& s : in)
+      for (int64_t d : {s.nx, s.ny, s.nz})
+        for (int b = 0; b < 8; ++b) {
+          h ^= (uint64_t)((d >> (8 * b)) & 0xff);
+          h *= 1099511628211ull;
+        }
+    unsigned mask = 0;
+    for (int J : Js) mask |= 1u << J;
+    TileShape probe = default_tile(in[0].nx, in[0].ny, sizeof(T) == 8, single());
+    probe.pf = 3;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s:loads%02x:pal%d:samples%zu:%lldx%lldx%lld:dims%016llx:kernels%s",
+                  sizeof(T) == 4 ? "f32" : "f64", mask, with_moduli(probe).pal, in.size(), (long long)in[0].nx,
+                  (long long)in[0].ny, (long long)in[0].nz, (unsigned long long)h, CEFF_KERNEL_HASH);
+    return buf;
   }
 
   ceff_status setup() {
@@ -1002,7 +1090,6 @@ ceff_status stress_average_into(ceff_ctx* c, const SampleIn& s, int J, const dou
   return CEFF_OK;
 }
 
-
 std::mutex g_scratch_mu;
 std::map<int, double*> g_scratch_addr;  // device ordinal -> address of that GPU's `scratch`
 
@@ -1184,7 +1271,7 @@ void ceff_default_opts(ceff_solve_opts* o) {
   o->max_iter = 2000000;
   o->check_every = 100;
   o->courant = 0.95;
-  o->strouhal = 2.0;
+  o->strouhal = 0.0;
   o->fuse_loads = CEFF_FUSE_AUTO;
   o->use_graph = 1;
   o->keep_fields = 0;
@@ -1196,6 +1283,17 @@ void ceff_default_opts(ceff_solve_opts* o) {
 ceff_status ceff_check_grid(int64_t nx, int64_t ny, int64_t nz, double hx, double hy, double hz) {
   const double h[3] = {hx, hy, hz};
   return validate_grid(nullptr, nx, ny, nz, h);
+}
+
+ceff_status ceff_auto_strouhal(int64_t nx, int64_t ny, int64_t nz, double hx, double hy, double hz, double courant,
+                               double* st_out) {
+  const double h[3] = {hx, hy, hz};
+  if (!st_out) return CEFF_EINVAL;
+  STCK(validate_grid(nullptr, nx, ny, nz, h));
+  if (!(courant > 0.0) || !(courant <= 1.0)) return CEFF_EINVAL;
+  const double Lx = std::max({nx * hx, ny * hy, nz * hz});
+  *st_out = auto_strouhal(Lx, courant / std::sqrt(1.0 / (hx * hx) + 1.0 / (hy * hy) + 1.0 / (hz * hz)));
+  return CEFF_OK;
 }
 
 ceff_status ceff_create(int device, void* hip_stream, ceff_ctx** out) {
@@ -1651,7 +1749,8 @@ ceff_status ceff_apt_steps(ceff_ctx* c, int J, int64_t nsteps, int precision, do
   if (J < 0 || J > 5) return fail(c, CEFF_EINVAL, "load index must be in [0, 5]");
   if (nsteps < 1 || nsteps > 100000000) return fail(c, CEFF_EINVAL, "nsteps out of range");
   if (precision != CEFF_PREC_FP64 && precision != CEFF_PREC_MIXED) return fail(c, CEFF_EINVAL, "bad precision");
-  if (!(courant > 0.0) || !(courant <= 1.0) || !(strouhal > 0.0)) return fail(c, CEFF_EINVAL, "bad parameters");
+  if (!(courant > 0.0) || !(courant <= 1.0) || !(strouhal >= 0.0) || !std::isfinite(strouhal))
+    return fail(c, CEFF_EINVAL, "bad parameters");
   if (!u_out) return fail(c, CEFF_EINVAL, "u_out is null");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
   STCK(begin_call(c));
@@ -1830,6 +1929,17 @@ ceff_status ceff_triaxial_offdiagonals(const double sig_mean[3], const double ep
   out[1] = (eb[0] * sb[0] - eb[1] * sb[1] + eb[2] * sb[2]) / (2.0 * eb[0] * eb[2]);
   out[2] = (-eb[0] * sb[0] + eb[1] * sb[1] + eb[2] * sb[2]) / (2.0 * eb[1] * eb[2]);
   return CEFF_OK;
+}
+
+ceff_status ceff_triaxial_from_walls(const double C_walls[36], double out[3]) {
+  if (!C_walls || !out) return CEFF_EINVAL;
+  double sig[3], eps[3] = {1.0, 1.0, 1.0}, diag[3];
+  for (int i = 0; i < 3; ++i) {
+    // row i of the triaxial test: the sum of the three normal wall columns
+    sig[i] = C_walls[i * 6 + 0] + C_walls[i * 6 + 1] + C_walls[i * 6 + 2];
+    diag[i] = C_walls[i * 6 + i];
+  }
+  return ceff_triaxial_offdiagonals(sig, eps, diag, out);
 }
 
 }  // extern "C"

@@ -6,8 +6,8 @@ tests/golden/make_spheres191_golden.py, which calls only the oracle.  The GPU
 solves the same image in the benchmark's configuration (mixed precision, the library's own choice of
 load fusion -- one load after another at this size -- with the moduli read
 from the phase image, rtol 1e-8, Strouhal number 3.5, residual checks every
-100 iterations), at St 3.0, with the library's default Strouhal number, with
-the six loads forced into one launch, and in the plain FP64
+100 iterations), at St 3.0 and 2.0, with the library's automatic Strouhal
+number, with the six loads forced into one launch, and in the plain FP64
 one-load-at-a-time configuration."""
 import hashlib
 import json
@@ -34,8 +34,8 @@ def golden():
 
 
 @pytest.mark.parametrize("precision,fuse,strouhal", [("mixed", "auto", 3.5), ("mixed", "auto", 3.0),
-                                                     ("mixed", "auto", 2.0), ("mixed", True, 2.0),
-                                                     ("fp64", False, 2.0)])
+                                                     ("mixed", "auto", 2.0), ("mixed", "auto", 0.0),
+                                                     ("mixed", True, 2.0), ("fp64", False, 2.0)])
 def test_spheres191_matches_oracle_columns(golden, precision, fuse, strouhal):
     p = need_gpu()
     m, g = golden

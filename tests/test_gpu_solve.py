@@ -222,7 +222,8 @@ def test_error_paths():
     assert L.ceff_set_stiffness(h, None, 21, 1, 0) == _lib.CEFF_EUNSUPPORTED
     K, G = synth.random_fields((4, 4, 4), 1)
     assert L.ceff_set_isotropic(h, K.ctypes.data, G.ctypes.data, 1, 0) == 0
-    for field, val in (("courant", 1.5), ("rtol", -1.0), ("check_every", 0), ("strouhal", 0.0),
+    for field, val in (("courant", 1.5), ("rtol", -1.0), ("check_every", 0), ("strouhal", -1.0),
+                       ("strouhal", float("nan")),
                        ("precision", 7), ("max_iter", 0)):
         o2 = p.make_opts()
         setattr(o2, field, val)
