@@ -54,6 +54,13 @@ def lib():
         L.or_pcg_ortho.restype = ctypes.c_int64
         L.or_apt_disp.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int64, _dp, _dp]
+        L.or_stress_tri.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
+        L.or_residual_tri.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
+        L.or_average_stress_tri.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
+        L.or_pcg_tri.argtypes = [_ip, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp]
+        L.or_pcg_tri.restype = ctypes.c_int64
+        L.or_apt_disp_tri.argtypes = [_ip, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int64, _dp,
+                                      _dp]
         L.or_residual_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
         L.or_average_stress_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
         L.or_pcg_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int64, _dp, _dp, ctypes.c_int]
@@ -258,6 +265,115 @@ def apt_disp(J, nsteps, courant, strouhal, K=None, G=None, C9=None, h=(1.0, 1.0,
     up = np.empty((3,) + sh)
     lib().or_apt_disp(dims.ctypes.data_as(_ip), _d(hh), Kp, Gp, cp, wall_mode(J) if walls else 0, _d(unit_strain(J)), courant,
                       strouhal, nsteps, _d(u), _d(up))
+    return u, up
+
+
+# ---- general anisotropic cells (21 constants per cell) ------------------------------
+#
+# C21 is shaped (21, nz, ny, nx): the upper triangle of each cell's symmetric 6x6
+# Voigt stiffness (engineering shear), row by row: C11 C12 C13 C14 C15 C16 C22 C23
+# C24 C25 C26 C33 C34 C35 C36 C44 C45 C46 C55 C56 C66.  The coupled law's reading
+# on the staggered grid (eight corner octants per cell, series-weighted edge
+# strains) is described in ceff_oracle.c.
+
+TRI_PAIRS = [(r, q) for r in range(6) for q in range(r, 6)]
+
+
+def c21_of_voigt(M):
+    """21 constants (upper triangle row by row) of Voigt matrices M shaped (6, 6, ...)."""
+    M = np.asarray(M, np.float64)
+    return np.stack([M[r, q] for r, q in TRI_PAIRS])
+
+
+def voigt_of_c21(c):
+    """Symmetric 6x6 Voigt matrix (6, 6, ...) of 21 constants shaped (21, ...)."""
+    c = np.asarray(c, np.float64)
+    M = np.empty((6, 6) + c.shape[1:])
+    for n, (r, q) in enumerate(TRI_PAIRS):
+        M[r, q] = c[n]
+        M[q, r] = c[n]
+    return M
+
+
+def c21_of_c9(C9):
+    """21 constants of orthotropic cells given by their nine constants."""
+    C9 = np.asarray(C9, np.float64)
+    M = np.zeros((6, 6) + C9.shape[1:])
+    C11, C22, C33, C23, C13, C12, C44, C55, C66 = C9
+    M[0, 0], M[1, 1], M[2, 2] = C11, C22, C33
+    M[1, 2] = M[2, 1] = C23
+    M[0, 2] = M[2, 0] = C13
+    M[0, 1] = M[1, 0] = C12
+    M[3, 3], M[4, 4], M[5, 5] = C44, C55, C66
+    return c21_of_voigt(M)
+
+
+def _prep21(C21, h):
+    C21 = np.ascontiguousarray(C21, np.float64)
+    if C21.ndim != 4 or C21.shape[0] != 21:
+        raise ValueError("C21 must be shaped (21, nz, ny, nx)")
+    if not np.all(C21[[0, 6, 11, 15, 18, 20]] > 0):
+        raise ValueError("diagonal constants must be positive")
+    nz, ny, nx = C21.shape[1:]
+    return C21, np.array([nx, ny, nz], np.int64), np.array(h, np.float64)
+
+
+def stress_tri(C21, E, u, h=(1.0, 1.0, 1.0)):
+    """Stresses (6, nz, ny, nx): normal at cells, shear at edges."""
+    C21, dims, hh = _prep21(C21, h)
+    sh = C21.shape[1:]
+    u = np.ascontiguousarray(u, np.float64).reshape((3,) + sh)
+    out = np.empty((6,) + sh)
+    lib().or_stress_tri(dims.ctypes.data_as(_ip), _d(hh), _d(C21), _d(np.asarray(E, np.float64)), _d(u), _d(out))
+    return out
+
+
+def residual_tri(C21, E, u, h=(1.0, 1.0, 1.0)):
+    C21, dims, hh = _prep21(C21, h)
+    sh = C21.shape[1:]
+    u = np.ascontiguousarray(u, np.float64).reshape((3,) + sh)
+    out = np.empty((3,) + sh)
+    lib().or_residual_tri(dims.ctypes.data_as(_ip), _d(hh), _d(C21), _d(np.asarray(E, np.float64)), _d(u), _d(out))
+    return out
+
+
+def average_stress_tri(C21, E, u, h=(1.0, 1.0, 1.0)):
+    C21, dims, hh = _prep21(C21, h)
+    u = np.ascontiguousarray(u, np.float64).reshape((3,) + C21.shape[1:])
+    out = np.empty(6)
+    lib().or_average_stress_tri(dims.ctypes.data_as(_ip), _d(hh), _d(C21), _d(np.asarray(E, np.float64)), _d(u),
+                                _d(out))
+    return out
+
+
+def solve_load_tri(C21, J, h=(1.0, 1.0, 1.0), rtol=1e-11, max_iter=1_000_000):
+    C21, dims, hh = _prep21(C21, h)
+    u = np.zeros((3,) + C21.shape[1:])
+    rel = np.zeros(1)
+    it = lib().or_pcg_tri(dims.ctypes.data_as(_ip), _d(hh), _d(C21), _d(unit_strain(J)), rtol, max_iter, _d(u),
+                          _d(rel))
+    return u, int(it), float(rel[0])
+
+
+def ceff_tri(C21, h=(1.0, 1.0, 1.0), rtol=1e-11, loads=range(6), max_iter=1_000_000):
+    """Effective stiffness (6x6) of an image of general anisotropic cells."""
+    C = np.full((6, 6), np.nan)
+    info = {}
+    for J in loads:
+        u, it, rel = solve_load_tri(C21, J, h, rtol, max_iter)
+        C[:, J] = average_stress_tri(C21, unit_strain(J), u, h)
+        info[J] = (it, rel)
+    return C, info
+
+
+def apt_disp_tri(C21, J, nsteps, courant, strouhal, h=(1.0, 1.0, 1.0)):
+    """Displacement-form APT iterate u^nsteps and u^(nsteps-1) for general cells, from u^0 = 0."""
+    C21, dims, hh = _prep21(C21, h)
+    sh = C21.shape[1:]
+    u = np.empty((3,) + sh)
+    up = np.empty((3,) + sh)
+    lib().or_apt_disp_tri(dims.ctypes.data_as(_ip), _d(hh), _d(C21), _d(unit_strain(J)), courant, strouhal,
+                          nsteps, _d(u), _d(up))
     return u, up
 
 

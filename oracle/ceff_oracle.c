@@ -33,6 +33,25 @@
  *   with the edge constant the harmonic mean over the four cells, as for G.
  *   With C11 = K + 4G/3, C12 = K - 2G/3 and C44 = G this is the isotropic law.
  *
+ * General anisotropic cells (the same perspectives list: triclinic local
+ * stiffness, which needs strains shared between cells and edges) carry the full
+ * symmetric 6x6 Voigt matrix, 21 constants c21[q*N + cell], the upper triangle
+ * row by row: C11 C12 C13 C14 C15 C16 C22 C23 C24 C25 C26 C33 C34 C35 C36 C44
+ * C45 C46 C55 C56 C66.  Reading of the coupled law on the staggered grid: each
+ * cell is split into eight corner octants.  Octant (a, b, c) of cell (i, j, k),
+ * at the corner (i+a, j+b, k+c) of the cell's node box, takes the cell's normal
+ * strains and, for each shear component, the strain the cell carries of the
+ * edge of that component meeting the corner, when the edge's strain is shared by
+ * its four cells in series: w gamma_e with w = S_e / S_cell, S the diagonal
+ * shear constant of the component (C44 yz, C55 xz, C66 xy) and S_e its harmonic
+ * mean over the edge's four cells.  The energy is sum over cells of
+ * 1/8 sum over octants of 1/2 eps_o . C_cell eps_o (Voigt, engineering shear),
+ * and the stresses are its derivatives: at a cell the octant mean of the normal
+ * rows of C eps_o, at an edge the sum over its four cells and the two octants
+ * each has there of w/8 times the shear row.  Without couplings this is exactly
+ * the orthotropic law above; for positive definite cells the energy is a sum of
+ * positive definite octant terms.
+ *
  * Wall boundaries (the paper's direct tests, appendix on boundary conditions:
  * faces of the box are rigid in the normal direction and traction-free in the
  * tangential ones) on the same periodic layout: the box boundary in direction
@@ -75,6 +94,7 @@ typedef struct {
 typedef struct {
     const double *K, *G, *c9;
     int walls;
+    const double *c21;  /* general anisotropic cells (21 constants) or NULL */
 } mat_t;
 
 static inline int64_t wrap(int64_t a, int64_t n) { a %= n; return a < 0 ? a + n : a; }
@@ -99,13 +119,27 @@ static double edge_modulus(const grid_t *g, const double *G, int plane, int64_t 
     return 4.0 / s;
 }
 
-/* Shear constant of an edge for material m: the harmonic mean over the four
- * cells of G (isotropic) or of C66 (xy), C55 (xz), C44 (yz) (orthotropic). */
-static double edge_shear(const grid_t *g, const mat_t *m, int plane, int64_t i, int64_t j, int64_t k) {
-    if (!m->c9) return edge_modulus(g, m->G, plane, i, j, k);
+/* Index q of the Voigt constant C_rs (r, s = 0..5) in a cell's 21 constants
+ * (upper triangle row by row). */
+static int tri_q(int r, int s) {
+    const int a = r < s ? r : s, b = r < s ? s : r;
+    return 6 * a - a * (a - 1) / 2 + (b - a);
+}
+
+/* Diagonal shear constant of edge plane p (0 xy, 1 xz, 2 yz) of every cell:
+ * G, or C66 / C55 / C44 of orthotropic or general cells. */
+static const double *shear_field(const grid_t *g, const mat_t *m, int plane) {
     const int64_t N = g->nx * g->ny * g->nz;
-    const double *C = m->c9 + (plane == 0 ? 8 : (plane == 1 ? 7 : 6)) * N;
-    return edge_modulus(g, C, plane, i, j, k);
+    if (m->c21) return m->c21 + (int64_t)tri_q(5 - plane, 5 - plane) * N;
+    if (m->c9) return m->c9 + (plane == 0 ? 8 : (plane == 1 ? 7 : 6)) * N;
+    return m->G;
+}
+
+/* Shear constant of an edge for material m: the harmonic mean over the four
+ * cells of G (isotropic) or of C66 (xy), C55 (xz), C44 (yz) (orthotropic and
+ * general cells). */
+static double edge_shear(const grid_t *g, const mat_t *m, int plane, int64_t i, int64_t j, int64_t k) {
+    return edge_modulus(g, shear_field(g, m, plane), plane, i, j, k);
 }
 
 /* Voigt shear component s = 3, 4, 5 (yz, xz, xy): the direction it shears in the
@@ -205,6 +239,75 @@ static void hooke(const grid_t *g, const mat_t *m, const double *eps, double *si
             }
 }
 
+/* ---- general anisotropic cells (see the header) ---- */
+
+/* Voigt strain (engineering shear) of octant (a, b, c) of cell (i, j, k) from
+ * the tensor strains eps (cells: xx yy zz; edges: yz xz xy). */
+static void octant_strain(const grid_t *g, const mat_t *m, const double *eps, int64_t i, int64_t j, int64_t k,
+                          int a, int b, int c, double out[6]) {
+    const int64_t N = g->nx * g->ny * g->nz, cell = at(g, i, j, k);
+    for (int d = 0; d < 3; d++) out[d] = eps[d * N + cell];
+    /* the corner's edges: yz [i, j+b, k+c], xz [i+a, j, k+c], xy [i+a, j+b, k] (planes 2, 1, 0) */
+    const int64_t e[3][3] = {{i, j + b, k + c}, {i + a, j, k + c}, {i + a, j + b, k}};
+    for (int s = 0; s < 3; s++) {
+        const int plane = 2 - s;
+        const double *S = shear_field(g, m, plane);
+        const double Se = edge_modulus(g, S, plane, e[s][0], e[s][1], e[s][2]);
+        out[3 + s] = 2.0 * eps[(3 + s) * N + at(g, e[s][0], e[s][1], e[s][2])] * Se / S[cell];
+    }
+}
+
+/* Row r of cell's C times the Voigt vector v. */
+static double tri_row(const grid_t *g, const mat_t *m, int64_t cell, int r, const double v[6]) {
+    const int64_t N = g->nx * g->ny * g->nz;
+    double s = 0.0;
+    for (int q = 0; q < 6; q++) s += m->c21[(int64_t)tri_q(r, q) * N + cell] * v[q];
+    return s;
+}
+
+/* Stresses of general cells: cells get the octant mean of the normal rows, each
+ * edge the w/8-weighted shear rows of the two octants of each of its four
+ * cells that meet it. */
+static void hooke_tri(const grid_t *g, const mat_t *m, const double *eps, double *sig) {
+    const int64_t N = g->nx * g->ny * g->nz;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t k = 0; k < g->nz; k++)
+        for (int64_t j = 0; j < g->ny; j++)
+            for (int64_t i = 0; i < g->nx; i++) {
+                const int64_t c = at(g, i, j, k);
+                double v[6], acc[3] = {0.0, 0.0, 0.0};
+                for (int o = 0; o < 8; o++) {
+                    octant_strain(g, m, eps, i, j, k, o & 1, (o >> 1) & 1, o >> 2, v);
+                    for (int r = 0; r < 3; r++) acc[r] += tri_row(g, m, c, r, v);
+                }
+                for (int r = 0; r < 3; r++) sig[r * N + c] = acc[r] / 8.0;
+                /* edge (i, j, k) of each plane; its cells are (cell offset, corner) pairs */
+                for (int s = 0; s < 3; s++) {
+                    const int plane = 2 - s;
+                    const double *S = shear_field(g, m, plane);
+                    const double Se = edge_modulus(g, S, plane, i, j, k);
+                    double t = 0.0;
+                    for (int p = 0; p < 4; p++) {
+                        const int q0 = p & 1, q1 = p >> 1;  /* the two cell offsets across the edge */
+                        int64_t ci = i, cj = j, ck = k;
+                        int a = 0, b = 0, cc = 0;
+                        if (s == 0) { cj = j - 1 + q0; ck = k - 1 + q1; b = 1 - q0; cc = 1 - q1; }
+                        if (s == 1) { ci = i - 1 + q0; ck = k - 1 + q1; a = 1 - q0; cc = 1 - q1; }
+                        if (s == 2) { ci = i - 1 + q0; cj = j - 1 + q1; a = 1 - q0; b = 1 - q1; }
+                        const int64_t cell = at(g, ci, cj, ck);
+                        const double w = Se / S[cell];
+                        for (int h2 = 0; h2 < 2; h2++) {  /* the cell's two octants at the edge */
+                            int aa = a, bb = b, c2 = cc;
+                            if (s == 0) aa = h2; else if (s == 1) bb = h2; else c2 = h2;
+                            octant_strain(g, m, eps, ci, cj, ck, aa, bb, c2, v);
+                            t += w / 8.0 * tri_row(g, m, cell, 3 + s, v);
+                        }
+                    }
+                    sig[(3 + s) * N + c] = t;
+                }
+            }
+}
+
 /* r = div sigma at the faces (the out-of-balance force of eq. 1). */
 static void divergence(const grid_t *g, const double *sig, double *r) {
     const int64_t N = g->nx * g->ny * g->nz;
@@ -248,7 +351,10 @@ static void m_stress(const grid_t *g, const mat_t *m, const double E[6], const d
     const int64_t N = g->nx * g->ny * g->nz;
     double *eps = malloc(sizeof(double) * 6 * N);
     strains(g, E, u, eps);
-    hooke(g, m, eps, sig);
+    if (m->c21)
+        hooke_tri(g, m, eps, sig);
+    else
+        hooke(g, m, eps, sig);
     free(eps);
     const int s = m->walls;
     if (s >= 3) FOR_SPLIT_EDGES(g, s, i, j, k) sig[s * N + at(g, i, j, k)] = half_edge(g, m, s, E, u, i, j, k, 0);
@@ -310,7 +416,7 @@ static void m_average_stress(const grid_t *g, const mat_t *m, const double E[6],
 void or_stress(const int64_t dims[3], const double h[3], const double *K, const double *G,
                const double E[6], const double *u, double *sig) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL, 0};
+    mat_t m = {K, G, NULL, 0, NULL};
     m_stress(&g, &m, E, u, sig);
 }
 
@@ -318,7 +424,7 @@ void or_stress(const int64_t dims[3], const double h[3], const double *K, const 
 void or_residual(const int64_t dims[3], const double h[3], const double *K, const double *G,
                  const double E[6], const double *u, double *r) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL, 0};
+    mat_t m = {K, G, NULL, 0, NULL};
     m_residual(&g, &m, E, u, r);
 }
 
@@ -327,7 +433,7 @@ void or_residual(const int64_t dims[3], const double h[3], const double *K, cons
 void or_average_stress(const int64_t dims[3], const double h[3], const double *K, const double *G,
                        const double E[6], const double *u, double out[6]) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL, 0};
+    mat_t m = {K, G, NULL, 0, NULL};
     m_average_stress(&g, &m, E, u, out);
 }
 
@@ -335,21 +441,21 @@ void or_average_stress(const int64_t dims[3], const double h[3], const double *K
 void or_stress_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6],
                      const double *u, double *sig) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {NULL, NULL, c9, 0};
+    mat_t m = {NULL, NULL, c9, 0, NULL};
     m_stress(&g, &m, E, u, sig);
 }
 
 void or_residual_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6],
                        const double *u, double *r) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {NULL, NULL, c9, 0};
+    mat_t m = {NULL, NULL, c9, 0, NULL};
     m_residual(&g, &m, E, u, r);
 }
 
 void or_average_stress_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6],
                              const double *u, double out[6]) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {NULL, NULL, c9, 0};
+    mat_t m = {NULL, NULL, c9, 0, NULL};
     m_average_stress(&g, &m, E, u, out);
 }
 
@@ -357,6 +463,7 @@ void or_average_stress_ortho(const int64_t dims[3], const double h[3], const dou
 /* Normal stiffness acting on face displacements of direction d in cell c:
  * K + 4G/3 (isotropic) or C11/C22/C33 (orthotropic). */
 static double normal_stiffness(const mat_t *m, int64_t N, int d, int64_t c) {
+    if (m->c21) return m->c21[(int64_t)tri_q(d, d) * N + c];
     if (m->c9) return m->c9[d * N + c];
     return m->K[c] + 4.0 * m->G[c] / 3.0;
 }
@@ -455,14 +562,14 @@ int64_t or_pcg(const int64_t dims[3], const double h[3], const double *K, const 
                const double E[6], double rtol, int64_t max_iter, double *u, double *relres,
                double *hist, int64_t hist_cap) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL, 0};
+    mat_t m = {K, G, NULL, 0, NULL};
     return m_pcg(&g, &m, E, rtol, max_iter, u, relres, hist, hist_cap);
 }
 
 int64_t or_pcg_ortho(const int64_t dims[3], const double h[3], const double *c9, const double E[6], double rtol,
                      int64_t max_iter, double *u, double *relres, double *hist, int64_t hist_cap) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {NULL, NULL, c9, 0};
+    mat_t m = {NULL, NULL, c9, 0, NULL};
     return m_pcg(&g, &m, E, rtol, max_iter, u, relres, hist, hist_cap);
 }
 
@@ -472,6 +579,23 @@ int64_t or_pcg_ortho(const int64_t dims[3], const double h[3], const double *c9,
  * (x: C11, C66, C55; y: C22, C66, C44; z: C33, C55, C44), which bounds the
  * diagonal of the operator the same way K + 4G/3 does in the isotropic case. */
 static double step_stiffness(const mat_t *m, int64_t N, int d, int64_t c) {
+    if (m->c21) {
+        /* general cells: the same three rows (x: 11, 66, 55; y: 22, 66, 44; z: 33, 55, 44),
+         * each diagonal constant raised by the absolute values of the constants of its row
+         * that an orthotropic cell does not have (a Gershgorin bound of the coupled row) */
+        static const int rows[3][3] = {{0, 5, 4}, {1, 5, 3}, {2, 4, 3}};
+        double best = 0.0;
+        for (int t = 0; t < 3; t++) {
+            const int r = rows[d][t];
+            double v = m->c21[(int64_t)tri_q(r, r) * N + c];
+            for (int q = 0; q < 6; q++) {
+                const int ortho = (r < 3 && q < 3) || q == r;
+                if (!ortho) v += fabs(m->c21[(int64_t)tri_q(r, q) * N + c]);
+            }
+            best = fmax(best, v);
+        }
+        return best;
+    }
     if (!m->c9) return m->K[c] + 4.0 * m->G[c] / 3.0;
     static const int sh[3][2] = {{8, 7}, {8, 6}, {7, 6}};
     double a = m->c9[d * N + c], b = m->c9[sh[d][0] * N + c], e = m->c9[sh[d][1] * N + c];
@@ -521,7 +645,44 @@ void or_apt_disp(const int64_t dims[3], const double h[3], const double *K, cons
                  int walls, const double E[6], double courant, double strouhal, int64_t nsteps, double *u,
                  double *u_prev) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, c9, walls};
+    mat_t m = {K, G, c9, walls, NULL};
+    m_apt_disp(&g, &m, E, courant, strouhal, nsteps, u, u_prev);
+}
+
+/* General anisotropic cells (c21: 21N constants, see the header): stresses,
+ * residual, stress averages, Jacobi-PCG solve and displacement-form APT. */
+void or_stress_tri(const int64_t dims[3], const double h[3], const double *c21, const double E[6],
+                   const double *u, double *sig) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {NULL, NULL, NULL, 0, c21};
+    m_stress(&g, &m, E, u, sig);
+}
+
+void or_residual_tri(const int64_t dims[3], const double h[3], const double *c21, const double E[6],
+                     const double *u, double *r) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {NULL, NULL, NULL, 0, c21};
+    m_residual(&g, &m, E, u, r);
+}
+
+void or_average_stress_tri(const int64_t dims[3], const double h[3], const double *c21, const double E[6],
+                           const double *u, double out[6]) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {NULL, NULL, NULL, 0, c21};
+    m_average_stress(&g, &m, E, u, out);
+}
+
+int64_t or_pcg_tri(const int64_t dims[3], const double h[3], const double *c21, const double E[6], double rtol,
+                   int64_t max_iter, double *u, double *relres) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {NULL, NULL, NULL, 0, c21};
+    return m_pcg(&g, &m, E, rtol, max_iter, u, relres, NULL, 0);
+}
+
+void or_apt_disp_tri(const int64_t dims[3], const double h[3], const double *c21, const double E[6], double courant,
+                     double strouhal, int64_t nsteps, double *u, double *u_prev) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {NULL, NULL, NULL, 0, c21};
     m_apt_disp(&g, &m, E, courant, strouhal, nsteps, u, u_prev);
 }
 
@@ -530,21 +691,21 @@ void or_apt_disp(const int64_t dims[3], const double h[3], const double *K, cons
 void or_residual_walls(const int64_t dims[3], const double h[3], const double *K, const double *G,
                        const double E[6], const double *u, double *r, int mode) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL, mode};
+    mat_t m = {K, G, NULL, mode, NULL};
     m_residual(&g, &m, E, u, r);
 }
 
 void or_average_stress_walls(const int64_t dims[3], const double h[3], const double *K, const double *G,
                              const double E[6], const double *u, double out[6], int mode) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL, mode};
+    mat_t m = {K, G, NULL, mode, NULL};
     m_average_stress(&g, &m, E, u, out);
 }
 
 int64_t or_pcg_walls(const int64_t dims[3], const double h[3], const double *K, const double *G, const double E[6],
                      double rtol, int64_t max_iter, double *u, double *relres, int mode) {
     grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
-    mat_t m = {K, G, NULL, mode};
+    mat_t m = {K, G, NULL, mode, NULL};
     return m_pcg(&g, &m, E, rtol, max_iter, u, relres, NULL, 0);
 }
 

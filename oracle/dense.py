@@ -97,6 +97,80 @@ def _energy_weights_c9(C9):
     return apply
 
 
+def octant_strains(eps, C21):
+    """Voigt strains (engineering shear) of the eight corner octants of every cell of
+    general anisotropic cells, (8, 6, nz, ny, nx), octant o = a + 2b + 4c at the cell's
+    corner (+a, +b, +c): the cell's normal strains, and for each shear component the
+    edge strain meeting that corner weighted by (harmonic mean over the edge's four
+    cells of the component's diagonal constant) / (the cell's own)."""
+    S = (C21[15], C21[18], C21[20])  # C44, C55, C66
+    Se = (edge_moduli(S[0])[0], edge_moduli(S[1])[1], edge_moduli(S[2])[2])
+    x, y, z = _AX["x"], _AX["y"], _AX["z"]
+
+    def at_corner(f, da, db, dc):  # f at index (i + da, j + db, k + dc)
+        return np.roll(np.roll(np.roll(f, -da, axis=x), -db, axis=y), -dc, axis=z)
+    out = np.empty((8, 6) + eps.shape[1:])
+    for o in range(8):
+        a, b, c = o & 1, (o >> 1) & 1, o >> 2
+        out[o, :3] = eps[:3]
+        # yz edge [i, j+b, k+c], xz edge [i+a, j, k+c], xy edge [i+a, j+b, k]
+        for s_, (da, db, dc) in enumerate(((0, b, c), (a, 0, c), (a, b, 0))):
+            out[o, 3 + s_] = 2.0 * at_corner(eps[3 + s_] * Se[s_], da, db, dc) / S[s_]
+    return out
+
+
+def _octant_apply(C21):
+    """(C_cell / 8) times every octant's strain: the weights of W = sum 1/2 v . (C/8) v."""
+    M = np.stack([np.stack([C21[_tri_n(r, q)] for q in range(6)]) for r in range(6)])  # (6, 6, ...)
+
+    def apply(v):
+        return np.einsum("rq...,oq...->or...", M, v) / 8.0
+    return apply
+
+
+def _tri_n(r, q):
+    a, b = min(r, q), max(r, q)
+    return 6 * a - a * (a - 1) // 2 + (b - a)
+
+
+def solve_dense_tri(C21, E, h=(1.0, 1.0, 1.0)):
+    """Displacement fluctuation minimising the octant energy of general cells (3, nz, ny, nx)."""
+    shape = C21.shape[1:]
+    N = int(np.prod(shape))
+    zero = np.zeros(6)
+    B = np.empty((48 * N, 3 * N))
+    for col in range(3 * N):
+        u = np.zeros(3 * N); u[col] = 1.0
+        B[:, col] = octant_strains(strain_field(u.reshape((3,) + shape), zero, h), C21).reshape(48 * N)
+    D = _octant_apply(C21)
+    DB = np.empty_like(B)
+    for col in range(3 * N):
+        DB[:, col] = D(B[:, col].reshape((8, 6) + shape)).reshape(48 * N)
+    A = B.T @ DB
+    v0 = octant_strains(strain_field(np.zeros((3,) + shape), E, h), C21)
+    rhs = -B.T @ D(v0).reshape(48 * N)
+    u, *_ = np.linalg.lstsq(A, rhs, rcond=1e-13)
+    return u.reshape((3,) + shape), A
+
+
+def ceff_dense_tri(C21, h=(1.0, 1.0, 1.0)):
+    """6x6 effective stiffness of general cells by dense minimisation of the octant
+    energy; <sigma_I> = (1/N) dW/dE_I (E_I engineering for shear)."""
+    shape = C21.shape[1:]
+    N = int(np.prod(shape))
+    D = _octant_apply(C21)
+    C = np.empty((6, 6))
+    for J in range(6):
+        E = np.zeros(6); E[J] = 1.0 if J < 3 else 0.5
+        u, _ = solve_dense_tri(C21, E, h)
+        Dv = D(octant_strains(strain_field(u, E, h), C21))
+        for I in range(6):
+            EI = np.zeros(6); EI[I] = 1.0 if I < 3 else 0.5
+            dv = octant_strains(strain_field(np.zeros((3,) + shape), EI, h), C21)
+            C[I, J] = float(np.sum(dv * Dv)) / N
+    return C
+
+
 def _energy_weights(K, G):
     """Quadratic form of the energy density per node: returns a function that
     maps strains (6, N) to the weighted strains D eps (so W = eps^T D eps / 2)."""

@@ -318,6 +318,23 @@ def random_orthotropic(shape, seed, normal=(20.0, 120.0), shear=(5.0, 50.0), cou
     return np.stack([C11, C22, C33, C23, C13, C12, u(*shear), u(*shear), u(*shear)])
 
 
+def random_triclinic(shape, seed, scale=(5.0, 40.0), soft=0.0, soft_scale=0.05):
+    """Per-cell general anisotropic stiffness, (21, nz, ny, nx): the upper triangle of
+    s (B B^T + 2 I) row by row, B a 6x6 matrix of entries uniform in [-1, 1] and s
+    uniform in `scale`, so every cell is symmetric positive definite with all 21
+    constants nonzero.  A fraction `soft` of the cells (chosen at random) is scaled
+    by soft_scale."""
+    rng = SplitMix64(seed)
+    n = int(np.prod(shape))
+    B = (2.0 * rng.uniform_array(36 * n) - 1.0).reshape(n, 6, 6)
+    sc = scale[0] + (scale[1] - scale[0]) * rng.uniform_array(n)
+    if soft > 0.0:
+        sc = np.where(rng.uniform_array(n) < soft, sc * soft_scale, sc)
+    M = sc[:, None, None] * (np.einsum("nij,nkj->nik", B, B) + 2.0 * np.eye(6)[None])
+    out = np.stack([M[:, r, q] for r in range(6) for q in range(r, 6)])
+    return np.ascontiguousarray(out.reshape((21,) + tuple(shape)))
+
+
 def workload_sphere32() -> Microstructure:
     """32^3, matrix (70, 32), one centred fluid sphere of radius 8."""
     return centred_sphere(32, 8.0)

@@ -9,6 +9,10 @@ oracle and of the GPU library:
 * Voigt and Reuss bounds; Hashin-Shtrikman bounds for two isotropic phases;
 * Hill's exact result for the bulk response when all phases share one shear
   modulus;
+* rotation of a Voigt stiffness (through the fourth-order tensor) and the
+  exact long-wave average of a stack of anisotropic layers (Schoenberg and
+  Muir's partition into the components continuous across the layering and the
+  rest), which reduces to Backus for isotropic layers;
 * Eshelby's tensor of a spheroid (Mura's expressions in terms of the
   ellipsoid I-integrals, evaluated by quadrature) and the compliance
   contribution tensor H = [(S2 - S1)^-1 + Q]^-1, Q = C1 : (I - s)
@@ -223,3 +227,63 @@ def noninteracting_stiffness(C1_voigt, C2_voigt, aspect, phi, axis=2):
     H = compliance_contribution(C1_voigt, C2_voigt, s)
     S1 = np.linalg.inv(voigt_stiffness_to_mandel(C1_voigt))
     return mandel_to_voigt_stiffness(np.linalg.inv(S1 + phi * H))
+
+
+def voigt_to_tensor4(C):
+    """c_ijkl of a Voigt stiffness with engineering shear."""
+    T = np.zeros((3, 3, 3, 3))
+    for I, (i, j) in enumerate(VOIGT):
+        for J, (k, l) in enumerate(VOIGT):
+            for a, b in {(i, j), (j, i)}:
+                for c, d in {(k, l), (l, k)}:
+                    T[a, b, c, d] = C[I, J]
+    return T
+
+
+def tensor4_to_voigt(T):
+    return np.array([[T[i, j, k, l] for (k, l) in VOIGT] for (i, j) in VOIGT])
+
+
+def rotate_voigt(C, R):
+    """Stiffness of a material whose axes are turned by the rotation matrix R:
+    c'_ijkl = R_ia R_jb R_kc R_ld c_abcd."""
+    return tensor4_to_voigt(np.einsum("ia,jb,kc,ld,abcd->ijkl", R, R, R, R, voigt_to_tensor4(C)))
+
+
+def rotation(axis, theta):
+    c, s = math.cos(theta), math.sin(theta)
+    i, j = [(1, 2), (2, 0), (0, 1)][axis]
+    R = np.eye(3)
+    R[i, i], R[i, j], R[j, i], R[j, j] = c, -s, s, c
+    return R
+
+
+# Voigt components continuous in stress (the traction on the layer planes) for
+# layers stacked along x, y, z; the others (the in-plane strains) are continuous
+# in strain.
+_TRACTION = {0: [0, 4, 5], 1: [1, 3, 5], 2: [2, 3, 4]}
+
+
+def layered_average(fracs, Cs, axis):
+    """Exact effective stiffness (6x6 Voigt) of a periodic stack of homogeneous
+    anisotropic layers with volume fractions fracs and stiffnesses Cs, stacked
+    along `axis`.  With n the traction components and t the in-plane strain
+    components, each layer's eps_t equals the mean and its sigma_n is common:
+        C_nn* = <C_nn^-1>^-1,   C_nt* = C_nn* <C_nn^-1 C_nt>,
+        C_tt* = <C_tt - C_tn C_nn^-1 C_nt> + <C_tn C_nn^-1> C_nn* <C_nn^-1 C_nt>."""
+    n = _TRACTION[axis]
+    t = [q for q in range(6) if q not in n]
+    f = np.asarray(fracs, float) / np.sum(fracs)
+    inv = lambda A: np.linalg.inv(A)
+    Snn = sum(fk * inv(C[np.ix_(n, n)]) for fk, C in zip(f, Cs))
+    Cnn = inv(Snn)
+    A = sum(fk * inv(C[np.ix_(n, n)]) @ C[np.ix_(n, t)] for fk, C in zip(f, Cs))
+    B = sum(fk * C[np.ix_(t, n)] @ inv(C[np.ix_(n, n)]) for fk, C in zip(f, Cs))
+    T0 = sum(fk * (C[np.ix_(t, t)] - C[np.ix_(t, n)] @ inv(C[np.ix_(n, n)]) @ C[np.ix_(n, t)])
+             for fk, C in zip(f, Cs))
+    out = np.zeros((6, 6))
+    out[np.ix_(n, n)] = Cnn
+    out[np.ix_(n, t)] = Cnn @ A
+    out[np.ix_(t, n)] = B @ Cnn
+    out[np.ix_(t, t)] = T0 + B @ Cnn @ A
+    return out
