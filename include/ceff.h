@@ -178,9 +178,23 @@ ceff_status ceff_set_phases(ceff_ctx* ctx, const uint8_t* phase, int where, int 
  * the isotropic case (isotropic cells: C11 = K + 4G/3, C12 = K - 2G/3, C44 = G).
  * dtype CEFF_F32/CEFF_F64, host or device; copied.  Every constant must be
  * finite, the diagonal ones > 0 and each normal block positive definite, else
- * CEFF_EINVAL.  ncomp = 21 (general anisotropy, which needs strains
- * interpolated between cells and edges) returns CEFF_EUNSUPPORTED.  Replaces
- * any material set before; ceff_gradient is not available for such materials. */
+ * CEFF_EINVAL.
+ * ncomp = 21: general anisotropic (triclinic) cells, 21 x N values, component-
+ * major, the upper triangle of each cell's symmetric 6x6 Voigt matrix row by
+ * row: C11 C12 C13 C14 C15 C16 C22 C23 C24 C25 C26 C33 C34 C35 C36 C44 C45 C46
+ * C55 C56 C66.  The coupled law needs strains shared between cells and edges
+ * (the paper's perspectives: "averaging of some local fields"): each cell is
+ * split into eight corner octants, each with the cell's normal strains and, for
+ * each shear component, the strain of that component's edge meeting its corner
+ * times S_e / S_cell (S: the component's diagonal constant C44, C55 or C66, S_e
+ * its harmonic mean over the edge's four cells); the energy is the mean over
+ * octants of 1/2 eps : C : eps, summed over cells.  Without couplings this is
+ * the orthotropic law above.  Every cell must be finite and positive definite,
+ * else CEFF_EINVAL.  Such materials run one load at a time, with four launches
+ * per iteration and 24 N words of scratch; CEFF_EUNSUPPORTED with wall
+ * boundaries and in ceff_average_stress_noalloc.
+ * Replaces any material set before; ceff_gradient is not available for
+ * anisotropic materials. */
 ceff_status ceff_set_stiffness(ceff_ctx* ctx, const void* c, int ncomp, int dtype, int where);
 
 /* Boundary conditions of the context's problem (default CEFF_BC_PERIODIC).
@@ -213,7 +227,8 @@ ceff_status ceff_set_boundary(ceff_ctx* ctx, int mode);
  * (defaults).  hist (optional, 3*hist_cap doubles) receives (iteration, load,
  * relative residual) triples of every check; *hist_len their count.
  * iters_out (optional, 6 entries) gets the iterations per load (0 when the
- * affine guess is already in equilibrium).  On CEFF_ENOTCONV/CEFF_EDIVERGED
+ * affine guess is already in equilibrium, also up to rounding: its residual
+ * below 1e-13 of sqrt(3N) max|<sigma>| 2/h_min).  On CEFF_ENOTCONV/CEFF_EDIVERGED
  * the columns hold the stress averages of the last iterate. */
 ceff_status ceff_solve(ceff_ctx* ctx, uint32_t load_mask, const ceff_solve_opts* opts, double C_out[36],
                        double* hist, int64_t hist_cap, int64_t* hist_len, int64_t iters_out[6]);

@@ -267,15 +267,16 @@ class Context:
         self.shape = (nz, ny, nx)
         self.h_spacing = tuple(map(float, h))
 
-    def set_stiffness(self, C9, h=(1.0, 1.0, 1.0)):
-        """Orthotropic cells: C9 shaped (9, nz, ny, nx), constants C11 C22 C33 C23 C13 C12 C44 C55 C66
-        (numpy or torch, float32/float64)."""
-        if C9.ndim != 4 or C9.shape[0] != 9:
-            raise ValueError("C9 must be shaped (9, nz, ny, nx)")
-        nz, ny, nx = (int(v) for v in C9.shape[1:])
+    def set_stiffness(self, C, h=(1.0, 1.0, 1.0)):
+        """Anisotropic cells (numpy or torch, float32/float64): C shaped (9, nz, ny, nx), orthotropic
+        constants C11 C22 C33 C23 C13 C12 C44 C55 C66; or (21, nz, ny, nx), general cells, the upper
+        triangle of the 6x6 Voigt matrix row by row (C11 C12 ... C16 C22 ... C66)."""
+        if C.ndim != 4 or C.shape[0] not in (9, 21):
+            raise ValueError("C must be shaped (9, nz, ny, nx) or (21, nz, ny, nx)")
+        nz, ny, nx = (int(v) for v in C.shape[1:])
         ceff_set_grid(self.h, nx, ny, nz, *map(float, h))
-        p, dt, wh, keep = _array_arg(C9, "C9")
-        ceff_set_stiffness(self.h, p, 9, dt, wh)
+        p, dt, wh, keep = _array_arg(C, "C")
+        ceff_set_stiffness(self.h, p, int(C.shape[0]), dt, wh)
         self.shape = (nz, ny, nx)
         self.h_spacing = tuple(map(float, h))
 

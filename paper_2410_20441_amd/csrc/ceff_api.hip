@@ -103,6 +103,10 @@ struct ceff_ctx {
   // material given as orthotropic cells: 9N constants (FP64, FP32 copy for the mixed path)
   DevBuf c64, c32;
   bool ortho = false;
+  // material given as general anisotropic cells: 21N constants (FP64, FP32 copy), the
+  // harmonic edge means of the diagonal shear constants and the face step factors
+  DevBuf t64, t32, tse64, tse32, tihf64, tihf32;
+  bool tri = false;
   int boundary = CEFF_BC_PERIODIC;
   DevBuf keep[6];
   bool kept[6] = {false, false, false, false, false, false};
@@ -235,6 +239,8 @@ void clear_ortho(ceff_ctx* c) {
   c->c64.reset();
   c->c32.reset();
   c->ortho = false;
+  c->t64.reset(); c->t32.reset(); c->tse64.reset(); c->tse32.reset(); c->tihf64.reset(); c->tihf32.reset();
+  c->tri = false;
 }
 
 void clear_phases(ceff_ctx* c) {
@@ -266,6 +272,12 @@ struct SampleIn {
   int nphase = 0;
   const double* c64 = nullptr;  // orthotropic cells (9N) or nullptr
   const float* c32 = nullptr;
+  const double* t64 = nullptr;  // general cells (21N), their edge means and face factors, or nullptr
+  const float* t32 = nullptr;
+  const double* tse64 = nullptr;
+  const float* tse32 = nullptr;
+  const double* tihf64 = nullptr;
+  const float* tihf32 = nullptr;
   int walls = 0;                 // 1: rigid, free-slip walls
 };
 
@@ -308,6 +320,8 @@ TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single) {
   t.occ = 0;
   return t;
 }
+
+ceff_status stress_average(ceff_ctx* c, const SampleIn& s, int J, const double* u, double out6[6]);
 
 #ifndef CEFF_KERNEL_HASH
 #define CEFF_KERNEL_HASH "unknown"
@@ -367,9 +381,16 @@ struct Engine {
   std::vector<int> Js;          // requested loads
   TileShape ts{};
   // device
-  std::vector<std::array<DevBuf, 2 * kMaxLoads>> ubuf;  // per sample: u[b][slot] at index b*6+slot
+  std::vector<std::array<DevBuf, 4 * kMaxLoads>> ubuf;  // per sample: u[b][slot] at index b*6+slot
   std::vector<std::array<DevBuf, kMaxLoads>> base, force;
   DevBuf d_in, d_out, d_work, d_work_o, d_partials, d_norms, d_ranges, d_ranges_o, d_rout;
+  DevBuf tscr_in, tscr_out;  // general cells: pipeline scratch of the sweeps and of the FP64 residual
+  // two iterations per launch (ts.tb): the single iterations (the first of a solve, odd
+  // remainders) run on a work list tiled with the usual one-cell ghost ring
+  TileShape ts1{};
+  DevBuf d_work_s;
+  std::vector<WorkItem> work_s;
+  std::vector<int> ranges_s;
   std::vector<SampleDesc<T>> h_in;
   std::vector<SampleDesc<double>> h_out;
   std::vector<WorkItem> work, work_o;  // iteration launches / FP64 residual launches
@@ -378,7 +399,7 @@ struct Engine {
   int parity = 0;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
-  int graph_m = 0;
+  int graph_m = 0, graph_parity = -1;
   // accounting
   double step_ms = 0.0, step_bytes = 0.0, vu = 0.0;
   int64_t launches = 0, outer = 0;
@@ -392,7 +413,7 @@ struct Engine {
   bool single() const { return Js.size() == 1; }
   int slot_of(int J) const { return single() ? 0 : J; }
   int group() const {
-    return single() || ts.pf == 5 || ts.ortho || ts.walls ? 1 : (ts.group > 0 ? ts.group : kMaxLoads);
+    return single() || ts.pf == 5 || ts.ortho || ts.walls || ts.tri ? 1 : (ts.group > 0 ? ts.group : kMaxLoads);
   }
 
   // Read the moduli from the phase image when there is one (one sample) and the
@@ -402,13 +423,14 @@ struct Engine {
     const char* env = std::getenv("CEFF_MODULI");
     const bool fields = env != nullptr && std::strcmp(env, "fields") == 0;
     t.ortho = in[0].c64 != nullptr ? 1 : 0;
+    t.tri = in[0].t64 != nullptr ? 1 : 0;
     t.walls = in[0].walls;
     if (t.walls) t.pf = 3;  // the wall-boundary kernels are variant 3, one load per block
     // the phase table is staged once per block from the first sample, so every
     // sample of the launch must use that same table
     bool shared = true;
     for (const SampleIn& s : in) shared = shared && s.phase != nullptr && s.ptab64 == in[0].ptab64;
-    t.pal = !t.ortho && shared && t.pf == 3 && !fields ? 1 : 0;
+    t.pal = !t.ortho && !t.tri && shared && t.pf == 3 && !fields ? 1 : 0;
     return t;
   }
 
@@ -435,11 +457,13 @@ struct Engine {
     }
     const int G = (int)slots0.size();
     int64_t total_xy = 0;
-    for (auto& s : in) total_xy += ((s.nx + t.bx - 3) / (t.bx - 2)) * ((s.ny + t.by - 3) / (t.by - 2));
+    const int gh = t.tb ? 2 : 1;  // ghost ring of the tiles
+    for (auto& s : in)
+      total_xy += ((s.nx + t.bx - 2 * gh - 1) / (t.bx - 2 * gh)) * ((s.ny + t.by - 2 * gh - 1) / (t.by - 2 * gh));
     for (size_t si = 0; si < in.size(); ++si) {
       const auto& s = in[si];
-      const int tx = (int)((s.nx + t.bx - 3) / (t.bx - 2));
-      const int ty = (int)((s.ny + t.by - 3) / (t.by - 2));
+      const int tx = (int)((s.nx + t.bx - 2 * gh - 1) / (t.bx - 2 * gh));
+      const int ty = (int)((s.ny + t.by - 2 * gh - 1) / (t.by - 2 * gh));
       int kc;
       if (t.kc > 0) {
         kc = t.kc;
@@ -495,17 +519,22 @@ struct Engine {
     return CEFF_OK;
   }
 
-  double bytes_per_launch() const {
+  // Algorithmic bytes of one launch: per voxel and active load, the state words read and
+  // written (single iteration: u^n, u^{n-1} read, u^{n+1} written, 9 words; two iterations:
+  // u^n, u^{n-1} read, u^{n+1}, u^{n+2} written, 12 words), 3 words of body force, and the
+  // material once.
+  double bytes_per_launch(bool single_iteration = false) const {
     double b = 0.0;
+    const double state = ts.tb && !single_iteration ? 12.0 : 9.0;
     for (size_t si = 0; si < in.size(); ++si) {
       const double N = (double)in[si].nx * in[si].ny * in[si].nz;
       int nact = 0;
       for (int l = 0; l < kMaxLoads; ++l)
         if (h_in[si].active & (1u << l)) {
           ++nact;
-          b += N * sizeof(T) * (9.0 + (h_in[si].force[l] ? 3.0 : 0.0));
+          b += N * sizeof(T) * (state + (h_in[si].force[l] ? 3.0 : 0.0));
         }
-      if (nact) b += N * (ts.ortho ? sizeof(T) * 9.0 : (ts.pal ? 1.0 : sizeof(T) * 2.0));
+      if (nact) b += N * (ts.ortho ? sizeof(T) * 9.0 : (ts.tri ? sizeof(T) * 27.0 : (ts.pal ? 1.0 : sizeof(T) * 2.0)));
     }
     return b;
   }
@@ -520,6 +549,7 @@ struct Engine {
   hipError_t step_on(const WorkItem* dw, int nw, TileShape t, int grp, int par, int first, double* partials) {
     const SampleDesc<T>* d = d_in.as<SampleDesc<T>>();
     if (t.ortho) return launch_step_ortho<T>(d, dw, nw, t, par, first, partials, c->s);
+    if (t.tri) return launch_step_tri<T>(d, in[0].nx * in[0].ny * in[0].nz, nw, par, first, partials, c->s);
     switch (grp) {
       case 1: return launch_step<T, 1>(d, dw, nw, t, par, first, partials, c->s);
       case 2: return launch_step<T, 2>(d, dw, nw, t, par, first, partials, c->s);
@@ -528,8 +558,15 @@ struct Engine {
     }
   }
   hipError_t step(int first, double* partials) {
+    if (ts.tb) return step_on(d_work_s.as<WorkItem>(), (int)work_s.size(), ts1, 1, parity, first, partials);
     return step_on(d_work.as<WorkItem>(), (int)work.size(), ts, group(), parity, first, partials);
   }
+  // two iterations (ts.tb); the newest iterate is then in the odd buffer of the other pair
+  hipError_t step_pair(double* partials) {
+    return launch_step_pair<T>(d_in.as<SampleDesc<T>>(), d_work.as<WorkItem>(), (int)work.size(), ts, parity,
+                               partials, c->s);
+  }
+  static int after_pair(int par) { return (((par >> 1) ^ 1) << 1) | 1; }
 
   // FP64 residual of the outer (FP64) displacement with the macroscopic strain;
   // writes float residuals to force buffers when rout is set; norms into d_norms.
@@ -539,6 +576,9 @@ struct Engine {
     if (ts.ortho)
       e = launch_residual_ortho<double, float>(d_out.as<SampleDesc<double>>(), d_work_o.as<WorkItem>(),
                                                (int)work_o.size(), ts, 0, rout, d_partials.as<double>(), c->s);
+    else if (ts.tri)
+      e = launch_residual_tri<double, float>(d_out.as<SampleDesc<double>>(), in[0].nx * in[0].ny * in[0].nz,
+                                             (int)work_o.size(), 0, rout, d_partials.as<double>(), c->s);
     else if (single())
       e = launch_residual<double, float, 1>(d_out.as<SampleDesc<double>>(), d_work_o.as<WorkItem>(),
                                             (int)work_o.size(), ts, 0, rout, d_partials.as<double>(), c->s);
@@ -569,7 +609,7 @@ struct Engine {
   // to single-image FP32 solves with the phase table whose grid still yields
   // at least 2048 (tile, chunk) items at that shape.
   void large_grid_shape() {
-    if (sizeof(T) != 4 || in.size() != 1 || !ts.pal || ts.ortho || ts.walls) return;
+    if (sizeof(T) != 4 || in.size() != 1 || !ts.pal || ts.ortho || ts.walls || ts.tri) return;
     const SampleIn& s = in[0];
     const double ws = (double)s.nx * s.ny * s.nz * (6.0 * sizeof(T) * (double)Js.size() + 1.0);
     if (ws <= kInfinityCacheBytes) return;
@@ -598,7 +638,7 @@ struct Engine {
     }
     ts = with_moduli(default_tile(nxm, nym, fp64, single()));
     large_grid_shape();
-    if (!o.autotune || ts.ortho || ts.walls) return CEFF_OK;
+    if (!o.autotune || ts.ortho || ts.walls || ts.tri || want_tb()) return CEFF_OK;
     const std::string key = tune_key();
     TileShape cached{};
     if (lookup_tuned(c, key, cached)) {
@@ -699,8 +739,17 @@ struct Engine {
     return buf;
   }
 
+  // Two iterations per launch: one image, one load, FP32, periodic isotropic cells, when
+  // CEFF_TB=1 asks for it.
+  bool want_tb() const {
+    const char* env = std::getenv("CEFF_TB");
+    return env != nullptr && std::strcmp(env, "1") == 0 && sizeof(T) == 4 && in.size() == 1 && single() &&
+           in[0].c64 == nullptr && in[0].t64 == nullptr && !in[0].walls;
+  }
+
   ceff_status setup() {
     const int ns = (int)in.size();
+    const int nbuf = want_tb() ? 4 : 2;
     ubuf.resize(ns);
     base.resize(ns);
     force.resize(ns);
@@ -720,6 +769,9 @@ struct Engine {
         dsc->ptab = sizeof(T) == 8 ? (const T*)s.ptab64 : (const T*)s.ptab32;
         dsc->nphase = s.nphase;
         dsc->cst = sizeof(T) == 8 ? (const T*)s.c64 : (const T*)s.c32;
+        dsc->c21 = sizeof(T) == 8 ? (const T*)s.t64 : (const T*)s.t32;
+        dsc->tse = sizeof(T) == 8 ? (const T*)s.tse64 : (const T*)s.tse32;
+        dsc->tihf = sizeof(T) == 8 ? (const T*)s.tihf64 : (const T*)s.tihf32;
         dsc->walls = s.walls;
       }
       SampleDesc<double>& od = h_out[si];
@@ -728,11 +780,24 @@ struct Engine {
       od.mom = p.mom; od.sfac = p.sfac; od.sfac_first = p.sfac_first;
       od.K = s.K64; od.G = s.G64;
       od.cst = s.c64;
+      od.c21 = s.t64;
+      od.tse = s.tse64;
+      od.tihf = s.tihf64;
       od.walls = s.walls;
+      if (s.t64) {  // general cells: one sample; pipeline scratch (24N) for the sweeps and the FP64 residual
+        HIPCK(c, tscr_in.alloc(sizeof(T) * 24 * N));
+        h_in[si].tscr = tscr_in.as<T>();
+        if (sizeof(T) == 8) {
+          od.tscr = (double*)h_in[si].tscr;
+        } else {
+          HIPCK(c, tscr_out.alloc(sizeof(double) * 24 * N));
+          od.tscr = tscr_out.as<double>();
+        }
+      }
       for (int J : Js) {
         const int l = slot_of(J);
         h_in[si].wshear[l] = od.wshear[l] = s.walls && J >= 3 ? J : 0;
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < nbuf; ++b) {
           HIPCK(c, ubuf[si][b * kMaxLoads + l].alloc(sizeof(T) * 3 * N));
           HIPCK(c, launch_fill<T>(ubuf[si][b * kMaxLoads + l].as<T>(), 3 * N, T(0), c->s));
           h_in[si].u[b][l] = ubuf[si][b * kMaxLoads + l].as<T>();
@@ -760,7 +825,19 @@ struct Engine {
     HIPCK(c, d_out.alloc(sizeof(SampleDesc<double>) * ns));
     STCK(tune());
     std::vector<int> kcs, kcs_o;
+    if (nbuf == 4) ts.tb = 1;
     STCK(build_work(ts, group(), work, ranges, kcs));
+    if (ts.tb) {
+      // the single iterations share the z-chunk length (SampleDesc::kc) with the pairs
+      ts.kc = kcs[0];
+      ts1 = ts;
+      ts1.tb = 0;
+      std::vector<int> kcs_s;
+      STCK(build_work(ts1, 1, work_s, ranges_s, kcs_s));
+      HIPCK(c, d_work_s.alloc(sizeof(WorkItem) * work_s.size()));
+      HIPCK(c, hipMemcpyAsync(d_work_s.p, work_s.data(), sizeof(WorkItem) * work_s.size(), hipMemcpyHostToDevice,
+                              c->s));
+    }
     TileShape to = ts;
     to.kc = 0;
     STCK(build_work(to, single() || ts.ortho || ts.walls ? 1 : kMaxLoads, work_o, ranges_o, kcs_o));
@@ -777,7 +854,7 @@ struct Engine {
     HIPCK(c, d_work_o.alloc(sizeof(WorkItem) * work_o.size()));
     HIPCK(c, hipMemcpyAsync(d_work_o.p, work_o.data(), sizeof(WorkItem) * work_o.size(), hipMemcpyHostToDevice,
                             c->s));
-    HIPCK(c, d_partials.alloc(sizeof(double) * kMaxLoads * std::max(work.size(), work_o.size())));
+    HIPCK(c, d_partials.alloc(sizeof(double) * kMaxLoads * std::max({work.size(), work_o.size(), work_s.size()})));
     HIPCK(c, d_norms.alloc(sizeof(double) * kMaxLoads * ns));
     HIPCK(c, d_ranges.alloc(sizeof(int) * ranges.size()));
     HIPCK(c, hipMemcpyAsync(d_ranges.p, ranges.data(), sizeof(int) * ranges.size(), hipMemcpyHostToDevice, c->s));
@@ -793,7 +870,7 @@ struct Engine {
       for (int J : Js) {
         const int l = slot_of(J);
         const int64_t N = in[si].nx * in[si].ny * in[si].nz;
-        for (int b = 0; b < 2; ++b) HIPCK(c, launch_fill<T>(h_in[si].u[b][l], 3 * N, T(0), c->s));
+        for (int b = 0; b < nbuf; ++b) HIPCK(c, launch_fill<T>(h_in[si].u[b][l], 3 * N, T(0), c->s));
       }
     return CEFF_OK;
   }
@@ -833,8 +910,12 @@ struct Engine {
 
   ceff_status run_block(int m) {
     // m iterations: m-1 plain steps and one that also reduces the residual of its input
+    // (with two iterations per launch: m/2 launches, the last one reducing the residual of
+    // its intermediate iterate)
     const double bpl = bytes_per_launch(), vpl = vu_per_launch();
-    if (o.use_graph && (!gexec || graph_m != m)) {
+    const int nl = ts.tb ? m / 2 : m;
+    // a captured graph has the buffer parity of its first launch built in
+    if (o.use_graph && (!gexec || graph_m != m || graph_parity != parity)) {
       if (gexec) {
         (void)hipGraphExecDestroy(gexec);
         gexec = nullptr;
@@ -846,9 +927,10 @@ struct Engine {
       HIPCK(c, hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
       const int p0 = parity;
       hipError_t e = hipSuccess;
-      for (int q = 0; q < m && e == hipSuccess; ++q) {
-        e = step(0, q == m - 1 ? d_partials.as<double>() : nullptr);
-        parity ^= 1;
+      for (int q = 0; q < nl && e == hipSuccess; ++q) {
+        double* part = q == nl - 1 ? d_partials.as<double>() : nullptr;
+        e = ts.tb ? step_pair(part) : step(0, part);
+        parity = ts.tb ? after_pair(parity) : parity ^ 1;
       }
       if (e == hipSuccess)
         e = launch_finalize_norms(d_ranges.as<int>(), (int)in.size(), d_partials.as<double>(), d_norms.as<double>(),
@@ -861,15 +943,17 @@ struct Engine {
       graph = g;
       HIPCK(c, hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
       graph_m = m;
+      graph_parity = p0;
     }
     HIPCK(c, hipEventRecord(c->ev0, c->s));
     if (o.use_graph) {
       HIPCK(c, hipGraphLaunch(gexec, c->s));
-      if (m & 1) parity ^= 1;
+      for (int q = 0; q < nl; ++q) parity = ts.tb ? after_pair(parity) : parity ^ 1;
     } else {
-      for (int q = 0; q < m; ++q) {
-        HIPCK(c, step(0, q == m - 1 ? d_partials.as<double>() : nullptr));
-        parity ^= 1;
+      for (int q = 0; q < nl; ++q) {
+        double* part = q == nl - 1 ? d_partials.as<double>() : nullptr;
+        HIPCK(c, ts.tb ? step_pair(part) : step(0, part));
+        parity = ts.tb ? after_pair(parity) : parity ^ 1;
       }
       HIPCK(c, launch_finalize_norms(d_ranges.as<int>(), (int)in.size(), d_partials.as<double>(),
                                      d_norms.as<double>(), c->s));
@@ -879,9 +963,9 @@ struct Engine {
     float ms = 0.f;
     HIPCK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     step_ms += ms;
-    step_bytes += bpl * m;
+    step_bytes += bpl * nl;
     vu += vpl * m;
-    launches += m;
+    launches += nl;
     return CEFF_OK;
   }
 
@@ -949,6 +1033,22 @@ struct Engine {
     for (auto& p : probs) {
       p.r0 = std::sqrt(nn[(size_t)p.s * kMaxLoads + p.slot]);
       if (p.r0 > 0.0 && std::isfinite(p.r0)) {
+        // A load whose affine state is in equilibrium up to rounding (e.g. a shear that every
+        // layer of a laminate carries with the same modulus, in constants that are not exact
+        // binary numbers) leaves only rounding noise, which no iteration reduces: compare the
+        // residual with its rounding scale, sqrt(3N) |sigma| 2/h_min, |sigma| from the affine
+        // state's mean stresses, and treat it as zero below 1e-13 of that.
+        double a6[6];
+        const double* zero = mixed ? base[p.s][p.slot].template as<double>() : (const double*)h_in[p.s].u[0][p.slot];
+        STCK(stress_average(c, in[p.s], p.J, zero, a6));
+        double smax = 0.0;
+        for (double v : a6) smax = std::max(smax, std::fabs(v));
+        const SampleIn& sp = in[p.s];
+        const double N = (double)sp.nx * sp.ny * sp.nz;
+        const double scale = std::sqrt(3.0 * N) * smax * 2.0 / std::min({sp.h[0], sp.h[1], sp.h[2]});
+        if (p.r0 <= 1e-13 * scale) p.r0 = 0.0;
+      }
+      if (p.r0 > 0.0 && std::isfinite(p.r0)) {
         p.active = true;
         h_in[p.s].active |= 1u << p.slot;
       } else if (!std::isfinite(p.r0)) {
@@ -966,7 +1066,7 @@ struct Engine {
     if (any) {
       STCK(upload_desc());
       // first iteration: u^1 from u^0 (zero, or the initial guess) without momentum
-      const double bpl = bytes_per_launch() * 6.0 / 9.0, vpl = vu_per_launch();
+      const double bpl = bytes_per_launch(true) * 6.0 / 9.0, vpl = vu_per_launch();
       HIPCK(c, hipEventRecord(c->ev0, c->s));
       parity = 0;
       HIPCK(c, step(1, nullptr));
@@ -980,6 +1080,7 @@ struct Engine {
         if (p.active) p.iters = 1;
     }
     int m = o.check_every + (o.check_every & 1);
+    if (ts.tb) m = (m + 3) / 4 * 4;  // whole pairs, an even number of them
     while (true) {
       bool act = false;
       for (auto& p : probs) act |= p.active;
@@ -1079,7 +1180,20 @@ ceff_status stress_average_into(ceff_ctx* c, const SampleIn& s, int J, const dou
   const int64_t N = s.nx * s.ny * s.nz;
   double E[6];
   unit_strain(J, E);
-  if (s.c64)
+  DevBuf tscr, tdesc;  // general cells: the pipeline's scratch and a one-entry sample table
+  SampleDesc<double> th{};
+  if (s.t64) {
+    HIPCK(c, tscr.alloc(sizeof(double) * 24 * N));
+    th.nx = s.nx; th.ny = s.ny; th.nz = s.nz; th.N = N;
+    th.rhx = 1.0 / s.h[0]; th.rhy = 1.0 / s.h[1]; th.rhz = 1.0 / s.h[2];
+    th.u[0][0] = const_cast<double*>(u);
+    for (int q = 0; q < 6; ++q) th.E[0][q] = E[q];
+    th.active = 1u;
+    th.c21 = s.t64; th.tse = s.tse64; th.tihf = s.tihf64; th.tscr = tscr.as<double>();
+    HIPCK(c, tdesc.alloc(sizeof th));
+    HIPCK(c, hipMemcpyAsync(tdesc.p, &th, sizeof th, hipMemcpyHostToDevice, c->s));
+    HIPCK(c, launch_average_stress_tri(tdesc.as<SampleDesc<double>>(), tscr.as<double>(), N, part, cap, o6, c->s));
+  } else if (s.c64)
     HIPCK(c, launch_average_stress_ortho(s.nx, s.ny, s.nz, s.h, s.c64, E, u, part, cap, o6, c->s));
   else
     HIPCK(c, launch_average_stress(s.nx, s.ny, s.nz, s.h, s.K64, s.G64, E, u, part, cap, o6,
@@ -1123,7 +1237,7 @@ void record_shape(ceff_ctx* c, const Engine<T>& e) {
   c->stats.tile_by = e.ts.by;
   c->stats.tile_kc = e.h_in.empty() ? 0 : e.h_in[0].kc;
   c->stats.tile_group = e.group();
-  c->stats.tile_variant = e.ts.pf;
+  c->stats.tile_variant = e.ts.tb ? 6 : e.ts.pf;
   c->stats.phase_moduli = e.ts.pal;
 }
 
@@ -1166,6 +1280,16 @@ ceff_status run_engine(ceff_ctx* c, std::vector<SampleIn> samples, std::vector<i
 ceff_status ensure32(ceff_ctx* c) {
   if (c->have32) return CEFF_OK;
   const int64_t N = c->nx * c->ny * c->nz;
+  if (c->tri) {
+    HIPCK(c, c->t32.alloc(sizeof(float) * 21 * N));
+    HIPCK(c, launch_convert<double, float>(c->t64.as<double>(), c->t32.as<float>(), 21 * N, c->s));
+    HIPCK(c, c->tse32.alloc(sizeof(float) * 3 * N));
+    HIPCK(c, c->tihf32.alloc(sizeof(float) * 3 * N));
+    HIPCK(c, launch_tri_setup<float>(c->t64.as<double>(), c->nx, c->ny, c->nz, c->tse32.as<float>(),
+                                     c->tihf32.as<float>(), c->s));
+    c->have32 = true;
+    return CEFF_OK;
+  }
   if (c->ortho) {
     HIPCK(c, c->c32.alloc(sizeof(float) * 9 * N));
     HIPCK(c, launch_convert<double, float>(c->c64.as<double>(), c->c32.as<float>(), 9 * N, c->s));
@@ -1177,6 +1301,13 @@ ceff_status ensure32(ceff_ctx* c) {
   HIPCK(c, launch_convert<double, float>(c->K64.as<double>(), c->K32.as<float>(), N, c->s));
   HIPCK(c, launch_convert<double, float>(c->G64.as<double>(), c->G32.as<float>(), N, c->s));
   c->have32 = true;
+  return CEFF_OK;
+}
+
+// Wall boundaries are implemented for isotropic cells only.
+ceff_status check_walls_material(ceff_ctx* c) {
+  if (c->boundary == CEFF_BC_WALLS && (c->ortho || c->tri))
+    return fail(c, CEFF_EUNSUPPORTED, "wall boundaries with anisotropic cells");
   return CEFF_OK;
 }
 
@@ -1248,6 +1379,14 @@ SampleIn ctx_sample(ceff_ctx* c) {
   if (c->ortho) {
     s.c64 = c->c64.as<double>();
     s.c32 = c->have32 ? c->c32.as<float>() : nullptr;
+  }
+  if (c->tri) {
+    s.t64 = c->t64.as<double>();
+    s.tse64 = c->tse64.as<double>();
+    s.tihf64 = c->tihf64.as<double>();
+    s.t32 = c->have32 ? c->t32.as<float>() : nullptr;
+    s.tse32 = c->have32 ? c->tse32.as<float>() : nullptr;
+    s.tihf32 = c->have32 ? c->tihf32.as<float>() : nullptr;
   }
   if (c->nphase > 0) {
     s.phase = c->phase8.as<uint8_t>();
@@ -1425,8 +1564,8 @@ ceff_status ceff_set_phases(ceff_ctx* c, const uint8_t* phase, int where, int np
 ceff_status ceff_set_stiffness(ceff_ctx* c, const void* cmat, int ncomp, int dtype, int where) {
   if (!c) return CEFF_EINVAL;
   if (!c->grid_set) return fail(c, CEFF_ESTATE, "set the grid first");
-  if (ncomp == 21) return fail(c, CEFF_EUNSUPPORTED, "general anisotropic (21-constant) cells are not implemented");
-  if (ncomp != 9) return fail(c, CEFF_EINVAL, "ncomp must be 9 (orthotropic, axes aligned with the grid)");
+  if (ncomp != 9 && ncomp != 21)
+    return fail(c, CEFF_EINVAL, "ncomp must be 9 (orthotropic, axes aligned with the grid) or 21 (general)");
   if (!cmat) return fail(c, CEFF_EINVAL, "null stiffness");
   if (dtype != CEFF_F32 && dtype != CEFF_F64) return fail(c, CEFF_EINVAL, "dtype must be CEFF_F32 or CEFF_F64");
   if (where != CEFF_HOST && where != CEFF_DEVICE) return fail(c, CEFF_EINVAL, "where must be CEFF_HOST or CEFF_DEVICE");
@@ -1438,23 +1577,38 @@ ceff_status ceff_set_stiffness(ceff_ctx* c, const void* cmat, int ncomp, int dty
   clear_phases(c);
   clear_ortho(c);
   clear_kept(c);
-  STCK(load_moduli(c, cmat, dtype, where, 9 * N, c->c64));
+  DevBuf& dst = ncomp == 21 ? c->t64 : c->c64;
+  STCK(load_moduli(c, cmat, dtype, where, ncomp * N, dst));
   {
     DevBuf bad;
     int nb = 0;
     HIPCK(c, bad.alloc(sizeof(int) * 65536));
-    HIPCK(c, launch_check_ortho(c->c64.as<double>(), N, bad.as<int>(), &nb, c->s));
+    if (ncomp == 21)
+      HIPCK(c, launch_check_tri(c->t64.as<double>(), N, bad.as<int>(), &nb, c->s));
+    else
+      HIPCK(c, launch_check_ortho(c->c64.as<double>(), N, bad.as<int>(), &nb, c->s));
     std::vector<int> h(nb);
     HIPCK(c, hipMemcpyAsync(h.data(), bad.p, sizeof(int) * nb, hipMemcpyDeviceToHost, c->s));
     HIPCK(c, hipStreamSynchronize(c->s));
     for (int v : h)
       if (v) {
-        c->c64.reset();
-        return fail(c, CEFF_EINVAL, "orthotropic constants must be finite, with positive diagonal and a "
-                                    "positive definite normal block");
+        dst.reset();
+        return ncomp == 21 ? fail(c, CEFF_EINVAL, "every cell's 21 constants must be finite and form a positive "
+                                                  "definite 6x6 matrix")
+                           : fail(c, CEFF_EINVAL, "orthotropic constants must be finite, with positive diagonal and "
+                                                  "a positive definite normal block");
       }
   }
-  c->ortho = true;
+  if (ncomp == 21) {
+    HIPCK(c, c->tse64.alloc(sizeof(double) * 3 * N));
+    HIPCK(c, c->tihf64.alloc(sizeof(double) * 3 * N));
+    HIPCK(c, launch_tri_setup<double>(c->t64.as<double>(), c->nx, c->ny, c->nz, c->tse64.as<double>(),
+                                      c->tihf64.as<double>(), c->s));
+    HIPCK(c, hipStreamSynchronize(c->s));
+    c->tri = true;
+  } else {
+    c->ortho = true;
+  }
   c->have_material = true;
   return CEFF_OK;
 }
@@ -1481,7 +1635,7 @@ ceff_status ceff_solve(ceff_ctx* c, uint32_t load_mask, const ceff_solve_opts* o
   if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(c, CEFF_EINVAL, "bad history buffer");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
   const bool walls = c->boundary == CEFF_BC_WALLS;
-  if (walls && c->ortho) return fail(c, CEFF_EUNSUPPORTED, "wall boundaries with orthotropic cells");
+  if (walls && (c->ortho || c->tri)) return fail(c, CEFF_EUNSUPPORTED, "wall boundaries with anisotropic cells");
   if (walls && o.warm_u) return fail(c, CEFF_EUNSUPPORTED, "an initial guess with wall boundaries");
   STCK(begin_call(c));
   const auto t0 = std::chrono::steady_clock::now();
@@ -1499,8 +1653,9 @@ ceff_status ceff_solve(ceff_ctx* c, uint32_t load_mask, const ceff_solve_opts* o
   std::vector<double> hv;
   ceff_status worst = CEFF_OK;
   std::vector<std::vector<int>> groups;
-  const bool fuse = !walls && (o.fuse_loads == CEFF_FUSE_AUTO ? fuse_by_cache(c, mixed, (int)Js.size())
-                                                               : o.fuse_loads != 0);
+  // wall tests and general cells run one load at a time
+  const bool fuse = !walls && !c->tri && (o.fuse_loads == CEFF_FUSE_AUTO ? fuse_by_cache(c, mixed, (int)Js.size())
+                                                                         : o.fuse_loads != 0);
   if (fuse && Js.size() > 1)
     groups.push_back(Js);
   else
@@ -1705,7 +1860,8 @@ ceff_status ceff_gradient(ceff_ctx* c, const double W[36], void* dK, void* dG, i
   for (int q = 0; q < 36; ++q)
     if (!std::isfinite(W[q])) return fail(c, CEFF_EINVAL, "W must be finite");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
-  if (c->ortho) return fail(c, CEFF_EUNSUPPORTED, "the gradient is defined for isotropic (K, G) materials only");
+  if (c->ortho || c->tri)
+    return fail(c, CEFF_EUNSUPPORTED, "the gradient is defined for isotropic (K, G) materials only");
   if (c->boundary != CEFF_BC_PERIODIC) return fail(c, CEFF_EUNSUPPORTED, "the gradient needs periodic boundaries");
   GradLoads g{};
   for (int q = 0; q < 36; ++q) g.W[q] = W[q];
@@ -1753,6 +1909,7 @@ ceff_status ceff_apt_steps(ceff_ctx* c, int J, int64_t nsteps, int precision, do
     return fail(c, CEFF_EINVAL, "bad parameters");
   if (!u_out) return fail(c, CEFF_EINVAL, "u_out is null");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  STCK(check_walls_material(c));
   STCK(begin_call(c));
   ceff_solve_opts o;
   ceff_default_opts(&o);
@@ -1777,7 +1934,13 @@ ceff_status ceff_apt_steps(ceff_ctx* c, int J, int64_t nsteps, int precision, do
     e.parity = 0;
     HIPCK(c, e.step(1, nullptr));
     e.parity = 1;
-    for (int64_t q = 1; q < nsteps; ++q) {
+    int64_t q = 1;
+    if (e.ts.tb)
+      for (; q + 2 <= nsteps; q += 2) {
+        HIPCK(c, e.step_pair(nullptr));
+        e.parity = e.after_pair(e.parity);
+      }
+    for (; q < nsteps; ++q) {
       HIPCK(c, e.step(0, nullptr));
       e.parity ^= 1;
     }
@@ -1809,6 +1972,7 @@ ceff_status ceff_residual(ceff_ctx* c, int J, int precision, const double* u, do
   if (precision != CEFF_PREC_FP64 && precision != CEFF_PREC_MIXED) return fail(c, CEFF_EINVAL, "bad precision");
   if (!u) return fail(c, CEFF_EINVAL, "u is null");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  STCK(check_walls_material(c));
   STCK(begin_call(c));
   const int64_t N = c->nx * c->ny * c->nz;
   ceff_solve_opts o;
@@ -1840,6 +2004,9 @@ ceff_status ceff_residual(ceff_ctx* c, int J, int precision, const double* u, do
       HIPCK(c, launch_residual_ortho<T, T>(e.d_in.template as<SampleDesc<T>>(), e.d_work.template as<WorkItem>(),
                                            (int)e.work.size(), e.ts, 0, rp.as<T*>(),
                                            e.d_partials.template as<double>(), c->s));
+    else if (e.ts.tri)
+      HIPCK(c, launch_residual_tri<T, T>(e.d_in.template as<SampleDesc<T>>(), N, (int)e.work.size(), 0, rp.as<T*>(),
+                                         e.d_partials.template as<double>(), c->s));
     else
       HIPCK(c, launch_residual<T, T, 1>(e.d_in.template as<SampleDesc<T>>(), e.d_work.template as<WorkItem>(),
                                         (int)e.work.size(), e.ts, 0, rp.as<T*>(), e.d_partials.template as<double>(),
@@ -1871,6 +2038,7 @@ ceff_status ceff_average_stress(ceff_ctx* c, int J, const double* u, double out6
   if (J < 0 || J > 5) return fail(c, CEFF_EINVAL, "load index must be in [0, 5]");
   if (!u || !out6) return fail(c, CEFF_EINVAL, "null argument");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  STCK(check_walls_material(c));
   STCK(begin_call(c));
   const int64_t N = c->nx * c->ny * c->nz;
   DevBuf d;
@@ -1884,6 +2052,7 @@ ceff_status ceff_average_stress_noalloc(ceff_ctx* c, int J, const double* u, dou
   if (J < 0 || J > 5) return fail(c, CEFF_EINVAL, "load index must be in [0, 5]");
   if (!u || !out6) return fail(c, CEFF_EINVAL, "null argument");
   if (!c->grid_set || !c->have_material) return fail(c, CEFF_ESTATE, "set the grid and the material first");
+  if (c->tri) return fail(c, CEFF_EUNSUPPORTED, "general anisotropic cells need field-sized scratch");
   double* sc = scratch_addr(c->device);
   if (!sc) return fail(c, CEFF_EDEVICE, "no scratch address for device %d", c->device);
   STCK(begin_call(c));

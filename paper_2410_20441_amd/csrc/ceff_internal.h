@@ -19,7 +19,10 @@ struct SampleDesc {
   T sfac_first;               // step numerator of the very first iteration (no momentum yet)
   const T* K;                 // bulk modulus per cell (N)
   const T* G;                 // shear modulus per cell (N)
-  T* u[2][kMaxLoads];         // two rotating displacement buffers per load (3N each)
+  // rotating displacement buffers per load (3N each): single iterations use the pair
+  // (parity, parity ^ 1); the two-iteration kernel writes the other pair (u[2], u[3] or
+  // u[0], u[1]), which is allocated only for it
+  T* u[4][kMaxLoads];
   const T* force[kMaxLoads];  // optional constant body force per load (3N) or nullptr
   // Optional phase image: when phase != nullptr and the launch shape asks for it
   // (TileShape::pal), the iteration kernel reads the 1-byte phase id of each cell
@@ -32,6 +35,15 @@ struct SampleDesc {
   // (component-major) or nullptr; when set, K, G and the phase image are unused
   // and the orthotropic kernels run (TileShape::ortho).
   const T* cst;
+  // General anisotropic cells: 21N constants (upper triangle of the 6x6 Voigt
+  // matrix, row by row, component-major) or nullptr; tse: the harmonic edge
+  // means of C44 / C55 / C66 (3N), tihf: 1/H of every face (3N), tscr: 24N of
+  // scratch (strains, stresses, the cells' shares of edge stresses).  One
+  // sample, load slot 0 (TileShape::tri).
+  const T* c21;
+  const T* tse;
+  const T* tihf;
+  T* tscr;
   // 1: rigid walls instead of periodic boundaries: the d-faces of the grid
   // plane of index 0 in d are held, and edges lying in such a plane carry no
   // shear stress (one load per block; TileShape::walls).  wshear[l] = 3, 4, 5
@@ -67,6 +79,9 @@ struct TileShape {
   int pal;     // 1: moduli from the samples' phase image and table (variant 3 only)
   int ortho;   // 1: orthotropic cells (one load per block, its own kernel)
   int walls;   // 1: wall boundaries (variant 3, one load per block)
+  int tri;     // 1: general anisotropic cells (their own launches, one load)
+  int tb;      // 1: two iterations per launch (one load per block, 2-cell ghost ring; iterations
+               // after the first of a solve come in pairs)
 };
 
 // ---- launch wrappers (ceff_kernels.hip) ----------------------------------------
@@ -79,6 +94,16 @@ struct TileShape {
 template <typename T, int L>
 hipError_t launch_step(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
                        int parity, int first, double* partials, hipStream_t s);
+
+// Two heavy-ball iterations from (u^parity, u^{parity^1}) into the other buffer pair:
+// u^{n+1} to u[(parity ^ 2) & 2], u^{n+2} to u[((parity ^ 2) & 2) | 1] (one load per
+// block, work items tiled with a 2-cell ghost ring).  partials as for launch_step
+// (the residual of u^{n+1}).
+template <typename T>
+hipError_t launch_step_pair(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
+                            int parity, double* partials, hipStream_t s);
+// Dynamic LDS of the two-iteration kernel for shape ts and element size elem.
+size_t pair_lds_bytes(TileShape ts, size_t elem);
 
 // Residual only: r = div(C:(E + grad u^parity)) + force, written as float or T to
 // rout[l] (3N per load, may be nullptr), norms as above.  No update.
@@ -93,6 +118,25 @@ hipError_t launch_step_ortho(const SampleDesc<T>* d_samples, const WorkItem* d_w
 template <typename T, typename R>
 hipError_t launch_residual_ortho(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
                                  int parity, R* const* rout, double* partials, hipStream_t s);
+// General anisotropic cells (SampleDesc::c21, sample 0, load slot 0): one
+// heavy-ball iteration as four launches (strains, cell stresses and edge
+// shares, edge gather, update), or the residual (rout[0], 3N).  The update
+// launch has nwork blocks and writes norm partials like the other kernels.
+template <typename T>
+hipError_t launch_step_tri(const SampleDesc<T>* d_samples, int64_t N, int nwork, int parity, int first,
+                           double* partials, hipStream_t s);
+template <typename T, typename R>
+hipError_t launch_residual_tri(const SampleDesc<T>* d_samples, int64_t N, int nwork, int parity, R* const* rout,
+                               double* partials, hipStream_t s);
+// FP64 stress averages of general cells for the displacement u[0][0] of the
+// one-entry table d (its tscr holds 24N doubles): block partials, then the 6 sums.
+hipError_t launch_average_stress_tri(const SampleDesc<double>* d, const double* tscr, int64_t N, double* partials,
+                                     int nblocks_cap, double* out6, hipStream_t s);
+// Edge means and face step factors of general cells from FP64 constants.
+template <typename T>
+hipError_t launch_tri_setup(const double* c21, int64_t nx, int64_t ny, int64_t nz, T* se, T* ihf, hipStream_t s);
+// Per-block flags (1 = some cell's 21 constants not finite or not positive definite).
+hipError_t launch_check_tri(const double* c21, int64_t n, int* bad, int* nblocks, hipStream_t s);
 // Dynamic LDS of the orthotropic kernels for shape ts and element size elem.
 size_t ortho_lds_bytes(TileShape ts, size_t elem);
 

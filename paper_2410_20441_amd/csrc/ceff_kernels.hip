@@ -1006,6 +1006,258 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
   }
 }
 
+// Two heavy-ball iterations in one z-march (one load per block, periodic
+// boundaries): u^{n+1} from (u^n, u^{n-1}) and u^{n+2} from (u^{n+1}, u^n).
+// u^n and u^{n-1} are buffers parity and parity ^ 1; the results go to the
+// other pair of buffers, u^{n+1} to the even and u^{n+2} to the odd one, so
+// no block overwrites data another block still reads, and u^n, u^{n-1} are read
+// once for two iterations: 12 words of state traffic per two voxel-updates
+// instead of 18.  The ghost ring is two cells deep: stage 1 (u^{n+1}) is valid
+// on the tile and a one-cell ring around it, stage 2 on the tile.  Stage 2 runs
+// two planes behind stage 1, so both stages' inputs go to LDS together and a
+// plane takes two barriers.  The chunk [k0, k1) of u^{n+2} needs u^{n+1} on
+// [k0-1, k1], hence u^n on [k0-2, k1+1]: each stage starts with one plane that
+// only computes the stresses carried to the next.  LDS: 1/(8G) of four planes
+// (by plane index mod 4), 1/H of each stage's plane, and per stage ux uy uz
+// sxx syy sxy sxz syz.  On check iterations the squared residual of u^{n+1}
+// (stage 2's input) is reduced.
+template <typename T, bool HI>
+struct MinWavesT {
+  static constexpr int value = HI ? (sizeof(T) == 4 ? 4 : 2) : (sizeof(T) == 4 ? 2 : 1);
+};
+
+template <typename T, bool HI, bool PAL>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, 512), amdgpu_waves_per_eu(MinWavesT<T, HI>::value)))
+step_kernel_t(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
+              int by, int parity, double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const int nt = blockDim.x;
+  T* base = reinterpret_cast<T*>(smem_raw);
+  T* sG[4] = {base, base + nt, base + 2 * nt, base + 3 * nt};
+  T* sH[2] = {base + 4 * nt, base + 5 * nt};
+  auto S = [&](int st, int f) { return base + (size_t)(6 + 8 * st + f) * nt; };
+  CellCoef<T>* tab = reinterpret_cast<CellCoef<T>*>(base + (size_t)22 * nt);
+  if constexpr (PAL) stage_coef_table(samples[0], tab);
+
+  const int tid = threadIdx.x;
+  const int tx = tid % bx, ty = tid / bx;
+  const int TX = bx - 4, TY = by - 4;
+  const int xm = tid > 0 && tx > 0 ? tid - 1 : tid;
+  const int xp = tx < bx - 1 && tid + 1 < nt ? tid + 1 : tid;
+  const int ym = ty > 0 ? tid - bx : tid;
+  const int yp = ty < by - 1 && tid + bx < nt ? tid + bx : tid;
+  const int xmym = ty > 0 ? xm - bx : xm;
+
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const WorkItem wi = work[w];
+    const SampleDesc<T>* sdp = wi.sample >= 0 ? &samples[wi.sample] : nullptr;
+    if (sdp == nullptr || !((sdp->active >> wi.slot0) & 1u)) {
+      if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+      continue;
+    }
+    const SampleDesc<T>& sd = *sdp;
+    const int s0 = wi.slot0;
+    const int64_t nx = sd.nx, ny = sd.ny, N = sd.N, plane = nx * ny;
+    const int nz32 = (int)sd.nz;
+    const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
+    const T mom = sd.mom, sfac = sd.sfac;
+    const int64_t gi = (int64_t)wi.tx * TX + tx - 2, gj = (int64_t)wi.ty * TY + ty - 2;
+    const int64_t col = wrap_idx(gi, nx) + nx * wrap_idx(gj, ny);
+    const bool ring1 = tx >= 1 && tx <= bx - 2 && ty >= 1 && ty <= by - 2;
+    const bool own = tx >= 2 && tx <= bx - 3 && ty >= 2 && ty <= by - 3 && gi < nx && gj < ny;
+    const int k0 = wi.kz * sd.kc;
+    const int k1 = k0 + sd.kc < nz32 ? k0 + sd.kc : nz32;
+    auto wz = [&](int k) { return k < 0 ? k + nz32 : (k >= nz32 ? k - nz32 : k); };
+
+    const Moduli<T, PAL> mod(sd, tab);
+    const uint32_t col32 = (uint32_t)col, colb = (uint32_t)col * (uint32_t)sizeof(T);
+    const uint32_t pbytes = (uint32_t)(plane * (int64_t)sizeof(T));
+    const T* pn = sd.u[parity][s0];
+    const T* po = sd.u[parity ^ 1][s0];
+    const int dset = (parity ^ 2) & 2;
+    T* q1 = sd.u[dset][s0];
+    T* q2 = sd.u[dset | 1][s0];
+    const T* pf = sd.force[s0];
+    const bool hasf = pf != nullptr;
+    T E[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) E[q] = sd.E[s0][q];
+    auto ld = [&](const T* f, int c, int k) -> T {
+      return PlaneBuf(f + (c * N + plane * (int64_t)wz(k)), pbytes).template ld<T>(colb);
+    };
+    auto st = [&](T* f, int c, int k, T v) { PlaneBuf(f + (c * N + plane * (int64_t)wz(k)), pbytes).st(colb, v); };
+
+    // u^n of planes k+1 (un), k (uc), k-1, k-2 (uh1, uh2); u^{n+1} of planes k-1, k-2 (v1, v2);
+    // cell coefficients of planes k+1, k, k-1, k-2; stresses carried to the next plane per stage
+    T un[3], uc[3], uh1[3], uh2[3], v1[3], v2[3];
+    CellCoef<T> cn, cc, ch1, ch2;
+    T szz[2] = {T(0), T(0)}, sxzl[2] = {T(0), T(0)}, syzl[2] = {T(0), T(0)};
+    double nsum = 0.0;
+    {
+      const int k = k0 - 2;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        uc[c] = ld(pn, c, k);
+        uh1[c] = uh2[c] = v1[c] = v2[c] = T(0);
+      }
+      cc = mod.coef(mod.load(plane * (int64_t)wz(k), col32, colb));
+      ch1 = ch2 = cc;
+      sG[k & 3][tid] = cc.iG8;
+    }
+
+    // one stage's stresses at plane p (own column: u at p and p+1, coefficients of p and p+1;
+    // in-plane neighbours from LDS), published in LDS; returns the face step factors
+    struct Str {
+      T sxx, syy, szz, sxy, sxz, syz, sfx, sfy, sfz;
+    };
+    auto stresses = [&](int sidx, int p, const T* u, const T* unx, const CellCoef<T>& cp, const CellCoef<T>& cq)
+        -> Str {
+      const T* gk = sG[p & 3];
+      const T* gq = sG[(p + 1) & 3];
+      const T* sUx = S(sidx, 0);
+      const T* sUy = S(sidx, 1);
+      const T* sUz = S(sidx, 2);
+      const T ik = gk[tid], ikx = gk[xm], iky = gk[ym];
+      const T in_ = gq[tid], inx = gq[xm], iny = gq[ym];
+      const T G2xy = recip(gk[xmym] + iky + ikx + ik);
+      const T G2xz = recip(ikx + ik + inx + in_);
+      const T G2yz = recip(iky + ik + iny + in_);
+      Str r;
+      r.sfx = sfac * tmin(sH[sidx][xm], cp.iH);
+      r.sfy = sfac * tmin(sH[sidx][ym], cp.iH);
+      r.sfz = sfac * tmin(cq.iH, cp.iH);
+      const T exx = E[0] + (sUx[xp] - u[0]) * rhx;
+      const T eyy = E[1] + (sUy[yp] - u[1]) * rhy;
+      const T ezz = E[2] + (unx[2] - u[2]) * rhz;
+      const T th = exx + eyy + ezz;
+      r.sxx = cp.lam * th + cp.twoG * exx;
+      r.syy = cp.lam * th + cp.twoG * eyy;
+      r.szz = cp.lam * th + cp.twoG * ezz;
+      r.sxy = G2xy * (E[5] + T(0.5) * ((u[0] - sUx[ym]) * rhy + (u[1] - sUy[xm]) * rhx));
+      r.sxz = G2xz * (E[4] + T(0.5) * ((unx[0] - u[0]) * rhz + (unx[2] - sUz[xm]) * rhx));
+      r.syz = G2yz * (E[3] + T(0.5) * ((unx[1] - u[1]) * rhz + (unx[2] - sUz[ym]) * rhy));
+      S(sidx, 3)[tid] = r.sxx;
+      S(sidx, 4)[tid] = r.syy;
+      S(sidx, 5)[tid] = r.sxy;
+      S(sidx, 6)[tid] = sxzl[sidx];
+      S(sidx, 7)[tid] = syzl[sidx];
+      return r;
+    };
+    // the out-of-balance force at this thread's faces of the stage's plane
+    auto residual = [&](int sidx, const Str& r, T* out) {
+      const T* sSxx = S(sidx, 3);
+      const T* sSyy = S(sidx, 4);
+      const T* sSxy = S(sidx, 5);
+      const T* sSxz = S(sidx, 6);
+      const T* sSyz = S(sidx, 7);
+      out[0] = (r.sxx - sSxx[xm]) * rhx + (sSxy[yp] - r.sxy) * rhy + (r.sxz - sxzl[sidx]) * rhz;
+      out[1] = (sSxy[xp] - r.sxy) * rhx + (r.syy - sSyy[ym]) * rhy + (r.syz - syzl[sidx]) * rhz;
+      out[2] = (sSxz[xp] - sxzl[sidx]) * rhx + (sSyz[yp] - syzl[sidx]) * rhy + (r.szz - szz[sidx]) * rhz;
+    };
+
+    auto march = [&](auto Nc) {
+      constexpr bool NORM = decltype(Nc)::value;
+      for (int k = k0 - 2; k <= k1 + 1; ++k) {
+        const int p = k - 2;
+        const bool s1 = k <= k1, s2 = p >= k0 - 1;
+        // global data: u^n and coefficients of plane k+1, u^{n-1} and force at plane k (stage 1),
+        // force at plane p (stage 2)
+        T uo[3] = {T(0), T(0), T(0)}, f1[3] = {T(0), T(0), T(0)}, f2[3] = {T(0), T(0), T(0)};
+        if (s1) {
+          const auto mr = mod.load(plane * (int64_t)wz(k + 1), col32, colb);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) un[c] = ld(pn, c, k + 1);
+          if (ring1 && k >= k0 - 1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) uo[c] = ld(po, c, k);
+            if (hasf) {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) f1[c] = ld(pf, c, k);
+            }
+          }
+          cn = mod.coef(mr);
+          sG[(k + 1) & 3][tid] = cn.iG8;
+          sH[0][tid] = cc.iH;
+          S(0, 0)[tid] = uc[0];
+          S(0, 1)[tid] = uc[1];
+          S(0, 2)[tid] = un[2];
+        }
+        if (s2) {
+          if (own && hasf && p >= k0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f2[c] = ld(pf, c, p);
+          }
+          sH[1][tid] = ch2.iH;
+          S(1, 0)[tid] = v2[0];
+          S(1, 1)[tid] = v2[1];
+          S(1, 2)[tid] = v1[2];
+        }
+        __syncthreads();
+        Str r1{}, r2{};
+        if (s1) r1 = stresses(0, k, uc, un, cc, cn);
+        if (s2) r2 = stresses(1, p, v2, v1, ch2, ch1);
+        __syncthreads();
+        T w1[3] = {T(0), T(0), T(0)};
+        if (s1) {
+          if (ring1 && k >= k0 - 1) {
+            T r[3];
+            residual(0, r1, r);
+            w1[0] = uc[0] + mom * (uc[0] - uo[0]) + r1.sfx * (r[0] + f1[0]);
+            w1[1] = uc[1] + mom * (uc[1] - uo[1]) + r1.sfy * (r[1] + f1[1]);
+            w1[2] = uc[2] + mom * (uc[2] - uo[2]) + r1.sfz * (r[2] + f1[2]);
+            if (own && k >= k0 && k < k1) {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) st(q1, c, k, w1[c]);
+            }
+          }
+          szz[0] = r1.szz;
+          sxzl[0] = r1.sxz;
+          syzl[0] = r1.syz;
+        }
+        if (s2) {
+          if (own && p >= k0) {
+            T r[3];
+            residual(1, r2, r);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r[c] += f2[c];
+            if (NORM) nsum += (double)r[0] * (double)r[0] + (double)r[1] * (double)r[1] + (double)r[2] * (double)r[2];
+            st(q2, 0, p, v2[0] + mom * (v2[0] - uh2[0]) + r2.sfx * r[0]);
+            st(q2, 1, p, v2[1] + mom * (v2[1] - uh2[1]) + r2.sfy * r[1]);
+            st(q2, 2, p, v2[2] + mom * (v2[2] - uh2[2]) + r2.sfz * r[2]);
+          }
+          szz[1] = r2.szz;
+          sxzl[1] = r2.sxz;
+          syzl[1] = r2.syz;
+        }
+        // shift the plane histories by one
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          uh2[c] = uh1[c];
+          uh1[c] = uc[c];
+          uc[c] = un[c];
+          v2[c] = v1[c];
+          v1[c] = w1[c];
+        }
+        ch2 = ch1;
+        ch1 = cc;
+        cc = cn;
+      }
+    };
+    if (partials != nullptr)
+      march(std::true_type{});
+    else
+      march(std::false_type{});
+
+    if (partials != nullptr) {
+      const double tot = block_sum(nsum, red);
+      if (tid == 0)
+        for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = q == s0 ? tot : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
 // Batched-barrier z-march unrolled by three with three rotating register sets,
 // so that the global data of plane k+2 (u^n), and of plane k+1 (u^{n-1},
 // body force), is requested while plane k is processed and first used one
@@ -1780,6 +2032,295 @@ __global__ void check_ortho_kernel(const T* __restrict__ c, int64_t n, int* __re
   if (threadIdx.x == 0) bad[blockIdx.x] = b > 0.0 ? 1 : 0;
 }
 
+// ---- general anisotropic (triclinic) cells ------------------------------------
+//
+// Reading of the coupled law on the staggered grid (the paper's perspectives,
+// items 2-3): each cell is split into eight corner octants; octant (a, b, c),
+// at the cell's corner (i+a, j+b, k+c), takes the cell's normal strains and,
+// for each shear component, the strain of that component's edge meeting the
+// corner weighted by w = S_e / S_cell (S: the component's diagonal constant C44,
+// C55 or C66; S_e: its harmonic mean over the edge's four cells).  The energy is
+// sum over cells of 1/8 sum over octants of 1/2 eps_o . C eps_o, so a cell's
+// normal stresses are the octant mean of C eps_o's normal rows and an edge's
+// shear stress sums, over its four cells and their two octants at the edge,
+// w/8 times the shear row.  One iteration is four launches over the cells of
+// sample 0, load slot 0 (the engine runs such materials one load at a time):
+// strains into scratch, stresses (cells) and each cell's share of its twelve
+// edges' stresses, the gather of those shares into edge stresses, and the
+// update (or residual).  Scratch per sample (SampleDesc::tscr): strains 6N
+// (xx yy zz at cells, engineering yz xz xy at edges), stresses 6N, shares 12N.
+// The constants are the upper triangle of the 6x6 Voigt matrix, row by row.
+
+__device__ __forceinline__ int tri_q(int r, int q) {
+  const int a = r < q ? r : q, b = r < q ? q : r;
+  return 6 * a - a * (a - 1) / 2 + (b - a);
+}
+
+__device__ __forceinline__ int64_t tri_at(int64_t i, int64_t j, int64_t k, int64_t nx, int64_t ny, int64_t nz) {
+  i = i < 0 ? i + nx : (i >= nx ? i - nx : i);
+  j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
+  k = k < 0 ? k + nz : (k >= nz ? k - nz : k);
+  return i + nx * (j + ny * k);
+}
+
+// Strains of u^parity (load slot 0) under the slot's macroscopic strain.
+template <typename T>
+__global__ void tri_strain_kernel(const SampleDesc<T>* __restrict__ samples, int parity) {
+  const SampleDesc<T>& sd = samples[0];
+  if (!(sd.active & 1u)) return;
+  const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N;
+  const T* ux = sd.u[parity][0];
+  const T* uy = ux + N;
+  const T* uz = ux + 2 * N;
+  T* eps = sd.tscr;
+  const T E0 = sd.E[0][0], E1 = sd.E[0][1], E2 = sd.E[0][2];
+  const T G3 = T(2) * sd.E[0][3], G4 = T(2) * sd.E[0][4], G5 = T(2) * sd.E[0][5];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    eps[c] = E0 + (ux[tri_at(i + 1, j, k, nx, ny, nz)] - ux[c]) * sd.rhx;
+    eps[N + c] = E1 + (uy[tri_at(i, j + 1, k, nx, ny, nz)] - uy[c]) * sd.rhy;
+    eps[2 * N + c] = E2 + (uz[tri_at(i, j, k + 1, nx, ny, nz)] - uz[c]) * sd.rhz;
+    eps[3 * N + c] = G3 + (uy[c] - uy[tri_at(i, j, k - 1, nx, ny, nz)]) * sd.rhz +
+                     (uz[c] - uz[tri_at(i, j - 1, k, nx, ny, nz)]) * sd.rhy;
+    eps[4 * N + c] = G4 + (ux[c] - ux[tri_at(i, j, k - 1, nx, ny, nz)]) * sd.rhz +
+                     (uz[c] - uz[tri_at(i - 1, j, k, nx, ny, nz)]) * sd.rhx;
+    eps[5 * N + c] = G5 + (ux[c] - ux[tri_at(i, j - 1, k, nx, ny, nz)]) * sd.rhy +
+                     (uy[c] - uy[tri_at(i - 1, j, k, nx, ny, nz)]) * sd.rhx;
+  }
+}
+
+// Normal stresses of every cell and its shares of the stresses of its twelve
+// edges: share (s, p) of component s (0 yz, 1 xz, 2 xy) at the cell's corner
+// pair p (yz: b + 2c, xz: a + 2c, xy: a + 2b) goes to tscr[(12 + 4 s + p) N + cell].
+template <typename T>
+__global__ void tri_stress_kernel(const SampleDesc<T>* __restrict__ samples) {
+  const SampleDesc<T>& sd = samples[0];
+  if (!(sd.active & 1u)) return;
+  const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N;
+  const T* eps = sd.tscr;
+  T* sig = sd.tscr + 6 * N;
+  T* share = sd.tscr + 12 * N;
+  const T* se = sd.tse;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    T M[21];
+#pragma unroll
+    for (int q = 0; q < 21; ++q) M[q] = sd.c21[q * N + c];
+    const T en[3] = {eps[c], eps[N + c], eps[2 * N + c]};
+    // weights w = S_e / S_cell and weighted strains of the twelve edges
+    T wyz[2][2], wxz[2][2], wxy[2][2], gyz[2][2], gxz[2][2], gxy[2][2];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int u0 = p & 1, u1 = p >> 1;
+      const int64_t eyz = tri_at(i, j + u0, k + u1, nx, ny, nz);  // yz: (b, c) = (u0, u1)
+      const int64_t exz = tri_at(i + u0, j, k + u1, nx, ny, nz);  // xz: (a, c)
+      const int64_t exy = tri_at(i + u0, j + u1, k, nx, ny, nz);  // xy: (a, b)
+      wyz[u0][u1] = se[eyz] / M[15];
+      wxz[u0][u1] = se[N + exz] / M[18];
+      wxy[u0][u1] = se[2 * N + exy] / M[20];
+      gyz[u0][u1] = wyz[u0][u1] * eps[3 * N + eyz];
+      gxz[u0][u1] = wxz[u0][u1] * eps[4 * N + exz];
+      gxy[u0][u1] = wxy[u0][u1] * eps[5 * N + exy];
+    }
+    T sn[3] = {T(0), T(0), T(0)};
+    T tyz[2][2] = {{T(0), T(0)}, {T(0), T(0)}}, txz[2][2] = {{T(0), T(0)}, {T(0), T(0)}},
+      txy[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int a = o & 1, b = (o >> 1) & 1, cc = o >> 2;
+      const T v[6] = {en[0], en[1], en[2], gyz[b][cc], gxz[a][cc], gxy[a][b]};
+      T row[6];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        T acc = T(0);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc += M[tri_q(r, q)] * v[q];
+        row[r] = acc;
+      }
+      sn[0] += row[0];
+      sn[1] += row[1];
+      sn[2] += row[2];
+      tyz[b][cc] += row[3];
+      txz[a][cc] += row[4];
+      txy[a][b] += row[5];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) sig[r * N + c] = sn[r] * T(0.125);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int u0 = p & 1, u1 = p >> 1;
+      share[(0 + p) * N + c] = T(0.125) * wyz[u0][u1] * tyz[u0][u1];
+      share[(4 + p) * N + c] = T(0.125) * wxz[u0][u1] * txz[u0][u1];
+      share[(8 + p) * N + c] = T(0.125) * wxy[u0][u1] * txy[u0][u1];
+    }
+  }
+}
+
+// Edge stresses: each edge sums the shares of its four cells.
+template <typename T>
+__global__ void tri_gather_kernel(const SampleDesc<T>* __restrict__ samples) {
+  const SampleDesc<T>& sd = samples[0];
+  if (!(sd.active & 1u)) return;
+  const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N;
+  T* sig = sd.tscr + 6 * N;
+  const T* share = sd.tscr + 12 * N;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    T tyz = T(0), txz = T(0), txy = T(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int q0 = q & 1, q1 = q >> 1;
+      const int p = (1 - q0) + 2 * (1 - q1);  // the edge's corner pair in that cell
+      tyz += share[(0 + p) * N + tri_at(i, j - 1 + q0, k - 1 + q1, nx, ny, nz)];
+      txz += share[(4 + p) * N + tri_at(i - 1 + q0, j, k - 1 + q1, nx, ny, nz)];
+      txy += share[(8 + p) * N + tri_at(i - 1 + q0, j - 1 + q1, k, nx, ny, nz)];
+    }
+    sig[3 * N + c] = tyz;
+    sig[4 * N + c] = txz;
+    sig[5 * N + c] = txy;
+  }
+}
+
+// Out-of-balance force at the faces, plus the slot's body force.  MODE 0: the
+// heavy-ball update of u^parity into the other buffer (step factor sfac times
+// the face's 1/H, SampleDesc::tihf); MODE 1: write the residual to rout[0].
+// The grid has one block per work item; block w writes its squared-norm partial
+// to partials[w * kMaxLoads] (and zeros for the other slots).
+template <typename T, int MODE, typename R>
+__global__ void __launch_bounds__(256) tri_update_kernel(const SampleDesc<T>* __restrict__ samples, int parity,
+                                                         int first, double* __restrict__ partials,
+                                                         R* const* __restrict__ rout) {
+  __shared__ double red[16];
+  const SampleDesc<T>& sd = samples[0];
+  const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N;
+  double nsum = 0.0;
+  if (sd.active & 1u) {
+    const T* sig = sd.tscr + 6 * N;
+    const T* ucur = sd.u[parity][0];
+    T* uold = sd.u[parity ^ 1][0];
+    const T* f = sd.force[0];
+    const T mom = first ? T(0) : sd.mom;
+    const T sfac = first ? sd.sfac_first : sd.sfac;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+      const T* sxx = sig;
+      const T* syy = sig + N;
+      const T* szz = sig + 2 * N;
+      const T* syz = sig + 3 * N;
+      const T* sxz = sig + 4 * N;
+      const T* sxy = sig + 5 * N;
+      T r[3];
+      r[0] = (sxx[c] - sxx[tri_at(i - 1, j, k, nx, ny, nz)]) * sd.rhx +
+             (sxy[tri_at(i, j + 1, k, nx, ny, nz)] - sxy[c]) * sd.rhy +
+             (sxz[tri_at(i, j, k + 1, nx, ny, nz)] - sxz[c]) * sd.rhz;
+      r[1] = (sxy[tri_at(i + 1, j, k, nx, ny, nz)] - sxy[c]) * sd.rhx +
+             (syy[c] - syy[tri_at(i, j - 1, k, nx, ny, nz)]) * sd.rhy +
+             (syz[tri_at(i, j, k + 1, nx, ny, nz)] - syz[c]) * sd.rhz;
+      r[2] = (sxz[tri_at(i + 1, j, k, nx, ny, nz)] - sxz[c]) * sd.rhx +
+             (syz[tri_at(i, j + 1, k, nx, ny, nz)] - syz[c]) * sd.rhy +
+             (szz[c] - szz[tri_at(i, j, k - 1, nx, ny, nz)]) * sd.rhz;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (f != nullptr) r[d] += f[d * N + c];
+        nsum += (double)r[d] * (double)r[d];
+        if constexpr (MODE == 0) {
+          const T u = ucur[d * N + c];
+          uold[d * N + c] = u + mom * (u - uold[d * N + c]) + sfac * sd.tihf[d * N + c] * r[d];
+        } else {
+          if (rout != nullptr && rout[0] != nullptr) rout[0][d * N + c] = (R)r[d];
+        }
+      }
+    }
+  }
+  if (partials != nullptr) {
+    const double tot = block_sum(nsum, red);
+    if (threadIdx.x == 0)
+      for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)blockIdx.x * kMaxLoads + q] = q == 0 ? tot : 0.0;
+  }
+}
+
+// Per-cell sums of the six stresses into block partials (6 per block).
+__global__ void tri_sum_kernel(const double* __restrict__ sig, int64_t N, double* __restrict__ partials) {
+  __shared__ double red[16];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x)
+    for (int q = 0; q < 6; ++q) acc[q] += sig[q * N + c];
+  for (int q = 0; q < 6; ++q) {
+    const double v = block_sum(acc[q], red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * 6 + q] = v;
+  }
+}
+
+// Material set-up of general cells (FP64 constants c, 21N): the harmonic edge
+// means S_e of C44 / C55 / C66 (se: yz, xz, xy edges, 3N), and 1/H of every face
+// (ihf, 3N), H the larger over the face's two cells of the step stiffness: for
+// direction d the largest of three diagonal constants (x: 11, 66, 55; y: 22,
+// 66, 44; z: 33, 55, 44), each raised by the absolute values of the constants
+// of its row that an orthotropic cell does not have.
+template <typename T>
+__global__ void tri_setup_kernel(const double* __restrict__ cst, int64_t nx, int64_t ny, int64_t nz,
+                                 T* __restrict__ se, T* __restrict__ ihf) {
+  const int64_t N = nx * ny * nz;
+  auto C = [&](int r, int q, int64_t cell) { return cst[(int64_t)tri_q(r, q) * N + cell]; };
+  auto hstep = [&](int d, int64_t cell) {
+    const int rows[3][3] = {{0, 5, 4}, {1, 5, 3}, {2, 4, 3}};
+    double best = 0.0;
+    for (int t = 0; t < 3; ++t) {
+      const int r = rows[d][t];
+      double v = C(r, r, cell);
+      for (int q = 0; q < 6; ++q)
+        if (!((r < 3 && q < 3) || q == r)) v += fabs(C(r, q, cell));
+      best = fmax(best, v);
+    }
+    return best;
+  };
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    se[c] = (T)(4.0 / (1.0 / C(3, 3, tri_at(i, j - 1, k - 1, nx, ny, nz)) + 1.0 / C(3, 3, tri_at(i, j, k - 1, nx, ny, nz)) +
+                       1.0 / C(3, 3, tri_at(i, j - 1, k, nx, ny, nz)) + 1.0 / C(3, 3, c)));
+    se[N + c] = (T)(4.0 / (1.0 / C(4, 4, tri_at(i - 1, j, k - 1, nx, ny, nz)) + 1.0 / C(4, 4, tri_at(i, j, k - 1, nx, ny, nz)) +
+                           1.0 / C(4, 4, tri_at(i - 1, j, k, nx, ny, nz)) + 1.0 / C(4, 4, c)));
+    se[2 * N + c] = (T)(4.0 / (1.0 / C(5, 5, tri_at(i - 1, j - 1, k, nx, ny, nz)) + 1.0 / C(5, 5, tri_at(i, j - 1, k, nx, ny, nz)) +
+                               1.0 / C(5, 5, tri_at(i - 1, j, k, nx, ny, nz)) + 1.0 / C(5, 5, c)));
+    const int64_t nb[3] = {tri_at(i - 1, j, k, nx, ny, nz), tri_at(i, j - 1, k, nx, ny, nz),
+                           tri_at(i, j, k - 1, nx, ny, nz)};
+    for (int d = 0; d < 3; ++d) ihf[d * N + c] = (T)(1.0 / fmax(hstep(d, c), hstep(d, nb[d])));
+  }
+}
+
+// Per-block flags: 1 if a cell's 21 constants are not finite or its 6x6 matrix
+// is not positive definite (Cholesky in FP64).
+__global__ void check_tri_kernel(const double* __restrict__ cst, int64_t n, int* __restrict__ bad) {
+  __shared__ double red[16];
+  double b = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double L[6][6];
+    bool ok = true;
+    for (int r = 0; r < 6; ++r)
+      for (int q = 0; q < 6; ++q) {
+        L[r][q] = cst[(int64_t)tri_q(r, q) * n + t];
+        ok = ok && isfinite(L[r][q]);
+      }
+    for (int q = 0; q < 6 && ok; ++q) {
+      double d = L[q][q];
+      for (int m = 0; m < q; ++m) d -= L[q][m] * L[q][m];
+      if (!(d > 0.0)) {
+        ok = false;
+        break;
+      }
+      L[q][q] = sqrt(d);
+      for (int r = q + 1; r < 6; ++r) {
+        double v = L[r][q];
+        for (int m = 0; m < q; ++m) v -= L[r][m] * L[q][m];
+        L[r][q] = v / L[q][q];
+      }
+    }
+    if (!ok) b = 1.0;
+  }
+  b = block_sum(b, red);
+  if (threadIdx.x == 0) bad[blockIdx.x] = b > 0.0 ? 1 : 0;
+}
+
 __global__ void average_finalize_kernel(const double* __restrict__ partials, int nblocks, double* __restrict__ out6) {
   __shared__ double red[16];
   const int q = blockIdx.x;
@@ -1979,6 +2520,26 @@ hipError_t launch_step(const SampleDesc<T>* d_samples, const WorkItem* d_work, i
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_step_pair(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
+                            int parity, double* partials, hipStream_t s) {
+  const int nt = ((ts.bx * ts.by + 63) / 64) * 64;
+  const size_t lds = pair_lds_bytes(ts, sizeof(T));
+  if (ts.occ && ts.pal)
+    hipLaunchKernelGGL((step_kernel_t<T, true, true>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork, ts.bx,
+                       ts.by, parity, partials);
+  else if (ts.occ)
+    hipLaunchKernelGGL((step_kernel_t<T, true, false>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork,
+                       ts.bx, ts.by, parity, partials);
+  else if (ts.pal)
+    hipLaunchKernelGGL((step_kernel_t<T, false, true>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork,
+                       ts.bx, ts.by, parity, partials);
+  else
+    hipLaunchKernelGGL((step_kernel_t<T, false, false>), dim3(nwork), dim3(nt), lds, s, d_samples, d_work, nwork,
+                       ts.bx, ts.by, parity, partials);
+  return hipGetLastError();
+}
+
 template <typename T, typename R, int L>
 hipError_t launch_residual(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts,
                            int parity, R* const* rout, double* partials, hipStream_t s) {
@@ -2012,6 +2573,11 @@ hipError_t launch_residual_ortho(const SampleDesc<T>* d_samples, const WorkItem*
 }
 
 #if CEFF_IN_PART(0)
+size_t pair_lds_bytes(TileShape ts, size_t elem) {
+  const size_t nt = (size_t)(((ts.bx * ts.by + 63) / 64) * 64);
+  return 22 * nt * elem + (ts.pal ? 256 * 4 * elem : 0);  // 22 arrays, and the 256-entry coefficient table
+}
+
 size_t ortho_lds_bytes(TileShape ts, size_t elem) {
   return (size_t)kOrthoArrays * (((ts.bx * ts.by + 63) / 64) * 64) * elem;
 }
@@ -2099,7 +2665,55 @@ hipError_t launch_check_moduli(const T* K, const T* G, int64_t n, int* bad, int*
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_step_tri(const SampleDesc<T>* d, int64_t N, int nwork, int parity, int first, double* partials,
+                           hipStream_t s) {
+  const int g = grid_for(N);
+  hipLaunchKernelGGL((tri_strain_kernel<T>), dim3(g), dim3(256), 0, s, d, parity);
+  hipLaunchKernelGGL((tri_stress_kernel<T>), dim3(g), dim3(256), 0, s, d);
+  hipLaunchKernelGGL((tri_gather_kernel<T>), dim3(g), dim3(256), 0, s, d);
+  hipLaunchKernelGGL((tri_update_kernel<T, 0, T>), dim3(nwork), dim3(256), 0, s, d, parity, first, partials,
+                     (T* const*)nullptr);
+  return hipGetLastError();
+}
+
+template <typename T, typename R>
+hipError_t launch_residual_tri(const SampleDesc<T>* d, int64_t N, int nwork, int parity, R* const* rout,
+                               double* partials, hipStream_t s) {
+  const int g = grid_for(N);
+  hipLaunchKernelGGL((tri_strain_kernel<T>), dim3(g), dim3(256), 0, s, d, parity);
+  hipLaunchKernelGGL((tri_stress_kernel<T>), dim3(g), dim3(256), 0, s, d);
+  hipLaunchKernelGGL((tri_gather_kernel<T>), dim3(g), dim3(256), 0, s, d);
+  hipLaunchKernelGGL((tri_update_kernel<T, 1, R>), dim3(nwork), dim3(256), 0, s, d, parity, 0, partials, rout);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tri_setup(const double* c21, int64_t nx, int64_t ny, int64_t nz, T* se, T* ihf, hipStream_t s) {
+  hipLaunchKernelGGL((tri_setup_kernel<T>), dim3(grid_for(nx * ny * nz)), dim3(256), 0, s, c21, nx, ny, nz, se, ihf);
+  return hipGetLastError();
+}
+
 #if CEFF_IN_PART(0)
+hipError_t launch_average_stress_tri(const SampleDesc<double>* d, const double* tscr, int64_t N, double* partials,
+                                     int nblocks_cap, double* out6, hipStream_t s) {
+  const int g = grid_for(N);
+  hipLaunchKernelGGL((tri_strain_kernel<double>), dim3(g), dim3(256), 0, s, d, 0);
+  hipLaunchKernelGGL((tri_stress_kernel<double>), dim3(g), dim3(256), 0, s, d);
+  hipLaunchKernelGGL((tri_gather_kernel<double>), dim3(g), dim3(256), 0, s, d);
+  const int nb = g < nblocks_cap ? g : nblocks_cap;
+  hipLaunchKernelGGL(tri_sum_kernel, dim3(nb), dim3(256), 0, s, tscr + 6 * N, N, partials);
+  hipLaunchKernelGGL(average_finalize_kernel, dim3(6), dim3(256), 0, s, partials, nb, out6);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_tri(const double* c, int64_t n, int* bad, int* nblocks, hipStream_t s) {
+  const int g = grid_for(n);
+  *nblocks = g;
+  hipLaunchKernelGGL(check_tri_kernel, dim3(g), dim3(256), 0, s, c, n, bad);
+  return hipGetLastError();
+}
+
 hipError_t launch_check_ortho(const double* c, int64_t n, int* bad, int* nblocks, hipStream_t s) {
   const int g = grid_for(n);
   *nblocks = g;
@@ -2114,6 +2728,8 @@ hipError_t launch_check_ortho(const double* c, int64_t n, int* bad, int* nblocks
   template hipError_t launch_step<T, L>(const SampleDesc<T>*, const WorkItem*, int, TileShape, int, int, double*, \
                                         hipStream_t);
 #if CEFF_IN_PART(1)
+template hipError_t launch_step_pair<float>(const SampleDesc<float>*, const WorkItem*, int, TileShape, int, double*,
+                                            hipStream_t);
 CEFF_INST_STEP(float, 1)
 CEFF_INST_STEP(float, 2)
 #endif
@@ -2122,6 +2738,8 @@ CEFF_INST_STEP(float, 3)
 CEFF_INST_STEP(float, 6)
 #endif
 #if CEFF_IN_PART(3)
+template hipError_t launch_step_pair<double>(const SampleDesc<double>*, const WorkItem*, int, TileShape, int, double*,
+                                             hipStream_t);
 CEFF_INST_STEP(double, 1)
 CEFF_INST_STEP(double, 2)
 CEFF_INST_STEP(double, 3)
@@ -2160,6 +2778,16 @@ template hipError_t launch_phase_to_fields<double>(const uint8_t*, int64_t, cons
 template hipError_t launch_phase_to_fields<float>(const uint8_t*, int64_t, const double*, const double*, int, float*,
                                                   float*, hipStream_t);
 template hipError_t launch_check_moduli<double>(const double*, const double*, int64_t, int*, int*, hipStream_t);
+template hipError_t launch_step_tri<float>(const SampleDesc<float>*, int64_t, int, int, int, double*, hipStream_t);
+template hipError_t launch_step_tri<double>(const SampleDesc<double>*, int64_t, int, int, int, double*, hipStream_t);
+template hipError_t launch_residual_tri<double, float>(const SampleDesc<double>*, int64_t, int, int, float* const*,
+                                                       double*, hipStream_t);
+template hipError_t launch_residual_tri<double, double>(const SampleDesc<double>*, int64_t, int, int,
+                                                        double* const*, double*, hipStream_t);
+template hipError_t launch_residual_tri<float, float>(const SampleDesc<float>*, int64_t, int, int, float* const*,
+                                                      double*, hipStream_t);
+template hipError_t launch_tri_setup<float>(const double*, int64_t, int64_t, int64_t, float*, float*, hipStream_t);
+template hipError_t launch_tri_setup<double>(const double*, int64_t, int64_t, int64_t, double*, double*, hipStream_t);
 template hipError_t launch_check_moduli<float>(const float*, const float*, int64_t, int*, int*, hipStream_t);
 
 #endif

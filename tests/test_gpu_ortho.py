@@ -124,9 +124,9 @@ def test_set_stiffness_errors():
         bad[7, 1, 2, 3] = -1.0
         with pytest.raises(p.CeffError):
             c.set_stiffness(bad)
-        x = np.ascontiguousarray(np.zeros(21 * C9[0].size))
+        x = np.ascontiguousarray(np.zeros(21 * C9[0].size))  # general cells, not positive definite
         st = p._L.ceff_set_stiffness(c.h, x.ctypes.data, 21, _lib.CEFF_F64, _lib.CEFF_HOST)
-        assert st == _lib.CEFF_EUNSUPPORTED
+        assert st == _lib.CEFF_EINVAL
         st = p._L.ceff_set_stiffness(c.h, x.ctypes.data, 5, _lib.CEFF_F64, _lib.CEFF_HOST)
         assert st == _lib.CEFF_EINVAL
         c.set_stiffness(C9)

@@ -219,7 +219,7 @@ def test_error_paths():
     kt = np.array([70.0, 2.2]); gt = np.array([32.0, 1e-3])
     dkt = kt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)); dgt = gt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     assert L.ceff_set_phases(h, ph.ctypes.data, 0, 2, dkt, dgt) == _lib.CEFF_EINVAL
-    assert L.ceff_set_stiffness(h, None, 21, 1, 0) == _lib.CEFF_EUNSUPPORTED
+    assert L.ceff_set_stiffness(h, None, 21, 1, 0) == _lib.CEFF_EINVAL
     K, G = synth.random_fields((4, 4, 4), 1)
     assert L.ceff_set_isotropic(h, K.ctypes.data, G.ctypes.data, 1, 0) == 0
     for field, val in (("courant", 1.5), ("rtol", -1.0), ("check_every", 0), ("strouhal", -1.0),
