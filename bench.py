@@ -38,7 +38,7 @@ MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "e9eb9a7d0a6ce754", "bytes_per
 
 # iteration-kernel variant (ceff_stats.tile_variant) -> kernel name
 VARIANT_KERNEL = {0: "step_kernel", 1: "step_kernel", 2: "step_kernel_u2", 3: "step_kernel_b", 4: "step_kernel_p3",
-                  5: "step_kernel_c"}
+                  5: "step_kernel_c", 6: "step_kernel_t"}
 
 
 # Swept Strouhal numbers per workload family (six loads, mixed precision, rtol 1e-8):
@@ -455,9 +455,9 @@ def other_workload(a, torch, synth, ceff, dev):
         return hsweep(a, torch, synth, ceff, dev)
     if a.workload == "grad128":
         return grad128(a, torch, synth, ceff, dev)
+    if a.calibrate_copy:
+        calibrate_copy(torch, dev, a.calibrate_copy)
     if a.workload == "hbm480":
-        if a.calibrate_copy:
-            calibrate_copy(torch, dev, a.calibrate_copy)
         print(json.dumps(hbm_roofline(a, torch, synth, ceff, dev)), flush=True)
         return
     opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, max_iter=a.max_iter,

@@ -296,7 +296,7 @@ struct Prob {
 constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 
 TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single) {
-  TileShape t;
+  TileShape t{};
   // CEFF_TILE="bx,by[,kc[,group[,variant[,order[,occ]]]]]" overrides the launch shape (the iterates
   // do not depend on it; tests check that)
   if (const char* env = std::getenv("CEFF_TILE")) {
@@ -563,6 +563,9 @@ struct Engine {
   }
   // two iterations (ts.tb); the newest iterate is then in the odd buffer of the other pair
   hipError_t step_pair(double* partials) {
+    for (const SampleDesc<T>& d : h_in)
+      for (int b = 0; b < 4; ++b)
+        if (d.active && d.u[b][0] == nullptr) return hipErrorInvalidValue;
     return launch_step_pair<T>(d_in.as<SampleDesc<T>>(), d_work.as<WorkItem>(), (int)work.size(), ts, parity,
                                partials, c->s);
   }
@@ -825,7 +828,7 @@ struct Engine {
     HIPCK(c, d_out.alloc(sizeof(SampleDesc<double>) * ns));
     STCK(tune());
     std::vector<int> kcs, kcs_o;
-    if (nbuf == 4) ts.tb = 1;
+    ts.tb = nbuf == 4 ? 1 : 0;  // pairs only where the second buffer pair exists
     STCK(build_work(ts, group(), work, ranges, kcs));
     if (ts.tb) {
       // the single iterations share the z-chunk length (SampleDesc::kc) with the pairs
@@ -840,6 +843,7 @@ struct Engine {
     }
     TileShape to = ts;
     to.kc = 0;
+    to.tb = 0;  // the residual kernel tiles with a one-cell ghost ring
     STCK(build_work(to, single() || ts.ortho || ts.walls ? 1 : kMaxLoads, work_o, ranges_o, kcs_o));
     for (int si = 0; si < ns; ++si) {
       h_in[si].kc = kcs[si];

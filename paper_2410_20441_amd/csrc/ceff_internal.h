@@ -67,21 +67,21 @@ struct WorkItem {
 };
 
 struct TileShape {
-  int bx, by;  // block extent including the one-cell ghost ring (threads = bx*by)
-  int kc;      // z-planes per chunk (0 = choose automatically)
-  int group;   // loads per block: 1, 2, 3 or 6 (0 = all requested loads in one block)
-  int pf;      // 0: plain z-march; 1: prefetch the next plane into registers; 2: z-march unrolled by two;
-               // 3: unrolled, all loads of the group between one pair of barriers per plane;
-               // 4: as 3, unrolled by three with the next plane's data requested one plane ahead;
-               // 5: one load per block, no LDS: neighbours read through the caches
-  int order;   // 0: load groups of a tile 8 items apart; 1: each XCD takes a contiguous band
-  int occ;     // 1: build that targets more waves per SIMD (fewer registers)
-  int pal;     // 1: moduli from the samples' phase image and table (variant 3 only)
-  int ortho;   // 1: orthotropic cells (one load per block, its own kernel)
-  int walls;   // 1: wall boundaries (variant 3, one load per block)
-  int tri;     // 1: general anisotropic cells (their own launches, one load)
-  int tb;      // 1: two iterations per launch (one load per block, 2-cell ghost ring; iterations
-               // after the first of a solve come in pairs)
+  int bx = 0, by = 0;  // block extent including the one-cell ghost ring (threads = bx*by)
+  int kc = 0;      // z-planes per chunk (0 = choose automatically)
+  int group = 0;   // loads per block: 1, 2, 3 or 6 (0 = all requested loads in one block)
+  int pf = 0;      // 0: plain z-march; 1: prefetch the next plane into registers; 2: z-march unrolled by two;
+                   // 3: unrolled, all loads of the group between one pair of barriers per plane;
+                   // 4: as 3, unrolled by three with the next plane's data requested one plane ahead;
+                   // 5: one load per block, no LDS: neighbours read through the caches
+  int order = 0;   // 0: load groups of a tile 8 items apart; 1: each XCD takes a contiguous band
+  int occ = 0;     // 1: build that targets more waves per SIMD (fewer registers)
+  int pal = 0;     // 1: moduli from the samples' phase image and table (variant 3 only)
+  int ortho = 0;   // 1: orthotropic cells (one load per block, its own kernel)
+  int walls = 0;   // 1: wall boundaries (variant 3, one load per block)
+  int tri = 0;     // 1: general anisotropic cells (their own launches, one load)
+  int tb = 0;      // 1: two iterations per launch (one load per block, 2-cell ghost ring; iterations
+                   // after the first of a solve come in pairs)
 };
 
 // ---- launch wrappers (ceff_kernels.hip) ----------------------------------------

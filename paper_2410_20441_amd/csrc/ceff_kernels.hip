@@ -1092,7 +1092,9 @@ step_kernel_t(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
     // cell coefficients of planes k+1, k, k-1, k-2; stresses carried to the next plane per stage
     T un[3], uc[3], uh1[3], uh2[3], v1[3], v2[3];
     CellCoef<T> cn, cc, ch1, ch2;
-    T szz[2] = {T(0), T(0)}, sxzl[2] = {T(0), T(0)}, syzl[2] = {T(0), T(0)};
+    // per stage, carried from its previous plane: the lower cell's szz, the lower edges' sxz and
+    // syz, and the lower cell's 1/H (the z-face of a plane separates it from the plane below)
+    T szz[2] = {T(0), T(0)}, sxzl[2] = {T(0), T(0)}, syzl[2] = {T(0), T(0)}, iHlo[2] = {T(1), T(1)};
     double nsum = 0.0;
     {
       const int k = k0 - 2;
@@ -1106,13 +1108,13 @@ step_kernel_t(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       sG[k & 3][tid] = cc.iG8;
     }
 
-    // one stage's stresses at plane p (own column: u at p and p+1, coefficients of p and p+1;
-    // in-plane neighbours from LDS), published in LDS; returns the face step factors
+    // one stage's stresses at plane p (own column: u at p and p+1, the cell coefficients of p;
+    // in-plane neighbours and the 1/(8G) of planes p and p+1 from LDS), published in LDS;
+    // also returns the face step factors
     struct Str {
       T sxx, syy, szz, sxy, sxz, syz, sfx, sfy, sfz;
     };
-    auto stresses = [&](int sidx, int p, const T* u, const T* unx, const CellCoef<T>& cp, const CellCoef<T>& cq)
-        -> Str {
+    auto stresses = [&](int sidx, int p, const T* u, const T* unx, const CellCoef<T>& cp) -> Str {
       const T* gk = sG[p & 3];
       const T* gq = sG[(p + 1) & 3];
       const T* sUx = S(sidx, 0);
@@ -1126,7 +1128,7 @@ step_kernel_t(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       Str r;
       r.sfx = sfac * tmin(sH[sidx][xm], cp.iH);
       r.sfy = sfac * tmin(sH[sidx][ym], cp.iH);
-      r.sfz = sfac * tmin(cq.iH, cp.iH);
+      r.sfz = sfac * tmin(iHlo[sidx], cp.iH);
       const T exx = E[0] + (sUx[xp] - u[0]) * rhx;
       const T eyy = E[1] + (sUy[yp] - u[1]) * rhy;
       const T ezz = E[2] + (unx[2] - u[2]) * rhz;
@@ -1195,8 +1197,8 @@ step_kernel_t(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
         }
         __syncthreads();
         Str r1{}, r2{};
-        if (s1) r1 = stresses(0, k, uc, un, cc, cn);
-        if (s2) r2 = stresses(1, p, v2, v1, ch2, ch1);
+        if (s1) r1 = stresses(0, k, uc, un, cc);
+        if (s2) r2 = stresses(1, p, v2, v1, ch2);
         __syncthreads();
         T w1[3] = {T(0), T(0), T(0)};
         if (s1) {
@@ -1214,6 +1216,7 @@ step_kernel_t(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
           szz[0] = r1.szz;
           sxzl[0] = r1.sxz;
           syzl[0] = r1.syz;
+          iHlo[0] = cc.iH;
         }
         if (s2) {
           if (own && p >= k0) {
@@ -1229,6 +1232,7 @@ step_kernel_t(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
           szz[1] = r2.szz;
           sxzl[1] = r2.sxz;
           syzl[1] = r2.syz;
+          iHlo[1] = ch2.iH;
         }
         // shift the plane histories by one
 #pragma unroll

@@ -9,14 +9,4 @@ for p in (ROOT, os.path.join(ROOT, "tests")):
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
-    config.addinivalue_line("markers", "slow: long CPU run, skipped unless CEFF_SLOW=1")
 
-
-def pytest_collection_modifyitems(config, items):
-    import pytest
-    if os.environ.get("CEFF_SLOW") == "1":
-        return
-    skip = pytest.mark.skip(reason="slow; set CEFF_SLOW=1")
-    for it in items:
-        if "slow" in it.keywords:
-            it.add_marker(skip)
