@@ -747,18 +747,22 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
   const int yp = ty < by - 1 && tid + bx < nt ? tid + bx : tid;
   const int xmym = ty > 0 ? xm - bx : xm;
 
-  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+  // one work item per block (the grid is the work list): straight-line code, so
+  // the per-thread set-up above is not spilled around a loop over items
+  {
+    const int w = blockIdx.x;
+    if (w >= nwork) return;
     const WorkItem wi = work[w];
     if (wi.sample < 0) {
       if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
-      continue;
+      return;
     }
     const SampleDesc<T>& sd = samples[wi.sample];
     const int s0 = wi.slot0;
     const unsigned act = (sd.active >> s0) & ((1u << L) - 1u);
     if (act == 0u) {
       if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
-      continue;
+      return;
     }
     const int64_t nx = sd.nx, ny = sd.ny, nz = sd.nz, N = sd.N, plane = nx * ny;
     const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
@@ -833,11 +837,13 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
       const bool face = k >= k0 && interior;
       const auto mr = mod.load(pn, col32, colb);
       // u^{n-1} and the force only where a face is updated (ghost threads
-      // reading them costs more memory requests than the masking costs ALU)
+      // reading them costs more memory requests than the masking costs ALU).
+      // They are read only under the same conditions (face, not the first
+      // iteration, a force present), so they are not zeroed: zeroing cost a
+      // dozen vector moves per plane in an issue-bound loop.
       T uo0[L], uo1[L], uo2[L], f0[L], f1[L], f2[L];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
-        Ux[Q][l] = Uy[Q][l] = Uz[Q][l] = uo0[l] = uo1[l] = uo2[l] = f0[l] = f1[l] = f2[l] = T(0);
         if (act & (1u << l)) {
           Ux[Q][l] = ldu(l, 0, pn);
           Uy[Q][l] = ldu(l, 1, pn);
@@ -854,6 +860,8 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
               f2[l] = ldf(l, 2, pc);
             }
           }
+        } else {
+          Ux[Q][l] = Uy[Q][l] = Uz[Q][l] = T(0);
         }
       }
       T* gk = sG[P];
@@ -953,9 +961,11 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
           T rx = (sxx[l] - sSxx[xm]) * rhx + (sSxy[yp] - sxy[l]) * rhy + (sxz_n[l] - sxz_c) * rhz;
           T ry = (sSxy[xp] - sxy[l]) * rhx + (syy[l] - sSyy[ym]) * rhy + (syz_n[l] - syz_c) * rhz;
           T rz = (sSxz[xp] - sxz_c) * rhx + (sSyz[yp] - syz_c) * rhy + (szz[l] - Szz[Q][l]) * rhz;
-          rx += f0[l];
-          ry += f1[l];
-          rz += f2[l];
+          if (hasf[l]) {
+            rx += f0[l];
+            ry += f1[l];
+            rz += f2[l];
+          }
           if constexpr (WALLS) {  // held wall faces: no out-of-balance force
             if (wx) rx = T(0);
             if (wy) ry = T(0);
@@ -964,9 +974,15 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
           if (NORM && (L == 1 || partials != nullptr))
             nsum[l] += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
           const T ux = Ux[P][l], uy = Uy[P][l], uz = Uz[P][l];
-          sto_(l, 0, pc, ux + mom * (ux - uo0[l]) + sfx * rx);
-          sto_(l, 1, pc, uy + mom * (uy - uo1[l]) + sfy * ry);
-          sto_(l, 2, pc, uz + mom * (uz - uo2[l]) + sfz * rz);
+          if (first) {  // no momentum in the start-up step
+            sto_(l, 0, pc, ux + sfx * rx);
+            sto_(l, 1, pc, uy + sfy * ry);
+            sto_(l, 2, pc, uz + sfz * rz);
+          } else {
+            sto_(l, 0, pc, ux + mom * (ux - uo0[l]) + sfx * rx);
+            sto_(l, 1, pc, uy + mom * (uy - uo1[l]) + sfy * ry);
+            sto_(l, 2, pc, uz + mom * (uz - uo2[l]) + sfz * rz);
+          }
         }
         Szz[P][l] = szz[l];
         Sxz[P][l] = sxz_k[l];
