@@ -304,20 +304,21 @@ TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single) {
     const int n = std::sscanf(env, "%d,%d,%d,%d,%d,%d,%d", &bx, &by, &kc, &grp, &pf, &ord, &occ);
     if (n >= 2 && bx >= 3 && by >= 3 && ((bx * by + 63) / 64) * 64 <= 512 &&
         (grp == 1 || grp == 2 || grp == 3 || grp == 6))
-      return TileShape{bx, by, n >= 3 ? kc : 0, pf == 5 ? 1 : grp, pf >= 0 && pf <= 5 ? pf : 0, ord ? 1 : 0,
-                       occ ? 1 : 0, 0};
+      return TileShape{bx, by, n >= 3 ? kc : 0, pf == 5 || pf >= 7 ? 1 : grp,
+                       (pf >= 0 && pf <= 5) || pf == 7 || pf == 8 ? pf : 0, ord ? 1 : 0, occ ? 1 : 0, 0};
   }
   // Fastest shapes of the 191^3 sweeps, all with 12-plane chunks and the loads of a block staged
   // between one barrier pair per plane.  FP32, several loads per launch: 66 x 7 ghosted block
-  // (64 x 5 interior), two loads per block.  FP32, one load: 18 x 14 (16 x 12 interior).  FP64:
-  // 34 x 14 (32 x 12 interior), one load per block.
+  // (64 x 5 interior), two loads per block.  FP32, one load: 18 x 14 (16 x 12 interior), the
+  // high-occupancy build (0.0567-0.0570 ms per launch against 0.0594-0.0596 for the other).
+  // FP64: 34 x 14 (32 x 12 interior), one load per block.
   t.bx = (int)std::min<int64_t>(nx + 2, fp64 ? 34 : (single ? 18 : 66));
   t.by = (int)std::min<int64_t>(ny + 2, fp64 || single ? 14 : 7);
   t.kc = 12;
   t.group = fp64 ? 1 : 2;
   t.pf = 3;
   t.order = 1;
-  t.occ = 0;
+  t.occ = !fp64 && single ? 1 : 0;
   return t;
 }
 
@@ -348,7 +349,7 @@ bool lookup_tuned(ceff_ctx* c, const std::string& key, TileShape& out) {
         8)
       continue;
     const int nt = ((t.bx * t.by + 63) / 64) * 64;
-    const bool valid = t.bx >= 3 && t.by >= 3 && nt <= 512 && t.kc >= 0 && t.pf >= 0 && t.pf <= 5 &&
+    const bool valid = t.bx >= 3 && t.by >= 3 && nt <= 512 && t.kc >= 0 && ((t.pf >= 0 && t.pf <= 5) || t.pf == 7 || t.pf == 8) &&
                        (t.group == 1 || t.group == 2 || t.group == 3 || t.group == 6) && (t.order == 0 || t.order == 1) &&
                        (t.occ == 0 || t.occ == 1);
     if (valid && key == k) {  // the last valid entry of a key wins
@@ -413,7 +414,8 @@ struct Engine {
   bool single() const { return Js.size() == 1; }
   int slot_of(int J) const { return single() ? 0 : J; }
   int group() const {
-    return single() || ts.pf == 5 || ts.ortho || ts.walls || ts.tri ? 1 : (ts.group > 0 ? ts.group : kMaxLoads);
+    return single() || ts.pf == 5 || ts.pf >= 7 || ts.ortho || ts.walls || ts.tri ? 1
+                                                                                  : (ts.group > 0 ? ts.group : kMaxLoads);
   }
 
   // Read the moduli from the phase image when there is one (one sample) and the
@@ -426,11 +428,13 @@ struct Engine {
     t.tri = in[0].t64 != nullptr ? 1 : 0;
     t.walls = in[0].walls;
     if (t.walls) t.pf = 3;  // the wall-boundary kernels are variant 3, one load per block
+    // variants 7 and 8 exist for FP32 only; FP64 takes variant 3
+    if (t.pf >= 7 && sizeof(T) == 8) t.pf = 3;
     // the phase table is staged once per block from the first sample, so every
     // sample of the launch must use that same table
     bool shared = true;
     for (const SampleIn& s : in) shared = shared && s.phase != nullptr && s.ptab64 == in[0].ptab64;
-    t.pal = !t.ortho && !t.tri && shared && t.pf == 3 && !fields ? 1 : 0;
+    t.pal = !t.ortho && !t.tri && shared && (t.pf == 3 || t.pf >= 7) && !fields ? 1 : 0;
     return t;
   }
 
@@ -684,7 +688,7 @@ struct Engine {
     for (const TileShape& t : cand) {
       std::vector<WorkItem> w;
       std::vector<int> rg, kcs;
-      const int grp = single() || t.pf == 5 ? 1 : t.group;
+      const int grp = single() || t.pf == 5 || t.pf >= 7 ? 1 : t.group;
       STCK(build_work(t, grp, w, rg, kcs));
       DevBuf dw;
       HIPCK(c, dw.alloc(sizeof(WorkItem) * w.size()));
