@@ -25,15 +25,19 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the iteration kernel measured with rocprofv3 FETCH_SIZE /
-# WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_hbm_counters.md),
-# valid only for the kernel source they were taken on.
-MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "e9eb9a7d0a6ce754", "bytes_per_launch": 3.277046e+08,
-                    # (loads per block, kernel variant, loads fused, moduli from the phase image)
-                    "launch_signature": (1, 3, 0, 1),
+# WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_trace_and_counters.md and
+# profiles/step_kernel_spheres480_trace_and_counters.md), valid only for the kernel source they were taken on.
+MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "125317e7c5ec25d5", "bytes_per_launch": 3.304952e+08,
+                    # (loads per block, kernel variant, loads fused, moduli from the phase image, high occupancy)
+                    "launch_signature": (1, 3, 0, 1, 1),
                     # mean algorithmic bytes per launch of the profiled solve: fixes its mix of
                     # macroscopic-strain and body-force launches
-                    "algorithmic_bytes_per_launch": 3.004993e+08,
-                    "launch": "step_kernel_b<float,1,PAL>, mean over all launches of a full solve"}
+                    "algorithmic_bytes_per_launch": 3.009393e+08,
+                    "launch": "step_kernel_b<float,1,PAL,high occupancy>, mean over all launches of a full solve"}
+# the same for the HBM-resident measurement (480^3, one load, 200 iterations without body force; the mean over
+# its launches after the first, which reads no u^{n-1})
+MEASURED_TRAFFIC_HBM = {"ceff_kernels_sha256_prefix": "125317e7c5ec25d5", "n": 480, "bytes_per_launch": 4.415066e+09,
+                        "algorithmic_bytes_per_launch": 4.091904e+09, "launch_shape": "66x7x48 variant 3"}
 
 
 # iteration-kernel variant (ceff_stats.tile_variant) -> kernel name
@@ -121,12 +125,20 @@ def hbm_roofline(a, torch, synth, ceff, dev):
     st = info["stats"]
     ctx.close()
     achieved = st["step_bytes"] / (st["step_time_ms"] * 1e-3) / 1e9
+    shape = f"{st['tile_bx']}x{st['tile_by']}x{st['tile_kc']} variant {st['tile_variant']}"
+    mt = MEASURED_TRAFFIC_HBM
+    traffic = mt["bytes_per_launch"] if (kernel_source_hash() == mt["ceff_kernels_sha256_prefix"] and
+                                         a.hbm_n == mt["n"] and shape == mt["launch_shape"] and
+                                         st["tile_occ"] == 1) else None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "%s<float,%s> (heavy-ball APT iteration, loads per block = %s)" % (
-                VARIANT_KERNEL[st["tile_variant"]], st["tile_group"], st["tile_group"]),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_note": "HBM bytes per launch after the first (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, rocprofv3, "
+                            "scaled against a 1 GiB copy), taken on this kernel source" if traffic else None,
+            "kernel": "%s<float,%s>%s (heavy-ball APT iteration, loads per block = %s)" % (
+                VARIANT_KERNEL[st["tile_variant"]], st["tile_group"], ", high occupancy" if st["tile_occ"] else "",
+                st["tile_group"]),
             "workload": f"{a.hbm_n}^3 sphere pack (10% fluid pores), load 0, {st['step_launches']} iterations",
-            "launch_shape": f"{st['tile_bx']}x{st['tile_by']}x{st['tile_kc']} variant {st['tile_variant']}",
+            "launch_shape": shape,
             "avg_launch_ms": st["step_time_ms"] / max(st["step_launches"], 1),
             "launches": st["step_launches"],
             "bytes_per_launch": st["step_bytes"] / max(st["step_launches"], 1),
@@ -233,7 +245,7 @@ def main():
         tot["step_ms"] += st["step_time_ms"]
         tot["step_bytes"] += st["step_bytes"]
         tot["launches"] += st["step_launches"]
-        groups.add((st["tile_group"], st["tile_variant"], st["fused_loads"], st["phase_moduli"]))
+        groups.add((st["tile_group"], st["tile_variant"], st["fused_loads"], st["phase_moduli"], st["tile_occ"]))
         Cs.append(C)
         print(f"# step {k}: status {info['status']} iters {info['iters'].tolist()} solve {st['solve_ms']:.1f} ms, "
               f"kernel {st['step_time_ms'] / max(st['step_launches'], 1):.4f} ms/launch, tile {st['tile_bx']}x"
@@ -277,8 +289,9 @@ def main():
         "iterations_per_solve": tot["iters"] / a.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "%s<float,%s> (heavy-ball APT iteration, loads per block = %s)" % (
-                         VARIANT_KERNEL[st["tile_variant"]], st["tile_group"], st["tile_group"]),
+                     "kernel": "%s<float,%s>%s (heavy-ball APT iteration, loads per block = %s)" % (
+                         VARIANT_KERNEL[st["tile_variant"]], st["tile_group"],
+                         ", high occupancy" if st["tile_occ"] else "", st["tile_group"]),
                      "avg_launch_ms": tot["step_ms"] / max(tot["launches"], 1),
                      "bytes_per_launch": tot["step_bytes"] / max(tot["launches"], 1),
                      # the launch's distinct data: per voxel and load the two FP32 displacement

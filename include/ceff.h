@@ -69,10 +69,12 @@ typedef struct {
                            only the damping of the iteration, never its fixed point. */
   int fuse_loads;       /* 1: all requested loads advance in one launch per iteration;
                            0: one load after another;
-                           CEFF_FUSE_AUTO: one after another when the iteration working set of
-                           one load (two displacement buffers + moduli) fits in the GPU's
-                           Infinity Cache (256 MiB) and that of all requested loads does not,
-                           fused otherwise.  Results do not depend on this choice. */
+                           CEFF_FUSE_AUTO: one after another for a phase image in mixed
+                           precision (the loads share only the phase id); otherwise one after
+                           another when the iteration working set of one load (two displacement
+                           buffers + moduli) fits in the GPU's Infinity Cache (256 MiB) and that
+                           of all requested loads does not, fused otherwise.  Results do not
+                           depend on this choice. */
   int use_graph;        /* 1: replay each block of check_every iterations as a HIP graph */
   int keep_fields;      /* 1: keep the converged FP64 displacements for ceff_gradient */
   int autotune;         /* 1: time candidate launch shapes (block extent, z-chunk, loads per
@@ -110,10 +112,11 @@ typedef struct {
                               registers; 2 march unrolled by two planes; 3 as 2 with all loads of a block
                               between one barrier pair per plane; 4 as 3 unrolled by three, loads issued
                               one plane ahead; 5 one load per block, in-plane neighbours read through the
-                              caches instead of LDS */
+                              caches instead of LDS; 6 two iterations per launch (CEFF_TB=1) */
   int fused_loads;         /* 1 if the requested loads advanced together, one launch per iteration */
   int phase_moduli;        /* 1: the iteration kernel read each cell's 1-byte phase id and a per-phase
                               table (material set with ceff_set_phases) instead of the K and G fields */
+  int tile_occ;            /* 1: the high-occupancy build of the iteration kernel (fewer registers) */
 } ceff_stats;
 
 /* Fill *o with the defaults: MIXED, rtol 1e-8, max_iter 2e6, check_every 100,

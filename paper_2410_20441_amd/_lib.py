@@ -36,7 +36,8 @@ class ceff_stats(ctypes.Structure):
                 ("outer_checks", ctypes.c_int64), ("solve_ms", ctypes.c_double),
                 ("tile_bx", ctypes.c_int), ("tile_by", ctypes.c_int), ("tile_kc", ctypes.c_int),
                 ("tile_group", ctypes.c_int), ("tile_variant", ctypes.c_int),
-                ("fused_loads", ctypes.c_int), ("phase_moduli", ctypes.c_int)]
+                ("fused_loads", ctypes.c_int), ("phase_moduli", ctypes.c_int),
+                ("tile_occ", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

@@ -1022,627 +1022,6 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
   }
 }
 
-// ---- one iteration with u^n prefetched into LDS (variant 7) ----------------
-//
-// One heavy-ball iteration, one load per block, FP32, periodic isotropic cells
-// from K and G fields or a phase image.  Every node is computed with the
-// expressions of step_kernel_b in the same order (the compiler may contract the
-// momentum update's multiply-adds differently: iterates agree to a few ulps);
-// what differs is the memory pipeline.  In step_kernel_b a plane's
-// global reads are issued at the start of its step and consumed before the
-// step's first barrier, so every plane waits a full memory round trip and only
-// other resident blocks hide it.  Here each wave copies its lanes' u^n of a
-// z-plane from global memory straight into LDS (buffer loads with the LDS bit),
-// three planes ahead of the step that first reads it, into a ring of three
-// plane slots: no register holds the prefetched plane, so the latency leaves the
-// per-plane chain without costing occupancy.  u^{n-1}, the body force and the
-// moduli are register loads issued two planes ahead, so that waiting for them
-// (which waits for every older memory operation as well) never waits for a copy
-// before that copy is needed.
-//
-// The copies are issued from inline assembly (buffer_load_dword with the LDS
-// bit, no register result), outside the compiler's accounting of outstanding
-// memory operations: it would otherwise, after merging its counts around the
-// loop, wait for the latest copy before every read of the ring.  Its own waits
-// for the register loads stay correct (an operation it does not know about only
-// makes its count conservative).  Completion of the copies is tracked by hand.
-// Every wave issues the same
-// sequence of vector memory instructions (threads without a face use an
-// out-of-range offset, so their loads return 0 and their stores are dropped),
-// and vector memory operations complete in issue order, so before the step of
-// plane k a wait for "at most N younger operations outstanding" makes this
-// wave's copy of plane k+1 complete, N being the operations known to be issued
-// after it; the barrier that follows makes every wave's copy visible.  The
-// barriers are plain s_barrier with compiler fences and a wait for the wave's
-// ordinary LDS writes only (a workgroup fence would wait for the copies in
-// flight too).  A slot is refilled only after the barrier that follows the last
-// read of its plane.
-// s_waitcnt immediate (GFX9 layout) waiting for vmcnt <= n only
-__host__ __device__ constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8); }
-
-// Workgroup barrier that orders LDS without waiting for asynchronous copies into
-// LDS: compiler fences keep memory operations on their side, and the wait covers
-// this wave's ordinary LDS writes (vmcnt and expcnt at their maxima, lgkmcnt 0).
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_waitcnt(0xC07F);
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-
-// Asynchronous copy of one dword per lane from a buffer (the plane at `base`,
-// `bytes` long; lane offset `off`, out of range: zeros) into LDS at `dst` + 4 *
-// lane (dst the same for the whole wave).  No register receives data; M0 carries
-// the LDS address, and no other code of the kernels using it touches M0.
-__device__ __forceinline__ void copy_to_lds(const float* base, uint32_t bytes, const float* dst, uint32_t off) {
-  typedef unsigned u4 __attribute__((ext_vector_type(4)));
-  const uint64_t a = (uint64_t)base;
-  u4 r;
-  r.x = (unsigned)a;
-  r.y = (unsigned)(a >> 32) & 0xFFFFu;  // stride 0
-  r.z = bytes;                          // range of the raw buffer
-  r.w = 0x00020000u;                    // the flags word of PlaneBuf's descriptors
-  const unsigned lds = (unsigned)(uint64_t)(__attribute__((address_space(3))) const float*)dst;
-  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tbuffer_load_dword %1, %2, 0 offen lds"
-               :
-               : "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(off), "s"(r)
-               : "memory", "m0");
-}
-
-// CAP: the largest block (256 or 512 threads).  Every LDS array is static and
-// CAP elements long, so its base is an instruction offset and a neighbour's
-// address is the same register for all arrays.
-template <bool HI, bool PAL, int CAP>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64, CAP), amdgpu_waves_per_eu(MinWaves<float, 1, HI>::value)))
-step_kernel_d(const SampleDesc<float>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
-              int by, int parity, int first, double* __restrict__ partials) {
-  using T = float;
-  constexpr int RT = CAP;  // stride of the components in a ring slot
-  // every per-thread LDS array in one object, so that all addresses are fixed
-  // offsets from the thread's index: rows 0-8 the ring (slot j, component c at
-  // row 3j + c), 9-11 the 1/(8G) of three planes, then 1/H and the stresses
-  __shared__ __align__(16) T sL[18][CAP];
-  __shared__ CellCoef<T> tab[PAL ? 256 : 1];
-  __shared__ double red[16];
-  const int nt = blockDim.x;
-  T* const ring0 = sL[0];
-  T* const ring1 = sL[3];
-  T* const ring2 = sL[6];
-  T* const sG[3] = {sL[9], sL[10], sL[11]};  // 1/(8G) of planes, ring of three
-  T* const sH = sL[12];
-  T* const sSxx = sL[13];
-  T* const sSyy = sL[14];
-  T* const sSxy = sL[15];
-  T* const sSxz = sL[16];
-  T* const sSyz = sL[17];
-  if constexpr (PAL) stage_coef_table(samples[0], tab);
-
-  const int tid = threadIdx.x;
-  const int wb = __builtin_amdgcn_readfirstlane(tid & ~63);  // first thread of this wave
-  const int tx = tid % bx, ty = tid / bx;
-  const int TX = bx - 2, TY = by - 2;
-  const int xm = tid > 0 && tx > 0 ? tid - 1 : tid;
-  const int xp = tx < bx - 1 && tid + 1 < nt ? tid + 1 : tid;
-  const int ym = ty > 0 ? tid - bx : tid;
-  const int yp = ty < by - 1 && tid + bx < nt ? tid + bx : tid;
-  const int xmym = ty > 0 ? xm - bx : xm;
-
-  const int w = blockIdx.x;  // one work item per block
-  if (w >= nwork) return;
-  const WorkItem wi = work[w];
-  if (wi.sample < 0) {
-    if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
-    return;
-  }
-  const SampleDesc<T>& sd = samples[wi.sample];
-  const int s0 = wi.slot0;
-  if (!((sd.active >> s0) & 1u)) {
-    if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
-    return;
-  }
-  const int64_t nx = sd.nx, ny = sd.ny, N = sd.N, plane = nx * ny;
-  const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
-  const T mom = first ? T(0) : sd.mom;
-  const T sfac = first ? sd.sfac_first : sd.sfac;
-  const int64_t gi = (int64_t)wi.tx * TX + tx - 1, gj = (int64_t)wi.ty * TY + ty - 1;
-  const int64_t col = wrap_idx(gi, nx) + nx * wrap_idx(gj, ny);
-  const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
-  const int nz32 = (int)sd.nz;
-  const int k0 = wi.kz * sd.kc;
-  const int k1 = k0 + sd.kc < nz32 ? k0 + sd.kc : nz32;
-
-  const Moduli<T, PAL> mod(sd, tab);
-  const uint32_t col32 = (uint32_t)col, colb = (uint32_t)col * (uint32_t)sizeof(T);
-  const uint32_t pbytes = (uint32_t)(plane * (int64_t)sizeof(T));
-  // threads without a face use an offset one past the plane: the buffer drops their
-  // stores and returns 0 for their loads, so every wave issues the same instructions
-  const uint32_t fb = interior ? colb : pbytes;
-  const T* pcur = sd.u[parity][s0];
-  T* pold = sd.u[parity ^ 1][s0];
-  // without a body force the force loads read u^{n-1}'s buffer out of range (zeros)
-  const bool hasf = sd.force[s0] != nullptr;
-  const T* pfrc = hasf ? sd.force[s0] : pold;
-  const uint32_t ffb = hasf ? fb : pbytes;
-  T E[6];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) E[q] = sd.E[s0][q];
-
-  auto wrapk = [&](int k) -> int64_t {  // element offset of plane k (k in [-1, nz + 2], nz >= 1)
-    int kk = k < 0 ? k + nz32 : k;
-    kk = kk >= nz32 ? kk - nz32 : kk;
-    kk = kk >= nz32 ? kk - nz32 : kk;
-    kk = kk >= nz32 ? kk - nz32 : kk;
-    return plane * kk;
-  };
-  auto ring = [&](auto Jc) -> T* {
-    constexpr int J = decltype(Jc)::value;
-    if constexpr (J == 0) return ring0;
-    else if constexpr (J == 1) return ring1;
-    else return ring2;
-  };
-  // asynchronous copy of this wave's lanes of u^n in plane k into a ring slot;
-  // off = pbytes issues the copy without moving data (it lands as zeros)
-  auto copy_plane = [&](T* slot, int k, uint32_t off) {
-    const int64_t pk = wrapk(k);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) copy_to_lds(pcur + (c * N + pk), pbytes, slot + c * RT + wb, off);
-  };
-  auto ldo = [&](int c, int64_t pk) -> T { return PlaneBuf(pold + (c * N + pk), pbytes).template ld<T>(fb); };
-  auto ldf = [&](int c, int64_t pk) -> T { return PlaneBuf(pfrc + (c * N + pk), pbytes).template ld<T>(ffb); };
-  auto sto = [&](int c, int64_t pk, T v) { PlaneBuf(pold + (c * N + pk), pbytes).st(fb, v); };
-  // Before the step of plane k: this wave's copy of plane k+1 is complete.  Every
-  // step issues, in this order, the moduli (kMod loads) of the plane three ahead,
-  // u^{n-1} (3) and force (3) of the plane two ahead, after its second barrier a
-  // copy (3) and then its stores (3, not in the step at k0 - 1).  From the third
-  // step of the chunk on, the copy of plane k+1 (two steps back) is followed by
-  // 3 + kMod + 6 + 3 + 3 operations; the first two steps wait for all.
-  constexpr int kMod = PAL ? 1 : 2;
-  auto wait_copy = [&](int k) {
-    asm volatile("" ::: "memory");
-    if (k < k0 + 2)
-      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-    else
-      __builtin_amdgcn_s_waitcnt(vmcnt_imm(kMod + 15));
-    asm volatile("" ::: "memory");
-  };
-
-  // carried from plane to plane: own u^n of plane k, the coefficients of plane k,
-  // 1/H of plane k-1, the stresses of plane k-1 needed by plane k, the moduli of
-  // planes k+1 and k+2, u^{n-1} and the force of planes k and k+1
-  T ux, uy, uz, iHlo = T(1), szz_lo = T(0), sxz_lo = T(0), syz_lo = T(0);
-  T uo0, uo1, uo2, f0, f1, f2, uo0n, uo1n, uo2n, f0n, f1n, f2n;
-  CellCoef<T> Cc;
-  typename Moduli<T, PAL>::Raw mr_n, mr_nn;
-  double nsum = 0.0;
-
-  // prologue: planes k0-1, k0, k0+1 on their way into slots 0, 1, 2; the moduli of
-  // k0-1 .. k0+1, u^{n-1} and the force of plane k0
-  copy_plane(ring0, k0 - 1, colb);
-  copy_plane(ring1, k0, colb);
-  copy_plane(ring2, k0 + 1, colb);
-  {
-    const int64_t pl = wrapk(k0 - 1), p0 = wrapk(k0);
-    Cc = mod.coef(mod.load(pl, col32, colb));
-    sG[0][tid] = Cc.iG8;
-    mr_n = mod.load(p0, col32, colb);
-    mr_nn = mod.load(wrapk(k0 + 1), col32, colb);
-    uo0n = ldo(0, p0);
-    uo1n = ldo(1, p0);
-    uo2n = ldo(2, p0);
-    f0n = ldf(0, p0);
-    f1n = ldf(1, p0);
-    f2n = ldf(2, p0);
-    uo0 = uo1 = uo2 = f0 = f1 = f2 = T(0);
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-    asm volatile("" ::: "memory");
-    ux = ring0[tid];
-    uy = ring0[RT + tid];
-    uz = ring0[2 * RT + tid];
-  }
-
-  // step at plane k with plane k in ring slot J and plane k+1 in slot J+1 (mod 3);
-  // UPD: update the faces of plane k (every step but the one at k0 - 1)
-  auto step = [&](int k, auto Jc, auto Uc, auto Nc) {
-    constexpr int J = decltype(Jc)::value;
-    constexpr int Jn = (J + 1) % 3;
-    constexpr bool UPD = decltype(Uc)::value;
-    constexpr bool NORM = decltype(Nc)::value;
-    T* const cur = ring(std::integral_constant<int, J>{});
-    T* const nxt = ring(std::integral_constant<int, Jn>{});
-    const int64_t pc = wrapk(k);
-    wait_copy(k);
-    // own u^n of plane k+1
-    const T unx = nxt[tid], uny = nxt[RT + tid], unz = nxt[2 * RT + tid];
-    const CellCoef<T> Cn = mod.coef(mr_n);
-    T* const gk = sG[J];
-    T* const gn = sG[Jn];
-    gn[tid] = Cn.iG8;
-    sH[tid] = Cc.iH;
-    lds_barrier();
-    // two planes ahead: the moduli of plane k+3, u^{n-1} and the force of plane k+2
-    const int64_t pn2 = wrapk(k + 2);
-    const auto mr_3 = mod.load(wrapk(k + 3), col32, colb);
-    const T uo0m = ldo(0, pn2), uo1m = ldo(1, pn2), uo2m = ldo(2, pn2);
-    const T f0m = ldf(0, pn2), f1m = ldf(1, pn2), f2m = ldf(2, pn2);
-    const T* sUx = cur;
-    const T* sUy = cur + RT;
-    const T* sUzn = nxt + 2 * RT;
-    const T lam = Cc.lam;
-    const T twoG = Cc.twoG;
-    const T ik = gk[tid], ikx = gk[xm], iky = gk[ym];
-    const T in = gn[tid], inx = gn[xm], iny = gn[ym];
-    const T G2xy = recip(gk[xmym] + iky + ikx + ik);
-    const T G2xz = recip(ikx + ik + inx + in);
-    const T G2yz = recip(iky + ik + iny + in);
-    const T sfx = sfac * tmin(sH[xm], Cc.iH);
-    const T sfy = sfac * tmin(sH[ym], Cc.iH);
-    const T sfz = sfac * tmin(iHlo, Cc.iH);
-    const T exx = E[0] + (sUx[xp] - ux) * rhx;
-    const T eyy = E[1] + (sUy[yp] - uy) * rhy;
-    const T ezz = E[2] + (unz - uz) * rhz;
-    const T th = exx + eyy + ezz;
-    const T sxx = lam * th + twoG * exx;
-    const T syy = lam * th + twoG * eyy;
-    const T szz = lam * th + twoG * ezz;
-    const T sxy = G2xy * (E[5] + T(0.5) * ((ux - sUx[ym]) * rhy + (uy - sUy[xm]) * rhx));
-    const T sxz_n = G2xz * (E[4] + T(0.5) * ((unx - ux) * rhz + (unz - sUzn[xm]) * rhx));
-    const T syz_n = G2yz * (E[3] + T(0.5) * ((uny - uy) * rhz + (unz - sUzn[ym]) * rhy));
-    sSxx[tid] = sxx;
-    sSyy[tid] = syy;
-    sSxy[tid] = sxy;
-    sSxz[tid] = sxz_lo;
-    sSyz[tid] = syz_lo;
-    lds_barrier();
-    // plane k's slot is free (its last reads were before this barrier): refill it
-    // with plane k+3 (without moving data if the chunk ends before it)
-    copy_plane(cur, k + 3, k + 3 <= k1 ? colb : pbytes);
-    if constexpr (UPD) {
-      T rx = (sxx - sSxx[xm]) * rhx + (sSxy[yp] - sxy) * rhy + (sxz_n - sxz_lo) * rhz;
-      T ry = (sSxy[xp] - sxy) * rhx + (syy - sSyy[ym]) * rhy + (syz_n - syz_lo) * rhz;
-      T rz = (sSxz[xp] - sxz_lo) * rhx + (sSyz[yp] - syz_lo) * rhy + (szz - szz_lo) * rhz;
-      rx += f0;  // zeros without a body force
-      ry += f1;
-      rz += f2;
-      if (NORM && interior) nsum += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
-      // mom = 0 in the start-up step (u^{n-1} is finite: the buffers start at zero)
-      sto(0, pc, ux + mom * (ux - uo0) + sfx * rx);
-      sto(1, pc, uy + mom * (uy - uo1) + sfy * ry);
-      sto(2, pc, uz + mom * (uz - uo2) + sfz * rz);
-    }
-    szz_lo = szz;
-    sxz_lo = sxz_n;
-    syz_lo = syz_n;
-    iHlo = Cc.iH;
-    Cc = Cn;
-    ux = unx;
-    uy = uny;
-    uz = unz;
-    uo0 = uo0n;
-    uo1 = uo1n;
-    uo2 = uo2n;
-    f0 = f0n;
-    f1 = f1n;
-    f2 = f2n;
-    uo0n = uo0m;
-    uo1n = uo1m;
-    uo2n = uo2m;
-    f0n = f0m;
-    f1n = f1m;
-    f2n = f2m;
-    mr_n = mr_nn;
-    mr_nn = mr_3;
-  };
-
-  auto march = [&](auto Nc) {
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    step(k0 - 1, I0{}, std::false_type{}, Nc);
-    for (int k = k0;;) {
-      if (k >= k1) break;
-      step(k, I1{}, std::true_type{}, Nc);
-      if (++k >= k1) break;
-      step(k, I2{}, std::true_type{}, Nc);
-      if (++k >= k1) break;
-      step(k, I0{}, std::true_type{}, Nc);
-      ++k;
-    }
-  };
-  if (partials != nullptr)
-    march(std::true_type{});
-  else
-    march(std::false_type{});
-
-  if (partials != nullptr) {
-    const double tot = block_sum(nsum, red);
-    if (tid == 0)
-      for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = q == s0 ? tot : 0.0;
-  }
-}
-
-// ---- one iteration, one barrier per plane (variant 8) ------------------------
-//
-// One heavy-ball iteration, one load per block, FP32, periodic isotropic cells
-// from K and G fields or a phase image, with the expressions of step_kernel_b in
-// the same order (iterates agree to a few ulps: the compiler may contract the
-// momentum update differently).  step_kernel_b takes two barriers per plane: one
-// after publishing the plane's displacements and moduli in LDS, one after
-// publishing its stresses.  Here the work between two barriers is one segment:
-// the face update of plane p-1 (from the stresses of p-1 published before the
-// barrier), the stresses of plane p (from the displacements and moduli of p
-// published before the barrier), and the publication of plane p+1's
-// displacements and moduli.  The LDS inputs of a plane alternate between two
-// buffers (the 1/(8G) of three consecutive planes between three) and so do the
-// stresses, so no segment overwrites what the same segment reads: one barrier
-// per plane instead of two, and twice the independent work between barriers.
-// HI asks for five waves per SIMD (at most 96 registers), otherwise four.
-template <bool HI, bool PAL, int CAP>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64, CAP), amdgpu_waves_per_eu(HI ? 5 : 4)))
-step_kernel_e(const SampleDesc<float>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
-              int by, int parity, int first, double* __restrict__ partials) {
-  using T = float;
-  // one object, fixed row offsets from the thread's index:
-  // (j = p - (k0 - 1) numbers the planes of the chunk from its first segment)
-  //   rows 0-5   displacements of plane p for j even (0-2) and odd (3-5): ux(p), uy(p), uz(p+1)
-  //   rows 6-7   1/H of plane p, j even and odd
-  //   rows 8-10  1/(8G) of plane p in row 8 + j mod 3
-  //   rows 11-20 stresses of plane p, j even (11-15) and odd (16-20): sxx, syy, sxy of
-  //              plane p and sxz, syz of the edges between planes p-1 and p
-  __shared__ __align__(16) T sL[21][CAP];
-  __shared__ CellCoef<T> tab[PAL ? 256 : 1];
-  __shared__ double red[16];
-  if constexpr (PAL) stage_coef_table(samples[0], tab);
-  const int nt = blockDim.x;
-
-  const int tid = threadIdx.x;
-  const int tx = tid % bx, ty = tid / bx;
-  const int TX = bx - 2, TY = by - 2;
-  const int xm = tid > 0 && tx > 0 ? tid - 1 : tid;
-  const int xp = tx < bx - 1 && tid + 1 < nt ? tid + 1 : tid;
-  const int ym = ty > 0 ? tid - bx : tid;
-  const int yp = ty < by - 1 && tid + bx < nt ? tid + bx : tid;
-  const int xmym = ty > 0 ? xm - bx : xm;
-
-  const int w = blockIdx.x;  // one work item per block
-  if (w >= nwork) return;
-  const WorkItem wi = work[w];
-  if (wi.sample < 0) {
-    if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
-    return;
-  }
-  const SampleDesc<T>& sd = samples[wi.sample];
-  const int s0 = wi.slot0;
-  if (!((sd.active >> s0) & 1u)) {
-    if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
-    return;
-  }
-  const int64_t nx = sd.nx, ny = sd.ny, N = sd.N, plane = nx * ny;
-  const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
-  const T mom = first ? T(0) : sd.mom;
-  const T sfac = first ? sd.sfac_first : sd.sfac;
-  const int64_t gi = (int64_t)wi.tx * TX + tx - 1, gj = (int64_t)wi.ty * TY + ty - 1;
-  const int64_t col = wrap_idx(gi, nx) + nx * wrap_idx(gj, ny);
-  const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
-  const int nz32 = (int)sd.nz;
-  const int k0 = wi.kz * sd.kc;
-  const int k1 = k0 + sd.kc < nz32 ? k0 + sd.kc : nz32;
-
-  const Moduli<T, PAL> mod(sd, tab);
-  const uint32_t col32 = (uint32_t)col, colb = (uint32_t)col * (uint32_t)sizeof(T);
-  const uint32_t pbytes = (uint32_t)(plane * (int64_t)sizeof(T));
-  // threads without a face read u^{n-1} and the force out of range (no request, zeros)
-  const uint32_t fb = interior ? colb : pbytes;
-  const T* pcur = sd.u[parity][s0];
-  T* pold = sd.u[parity ^ 1][s0];
-  // without a body force the force loads read u^{n-1}'s buffer out of range (zeros)
-  const bool hasf = sd.force[s0] != nullptr;
-  const T* pfrc = hasf ? sd.force[s0] : pold;
-  const uint32_t ffb = hasf ? fb : pbytes;
-  T E[6];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) E[q] = sd.E[s0][q];
-
-  auto wrapk = [&](int k) -> int64_t {  // element offset of plane k (k in [-1, nz + 1], nz >= 2)
-    int kk = k < 0 ? k + nz32 : k;
-    kk = kk >= nz32 ? kk - nz32 : kk;
-    kk = kk >= nz32 ? kk - nz32 : kk;
-    return plane * kk;
-  };
-  auto ldu = [&](int c, int64_t pk) -> T { return PlaneBuf(pcur + (c * N + pk), pbytes).template ld<T>(colb); };
-  auto ldo = [&](int c, int64_t pk) -> T { return PlaneBuf(pold + (c * N + pk), pbytes).template ld<T>(fb); };
-  auto ldf = [&](int c, int64_t pk) -> T { return PlaneBuf(pfrc + (c * N + pk), pbytes).template ld<T>(ffb); };
-  auto sto = [&](int c, int64_t pk, uint32_t off, T v) { PlaneBuf(pold + (c * N + pk), pbytes).st(off, v); };
-
-  // ---- state carried between segments (plane p is the plane whose stresses the
-  // segment computes; p-1 the plane it updates)
-  T u0x, u0y, u0z;            // own u^n of plane p
-  T u1x, u1y, u1z;            // own u^n of plane p+1
-  T v1x = T(0), v1y = T(0), v1z = T(0);  // own u^n of plane p-1
-  CellCoef<T> Cc, Cn;         // coefficients of planes p and p+1
-  T iHlo = T(1);              // 1/H of plane p-1
-  // stresses of plane p-1 (own), and of the edges between p-2 and p-1 (own)
-  T a_xx = T(0), a_yy = T(0), a_zz = T(0), a_xy = T(0), a_xz = T(0), a_yz = T(0);
-  T b_zz = T(0), b_xz = T(0), b_yz = T(0);
-  T sf_x = T(0), sf_y = T(0), sf_z = T(0);  // face step factors of plane p-1
-  double nsum = 0.0;
-
-  // prologue: publish the inputs of plane k0-1 (its displacements and uz of k0, 1/H,
-  // and 1/(8G) of k0-1 and k0)
-  {
-    const int64_t pm = wrapk(k0 - 1), p0 = wrapk(k0);
-    const auto mm = mod.load(pm, col32, colb);
-    const auto m0 = mod.load(p0, col32, colb);
-    u0x = ldu(0, pm);
-    u0y = ldu(1, pm);
-    u0z = ldu(2, pm);
-    u1x = ldu(0, p0);
-    u1y = ldu(1, p0);
-    u1z = ldu(2, p0);
-    Cc = mod.coef(mm);
-    Cn = mod.coef(m0);
-    sL[0][tid] = u0x;  // j = 0
-    sL[1][tid] = u0y;
-    sL[2][tid] = u1z;
-    sL[6][tid] = Cc.iH;
-    sL[8][tid] = Cc.iG8;
-    sL[9][tid] = Cn.iG8;  // j = 1
-    __syncthreads();
-  }
-
-  // segment of plane p: B = j mod 2, G0 = j mod 3 (compile-time in the unrolled march)
-  auto segment = [&](int p, auto Bc, auto Gc, auto Nc) {
-    constexpr int B = decltype(Bc)::value;
-    constexpr int G0 = decltype(Gc)::value;
-    constexpr int G1 = (G0 + 1) % 3, G2 = (G0 + 2) % 3;
-    constexpr bool NORM = decltype(Nc)::value;
-    // Only the face update depends on where the segment lies in the chunk; the
-    // stresses of plane k1 and the inputs of planes beyond it are computed and
-    // published without being used, so that every segment is the same
-    // straight-line code and the carried values pass between segments without
-    // register moves.
-    const bool upd = p - 1 >= k0;  // update plane p-1
-    // loads: u^{n-1} and force of plane p-1 (this segment's update, after the
-    // stresses of plane p), u^n and moduli of plane p+2 (published last)
-    const int64_t pm1 = wrapk(p - 1), p2 = wrapk(p + 2);
-    const T ox = ldo(0, pm1), oy = ldo(1, pm1), oz = ldo(2, pm1);
-    const T fx = ldf(0, pm1), fy = ldf(1, pm1), fz = ldf(2, pm1);
-    const T u2x = ldu(0, p2), u2y = ldu(1, p2), u2z = ldu(2, p2);
-    const auto m2 = mod.load(p2, col32, colb);
-    // keep the loads here: the scheduler would otherwise sink them next to their
-    // uses at the end of the segment, exposing their full latency there
-    asm volatile("" ::: "memory");
-    // plane p-1's own stresses, edges and step factors (phase 1 below replaces them)
-    const T c_xx = a_xx, c_yy = a_yy, c_zz = a_zz, c_xy = a_xy, c_xz = a_xz, c_yz = a_yz;
-    const T d_zz = b_zz, d_xz = b_xz, d_yz = b_yz, g_x = sf_x, g_y = sf_y, g_z = sf_z;
-    {
-      // stresses of plane p from its inputs published before the barrier
-      const T* sUx = sL[3 * B];
-      const T* sUy = sL[3 * B + 1];
-      const T* sUz = sL[3 * B + 2];
-      const T* sH = sL[6 + B];
-      const T* gk = sL[8 + G0];
-      const T* gn = sL[8 + G1];
-      const T ux = u0x, uy = u0y, uz = u0z, unx = u1x, uny = u1y, unz = u1z;
-      const T lam = Cc.lam;
-      const T twoG = Cc.twoG;
-      const T ik = gk[tid], ikx = gk[xm], iky = gk[ym];
-      const T in = gn[tid], inx = gn[xm], iny = gn[ym];
-      const T G2xy = recip(gk[xmym] + iky + ikx + ik);
-      const T G2xz = recip(ikx + ik + inx + in);
-      const T G2yz = recip(iky + ik + iny + in);
-      const T sfx = sfac * tmin(sH[xm], Cc.iH);
-      const T sfy = sfac * tmin(sH[ym], Cc.iH);
-      const T sfz = sfac * tmin(iHlo, Cc.iH);
-      const T exx = E[0] + (sUx[xp] - ux) * rhx;
-      const T eyy = E[1] + (sUy[yp] - uy) * rhy;
-      const T ezz = E[2] + (unz - uz) * rhz;
-      const T th = exx + eyy + ezz;
-      const T sxx = lam * th + twoG * exx;
-      const T syy = lam * th + twoG * eyy;
-      const T szz = lam * th + twoG * ezz;
-      const T sxy = G2xy * (E[5] + T(0.5) * ((ux - sUx[ym]) * rhy + (uy - sUy[xm]) * rhx));
-      const T sxz_n = G2xz * (E[4] + T(0.5) * ((unx - ux) * rhz + (unz - sUz[xm]) * rhx));
-      const T syz_n = G2yz * (E[3] + T(0.5) * ((uny - uy) * rhz + (unz - sUz[ym]) * rhy));
-      sL[11 + 5 * B][tid] = sxx;
-      sL[12 + 5 * B][tid] = syy;
-      sL[13 + 5 * B][tid] = sxy;
-      sL[14 + 5 * B][tid] = a_xz;  // the edges between p-1 and p (computed with plane p-1)
-      sL[15 + 5 * B][tid] = a_yz;
-      // plane p becomes plane p-1 of the next segment
-      b_zz = a_zz;
-      b_xz = a_xz;
-      b_yz = a_yz;
-      a_xx = sxx;
-      a_yy = syy;
-      a_zz = szz;
-      a_xy = sxy;
-      a_xz = sxz_n;
-      a_yz = syz_n;
-      sf_x = sfx;
-      sf_y = sfy;
-      sf_z = sfz;
-    }
-    // face update of plane p-1 from the stresses of p-1 published before the
-    // barrier, computed by every thread and stored where it is a face (elsewhere
-    // the offset is out of range and the store is dropped): no branch, so the
-    // compiler's count of outstanding memory operations stays exact
-    {
-      const bool face = upd && interior;
-      const uint32_t sb = face ? colb : pbytes;
-      const T* sSxx = sL[11 + 5 * (1 - B)];
-      const T* sSyy = sL[12 + 5 * (1 - B)];
-      const T* sSxy = sL[13 + 5 * (1 - B)];
-      const T* sSxz = sL[14 + 5 * (1 - B)];
-      const T* sSyz = sL[15 + 5 * (1 - B)];
-      T rx = (c_xx - sSxx[xm]) * rhx + (sSxy[yp] - c_xy) * rhy + (c_xz - d_xz) * rhz;
-      T ry = (sSxy[xp] - c_xy) * rhx + (c_yy - sSyy[ym]) * rhy + (c_yz - d_yz) * rhz;
-      T rz = (sSxz[xp] - d_xz) * rhx + (sSyz[yp] - d_yz) * rhy + (c_zz - d_zz) * rhz;
-      rx += fx;  // zeros without a body force
-      ry += fy;
-      rz += fz;
-      if (NORM && face) nsum += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
-      // mom = 0 in the start-up step (u^{n-1} is finite: the buffers start at zero)
-      sto(0, pm1, sb, v1x + mom * (v1x - ox) + g_x * rx);
-      sto(1, pm1, sb, v1y + mom * (v1y - oy) + g_y * ry);
-      sto(2, pm1, sb, v1z + mom * (v1z - oz) + g_z * rz);
-    }
-    {  // publish the inputs of plane p+1: ux, uy of p+1, uz of p+2, 1/H of p+1, 1/(8G) of p+2
-      const CellCoef<T> C2 = mod.coef(m2);
-      sL[3 * (1 - B)][tid] = u1x;
-      sL[3 * (1 - B) + 1][tid] = u1y;
-      sL[3 * (1 - B) + 2][tid] = u2z;
-      sL[6 + (1 - B)][tid] = Cn.iH;
-      sL[8 + G2][tid] = C2.iG8;
-      iHlo = Cc.iH;
-      Cc = Cn;
-      Cn = C2;
-    }
-    v1x = u0x;
-    v1y = u0y;
-    v1z = u0z;
-    u0x = u1x;
-    u0y = u1y;
-    u0z = u1z;
-    u1x = u2x;
-    u1y = u2y;
-    u1z = u2z;
-    // threads exchange data through LDS only: the barrier need not wait for the
-    // global stores of this segment (a workgroup fence would)
-    lds_barrier();
-  };
-
-  // segments p = k0-1 .. k1 (j = 0 .. kc+1), unrolled by six so that the buffer and
-  // ring indices are fixed and consecutive segments are straight-line code
-  auto march = [&](auto Nc) {
-    using std::integral_constant;
-    for (int p = k0 - 1;;) {
-      segment(p, integral_constant<int, 0>{}, integral_constant<int, 0>{}, Nc);
-      if (++p > k1) break;
-      segment(p, integral_constant<int, 1>{}, integral_constant<int, 1>{}, Nc);
-      if (++p > k1) break;
-      segment(p, integral_constant<int, 0>{}, integral_constant<int, 2>{}, Nc);
-      if (++p > k1) break;
-      segment(p, integral_constant<int, 1>{}, integral_constant<int, 0>{}, Nc);
-      if (++p > k1) break;
-      segment(p, integral_constant<int, 0>{}, integral_constant<int, 1>{}, Nc);
-      if (++p > k1) break;
-      segment(p, integral_constant<int, 1>{}, integral_constant<int, 2>{}, Nc);
-      if (++p > k1) break;
-    }
-  };
-  if (partials != nullptr)
-    march(std::true_type{});
-  else
-    march(std::false_type{});
-
-  if (partials != nullptr) {
-    const double tot = block_sum(nsum, red);
-    if (tid == 0)
-      for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = q == s0 ? tot : 0.0;
-  }
-}
-
 // Two heavy-ball iterations in one z-march (one load per block, periodic
 // boundaries): u^{n+1} from (u^n, u^{n-1}) and u^{n+2} from (u^{n+1}, u^n).
 // u^n and u^{n-1} are buffers parity and parity ^ 1; the results go to the
@@ -3115,46 +2494,6 @@ inline int grid_for(int64_t n, int block = 256) {
 template <typename T, int L, bool HI>
 void launch_step_occ(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts, int parity,
                      int first, double* partials, hipStream_t s, int nt, size_t lds) {
-  if constexpr (sizeof(T) == 4 && L == 1) {
-    if (ts.pf == 7 && !ts.walls) {  // u^n prefetched into LDS (FP32, one load per block)
-      if (nt <= 256) {
-        if (ts.pal)
-          hipLaunchKernelGGL((step_kernel_d<HI, true, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
-        else
-          hipLaunchKernelGGL((step_kernel_d<HI, false, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
-      } else {
-        if (ts.pal)
-          hipLaunchKernelGGL((step_kernel_d<HI, true, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
-        else
-          hipLaunchKernelGGL((step_kernel_d<HI, false, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
-      }
-      return;
-    }
-  }
-  if constexpr (sizeof(T) == 4 && L == 1) {
-    if (ts.pf == 8 && !ts.walls) {  // one barrier per plane (FP32, one load per block)
-      if (nt <= 256) {
-        if (ts.pal)
-          hipLaunchKernelGGL((step_kernel_e<HI, true, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
-        else
-          hipLaunchKernelGGL((step_kernel_e<HI, false, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
-      } else {
-        if (ts.pal)
-          hipLaunchKernelGGL((step_kernel_e<HI, true, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
-        else
-          hipLaunchKernelGGL((step_kernel_e<HI, false, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
-      }
-      return;
-    }
-  }
   if (ts.pf == 5) {
     const int ntc = (((ts.bx - 2) * (ts.by - 2) + 63) / 64) * 64;
     hipLaunchKernelGGL((step_kernel_c<T, HI>), dim3(nwork), dim3(ntc), 0, s, d_samples, d_work, nwork, ts.bx, ts.by,

@@ -278,14 +278,20 @@ def test_unrolled_march_matches(monkeypatch, tile):
     assert np.max(np.abs(Cr - Cq)) <= 1e-12 * np.abs(Cq).max()
 
 
-@pytest.mark.parametrize("n,fused", [(32, 1), (120, 1), (128, 0)])
-def test_automatic_load_fusion(n, fused):
-    """Loads run one after another exactly when one load's working set fits in the
-    Infinity Cache and all six do not (homogeneous images: no iterations needed)."""
+@pytest.mark.parametrize("n,fields,fused", [(32, True, 1), (120, True, 1), (128, True, 0), (208, True, 1),
+                                            (32, False, 0), (128, False, 0)])
+def test_automatic_load_fusion(n, fields, fused):
+    """With a phase image the loads run one after another (they share only the
+    1-byte phase id); with K and G fields they run one after another exactly when
+    one load's working set fits in the Infinity Cache and all six do not
+    (homogeneous images: no iterations needed)."""
     p = need_gpu()
     m = synth.homogeneous(n)
     with p.Context() as c:
-        c.set_phases(m.phase, m.K_tab, m.G_tab)
+        if fields:
+            c.set_material(*m.fields())
+        else:
+            c.set_phases(m.phase, m.K_tab, m.G_tab)
         C, info = c.solve(precision="mixed")
     assert info["stats"]["fused_loads"] == fused
     np.testing.assert_allclose(C, cf.c_iso(70.0, 32.0), rtol=1e-14, atol=1e-12)
