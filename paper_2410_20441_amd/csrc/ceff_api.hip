@@ -304,8 +304,8 @@ TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single) {
     const int n = std::sscanf(env, "%d,%d,%d,%d,%d,%d,%d", &bx, &by, &kc, &grp, &pf, &ord, &occ);
     if (n >= 2 && bx >= 3 && by >= 3 && ((bx * by + 63) / 64) * 64 <= 512 &&
         (grp == 1 || grp == 2 || grp == 3 || grp == 6))
-      return TileShape{bx, by, n >= 3 ? kc : 0, pf == 5 ? 1 : grp, pf >= 0 && pf <= 5 ? pf : 0, ord ? 1 : 0,
-                       occ ? 1 : 0, 0};
+      return TileShape{bx, by, n >= 3 ? kc : 0, pf == 5 || pf == 9 ? 1 : grp,
+                       (pf >= 0 && pf <= 5) || pf == 9 ? pf : 0, ord ? 1 : 0, occ ? 1 : 0, 0};
   }
   // Fastest shapes of the 191^3 sweeps, all with 12-plane chunks and the loads of a block staged
   // between one barrier pair per plane.  FP32, several loads per launch: 66 x 7 ghosted block
@@ -349,7 +349,7 @@ bool lookup_tuned(ceff_ctx* c, const std::string& key, TileShape& out) {
         8)
       continue;
     const int nt = ((t.bx * t.by + 63) / 64) * 64;
-    const bool valid = t.bx >= 3 && t.by >= 3 && nt <= 512 && t.kc >= 0 && t.pf >= 0 && t.pf <= 5 &&
+    const bool valid = t.bx >= 3 && t.by >= 3 && nt <= 512 && t.kc >= 0 && ((t.pf >= 0 && t.pf <= 5) || t.pf == 9) &&
                        (t.group == 1 || t.group == 2 || t.group == 3 || t.group == 6) && (t.order == 0 || t.order == 1) &&
                        (t.occ == 0 || t.occ == 1);
     if (valid && key == k) {  // the last valid entry of a key wins
@@ -414,7 +414,8 @@ struct Engine {
   bool single() const { return Js.size() == 1; }
   int slot_of(int J) const { return single() ? 0 : J; }
   int group() const {
-    return single() || ts.pf == 5 || ts.ortho || ts.walls || ts.tri ? 1 : (ts.group > 0 ? ts.group : kMaxLoads);
+    return single() || ts.pf == 5 || ts.pf == 9 || ts.ortho || ts.walls || ts.tri ? 1
+                                                                                   : (ts.group > 0 ? ts.group : kMaxLoads);
   }
 
   // Read the moduli from the phase image when there is one (one sample) and the
@@ -427,11 +428,13 @@ struct Engine {
     t.tri = in[0].t64 != nullptr ? 1 : 0;
     t.walls = in[0].walls;
     if (t.walls) t.pf = 3;  // the wall-boundary kernels are variant 3, one load per block
+    // variant 9 (x-neighbours across lanes) needs FP32 and rows that tile a wave
+    if (t.pf == 9 && (sizeof(T) == 8 || (t.bx != 16 && t.bx != 32 && t.bx != 64))) t.pf = 3;
     // the phase table is staged once per block from the first sample, so every
     // sample of the launch must use that same table
     bool shared = true;
     for (const SampleIn& s : in) shared = shared && s.phase != nullptr && s.ptab64 == in[0].ptab64;
-    t.pal = !t.ortho && !t.tri && shared && t.pf == 3 && !fields ? 1 : 0;
+    t.pal = !t.ortho && !t.tri && shared && (t.pf == 3 || t.pf == 9) && !fields ? 1 : 0;
     return t;
   }
 
@@ -685,7 +688,7 @@ struct Engine {
     for (const TileShape& t : cand) {
       std::vector<WorkItem> w;
       std::vector<int> rg, kcs;
-      const int grp = single() || t.pf == 5 ? 1 : t.group;
+      const int grp = single() || t.pf == 5 || t.pf == 9 ? 1 : t.group;
       STCK(build_work(t, grp, w, rg, kcs));
       DevBuf dw;
       HIPCK(c, dw.alloc(sizeof(WorkItem) * w.size()));

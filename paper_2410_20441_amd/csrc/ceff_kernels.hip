@@ -1022,6 +1022,215 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
   }
 }
 
+// ---- one iteration with x-neighbours across lanes (variant 9) ---------------
+//
+// step_kernel_b for one load per block and periodic isotropic FP32 cells, with the
+// block's rows exactly 16, 32 or 64 cells wide so that no row crosses a wave:
+// the x-neighbour of a thread is then the next or previous lane of its own wave,
+// and every x-neighbour value (u, 1/(8G), 1/H, sxx, sxy, the carried sxz) moves
+// between lanes with a DPP wave shift instead of a round trip through LDS.  Only
+// the y-neighbours go through LDS (9 reads and 8 writes per plane instead of 19
+// and 10).  The values and the arithmetic are those of step_kernel_b (lane 0 of
+// a wave and the first lane of each further row receive a value that no
+// interior thread consumes, as the clamped index does there).
+__device__ __forceinline__ float lane_prev(float v) {  // value of lane - 1 (lane 0: its own)
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v),
+                                                               0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_next(float v) {  // value of lane + 1 (lane 63: its own)
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v),
+                                                               0x130, 0xf, 0xf, false));
+}
+
+template <bool HI, bool PAL, int CAP>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, CAP), amdgpu_waves_per_eu(MinWaves<float, 1, HI>::value)))
+step_kernel_x(const SampleDesc<float>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
+              int by, int parity, int first, double* __restrict__ partials) {
+  using T = float;
+  // rows: 0-1 1/(8G) of two planes, 2 1/H, 3-5 ux, uy of plane k and uz of plane k+1, 6 syy, 7 sxy,
+  // 8 the carried syz
+  __shared__ __align__(16) T sL[9][CAP];
+  __shared__ CellCoef<T> tab[PAL ? 256 : 1];
+  __shared__ double red[16];
+  if constexpr (PAL) stage_coef_table(samples[0], tab);
+  const int nt = blockDim.x;
+  T* const sG[2] = {sL[0], sL[1]};
+  T* const sH = sL[2];
+  T* const sUx = sL[3];
+  T* const sUy = sL[4];
+  T* const sUz = sL[5];
+  T* const sSyy = sL[6];
+  T* const sSxy = sL[7];
+  T* const sSyz = sL[8];
+
+  const int tid = threadIdx.x;
+  const int tx = tid % bx, ty = tid / bx;
+  const int TX = bx - 2, TY = by - 2;
+  const int ym = ty > 0 ? tid - bx : tid;
+  const int yp = ty < by - 1 && tid + bx < nt ? tid + bx : tid;
+
+  const int w = blockIdx.x;  // one work item per block
+  if (w >= nwork) return;
+  const WorkItem wi = work[w];
+  if (wi.sample < 0) {
+    if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+    return;
+  }
+  const SampleDesc<T>& sd = samples[wi.sample];
+  const int s0 = wi.slot0;
+  if (!((sd.active >> s0) & 1u)) {
+    if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
+    return;
+  }
+  const int64_t nx = sd.nx, ny = sd.ny, N = sd.N, plane = nx * ny;
+  const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
+  const T mom = first ? T(0) : sd.mom;
+  const T sfac = first ? sd.sfac_first : sd.sfac;
+  const int64_t gi = (int64_t)wi.tx * TX + tx - 1, gj = (int64_t)wi.ty * TY + ty - 1;
+  const int64_t col = wrap_idx(gi, nx) + nx * wrap_idx(gj, ny);
+  const bool interior = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && gi < nx && gj < ny;
+  const int nz32 = (int)sd.nz;
+  const int k0 = wi.kz * sd.kc;
+  const int k1 = k0 + sd.kc < nz32 ? k0 + sd.kc : nz32;
+
+  const Moduli<T, PAL> mod(sd, tab);
+  const uint32_t col32 = (uint32_t)col, colb = (uint32_t)col * (uint32_t)sizeof(T);
+  const uint32_t pbytes = (uint32_t)(plane * (int64_t)sizeof(T));
+  const T* pcur = sd.u[parity][s0];
+  T* pold = sd.u[parity ^ 1][s0];
+  const T* pfrc = sd.force[s0];
+  const bool hasf = pfrc != nullptr;
+  T E[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) E[q] = sd.E[s0][q];
+  auto ldu = [&](int c, int64_t pk) -> T { return PlaneBuf(pcur + (c * N + pk), pbytes).template ld<T>(colb); };
+  auto ldo_ = [&](int c, int64_t pk) -> T { return PlaneBuf(pold + (c * N + pk), pbytes).template ld<T>(colb); };
+  auto ldf = [&](int c, int64_t pk) -> T { return PlaneBuf(pfrc + (c * N + pk), pbytes).template ld<T>(colb); };
+  auto sto_ = [&](int c, int64_t pk, T v) { PlaneBuf(pold + (c * N + pk), pbytes).st(colb, v); };
+
+  T Ux[2], Uy[2], Uz[2], Szz[2], Sxz[2], Syz[2], iHh[2];
+  CellCoef<T> Cc[2];
+  double nsum = 0.0;
+  {
+    const int kw = k0 - 1 < 0 ? k0 - 1 + nz32 : k0 - 1;
+    const int64_t po = plane * kw;
+    Ux[0] = ldu(0, po);
+    Uy[0] = ldu(1, po);
+    Uz[0] = ldu(2, po);
+    Szz[1] = Sxz[1] = Syz[1] = T(0);
+    Cc[0] = mod.coef(mod.load(po, col32, colb));
+    iHh[1] = T(1);
+    sG[0][tid] = Cc[0].iG8;
+  }
+
+  auto plane_step = [&](int k, auto Pc, auto Nc) {
+    constexpr int P = decltype(Pc)::value;
+    constexpr int Q = 1 - P;
+    constexpr bool NORM = decltype(Nc)::value;
+    const int kw = k < 0 ? k + nz32 : k;
+    const int kn = k + 1 >= nz32 ? k + 1 - nz32 : k + 1;
+    const int64_t pc = plane * kw, pn = plane * kn;
+    const bool face = k >= k0 && interior;
+    const auto mr = mod.load(pn, col32, colb);
+    T uo0, uo1, uo2, f0, f1, f2;
+    Ux[Q] = ldu(0, pn);
+    Uy[Q] = ldu(1, pn);
+    Uz[Q] = ldu(2, pn);
+    if (face) {
+      if (!first) {
+        uo0 = ldo_(0, pc);
+        uo1 = ldo_(1, pc);
+        uo2 = ldo_(2, pc);
+      }
+      if (hasf) {
+        f0 = ldf(0, pc);
+        f1 = ldf(1, pc);
+        f2 = ldf(2, pc);
+      }
+    }
+    T* gk = sG[P];
+    T* gn = sG[Q];
+    Cc[Q] = mod.coef(mr);
+    gn[tid] = Cc[Q].iG8;
+    iHh[P] = Cc[P].iH;
+    sH[tid] = iHh[P];
+    sUx[tid] = Ux[P];
+    sUy[tid] = Uy[P];
+    sUz[tid] = Uz[Q];
+    __syncthreads();
+    const T lam = Cc[P].lam;
+    const T twoG = Cc[P].twoG;
+    const T ux = Ux[P], uy = Uy[P], uz = Uz[P];
+    const T unx = Ux[Q], uny = Uy[Q], unz = Uz[Q];
+    // own values from registers, x-neighbours across lanes, y-neighbours from LDS
+    const T ik = Cc[P].iG8, ikx = lane_prev(ik), iky = gk[ym];
+    const T in = Cc[Q].iG8, inx = lane_prev(in), iny = gn[ym];
+    const T G2xy = recip(lane_prev(iky) + iky + ikx + ik);
+    const T G2xz = recip(ikx + ik + inx + in);
+    const T G2yz = recip(iky + ik + iny + in);
+    const T sfx = sfac * tmin(lane_prev(iHh[P]), iHh[P]);
+    const T sfy = sfac * tmin(sH[ym], iHh[P]);
+    const T sfz = sfac * tmin(iHh[Q], iHh[P]);
+    const T exx = E[0] + (lane_next(ux) - ux) * rhx;
+    const T eyy = E[1] + (sUy[yp] - uy) * rhy;
+    const T ezz = E[2] + (unz - uz) * rhz;
+    const T th = exx + eyy + ezz;
+    const T sxx = lam * th + twoG * exx;
+    const T syy = lam * th + twoG * eyy;
+    const T szz = lam * th + twoG * ezz;
+    const T sxy = G2xy * (E[5] + T(0.5) * ((ux - sUx[ym]) * rhy + (uy - lane_prev(uy)) * rhx));
+    const T sxz_n = G2xz * (E[4] + T(0.5) * ((unx - ux) * rhz + (unz - lane_prev(unz)) * rhx));
+    const T syz_n = G2yz * (E[3] + T(0.5) * ((uny - uy) * rhz + (unz - sUz[ym]) * rhy));
+    sSyy[tid] = syy;
+    sSxy[tid] = sxy;
+    sSyz[tid] = Syz[Q];
+    // the x-neighbours' stresses, across lanes (no barrier needed for these)
+    const T sxx_m = lane_prev(sxx), sxy_p = lane_next(sxy), sxz_p = lane_next(Sxz[Q]);
+    __syncthreads();
+    if (face) {
+      const T sxz_c = Sxz[Q], syz_c = Syz[Q];
+      T rx = (sxx - sxx_m) * rhx + (sSxy[yp] - sxy) * rhy + (sxz_n - sxz_c) * rhz;
+      T ry = (sxy_p - sxy) * rhx + (syy - sSyy[ym]) * rhy + (syz_n - syz_c) * rhz;
+      T rz = (sxz_p - sxz_c) * rhx + (sSyz[yp] - syz_c) * rhy + (szz - Szz[Q]) * rhz;
+      if (hasf) {
+        rx += f0;
+        ry += f1;
+        rz += f2;
+      }
+      if (NORM) nsum += (double)rx * (double)rx + (double)ry * (double)ry + (double)rz * (double)rz;
+      if (first) {  // no momentum in the start-up step
+        sto_(0, pc, ux + sfx * rx);
+        sto_(1, pc, uy + sfy * ry);
+        sto_(2, pc, uz + sfz * rz);
+      } else {
+        sto_(0, pc, ux + mom * (ux - uo0) + sfx * rx);
+        sto_(1, pc, uy + mom * (uy - uo1) + sfy * ry);
+        sto_(2, pc, uz + mom * (uz - uo2) + sfz * rz);
+      }
+    }
+    Szz[P] = szz;
+    Sxz[P] = sxz_n;
+    Syz[P] = syz_n;
+  };
+
+  auto march = [&](auto Nc) {
+    for (int k = k0 - 1; k < k1; k += 2) {
+      plane_step(k, std::integral_constant<int, 0>{}, Nc);
+      if (k + 1 < k1) plane_step(k + 1, std::integral_constant<int, 1>{}, Nc);
+    }
+  };
+  if (partials != nullptr)
+    march(std::true_type{});
+  else
+    march(std::false_type{});
+
+  if (partials != nullptr) {
+    const double tot = block_sum(nsum, red);
+    if (tid == 0)
+      for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = q == s0 ? tot : 0.0;
+  }
+}
+
 // Two heavy-ball iterations in one z-march (one load per block, periodic
 // boundaries): u^{n+1} from (u^n, u^{n-1}) and u^{n+2} from (u^{n+1}, u^n).
 // u^n and u^{n-1} are buffers parity and parity ^ 1; the results go to the
@@ -2494,6 +2703,26 @@ inline int grid_for(int64_t n, int block = 256) {
 template <typename T, int L, bool HI>
 void launch_step_occ(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts, int parity,
                      int first, double* partials, hipStream_t s, int nt, size_t lds) {
+  if constexpr (sizeof(T) == 4 && L == 1) {
+    if (ts.pf == 9 && !ts.walls) {  // x-neighbours across lanes (FP32, one load per block, bx 16, 32 or 64)
+      if (nt <= 256) {
+        if (ts.pal)
+          hipLaunchKernelGGL((step_kernel_x<HI, true, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
+                             ts.bx, ts.by, parity, first, partials);
+        else
+          hipLaunchKernelGGL((step_kernel_x<HI, false, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
+                             ts.bx, ts.by, parity, first, partials);
+      } else {
+        if (ts.pal)
+          hipLaunchKernelGGL((step_kernel_x<HI, true, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
+                             ts.bx, ts.by, parity, first, partials);
+        else
+          hipLaunchKernelGGL((step_kernel_x<HI, false, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
+                             ts.bx, ts.by, parity, first, partials);
+      }
+      return;
+    }
+  }
   if (ts.pf == 5) {
     const int ntc = (((ts.bx - 2) * (ts.by - 2) + 63) / 64) * 64;
     hipLaunchKernelGGL((step_kernel_c<T, HI>), dim3(nwork), dim3(ntc), 0, s, d_samples, d_work, nwork, ts.bx, ts.by,
