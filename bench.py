@@ -27,22 +27,22 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the iteration kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_trace_and_counters.md and
 # profiles/step_kernel_spheres480_trace_and_counters.md), valid only for the kernel source they were taken on.
-MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "125317e7c5ec25d5", "bytes_per_launch": 3.304952e+08,
+MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "22e568951d4187a4", "bytes_per_launch": 3.184297e+08,
                     # (loads per block, kernel variant, loads fused, moduli from the phase image, high occupancy)
-                    "launch_signature": (1, 3, 0, 1, 1),
+                    "launch_signature": (1, 9, 0, 1, 1),
                     # mean algorithmic bytes per launch of the profiled solve: fixes its mix of
                     # macroscopic-strain and body-force launches
                     "algorithmic_bytes_per_launch": 3.009393e+08,
-                    "launch": "step_kernel_b<float,1,PAL,high occupancy>, mean over all launches of a full solve"}
+                    "launch": "step_kernel_x<float,1,PAL,high occupancy>, mean over all launches of a full solve"}
 # the same for the HBM-resident measurement (480^3, one load, 200 iterations without body force; the mean over
 # its launches after the first, which reads no u^{n-1})
-MEASURED_TRAFFIC_HBM = {"ceff_kernels_sha256_prefix": "125317e7c5ec25d5", "n": 480, "bytes_per_launch": 4.415066e+09,
-                        "algorithmic_bytes_per_launch": 4.091904e+09, "launch_shape": "66x7x48 variant 3"}
+MEASURED_TRAFFIC_HBM = {"ceff_kernels_sha256_prefix": "22e568951d4187a4", "n": 480, "bytes_per_launch": 4.356568e+09,
+                        "algorithmic_bytes_per_launch": 4.091904e+09, "launch_shape": "64x8x32 variant 9"}
 
 
 # iteration-kernel variant (ceff_stats.tile_variant) -> kernel name
 VARIANT_KERNEL = {0: "step_kernel", 1: "step_kernel", 2: "step_kernel_u2", 3: "step_kernel_b", 4: "step_kernel_p3",
-                  5: "step_kernel_c", 6: "step_kernel_t"}
+                  5: "step_kernel_c", 6: "step_kernel_t", 9: "step_kernel_x"}
 
 
 # Swept Strouhal numbers per workload family (six loads, mixed precision, rtol 1e-8):

@@ -307,11 +307,23 @@ TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single) {
       return TileShape{bx, by, n >= 3 ? kc : 0, pf == 5 || pf == 9 ? 1 : grp,
                        (pf >= 0 && pf <= 5) || pf == 9 ? pf : 0, ord ? 1 : 0, occ ? 1 : 0, 0};
   }
-  // Fastest shapes of the 191^3 sweeps, all with 12-plane chunks and the loads of a block staged
-  // between one barrier pair per plane.  FP32, several loads per launch: 66 x 7 ghosted block
-  // (64 x 5 interior), two loads per block.  FP32, one load: 18 x 14 (16 x 12 interior), the
-  // high-occupancy build (0.0567-0.0570 ms per launch against 0.0594-0.0596 for the other).
-  // FP64: 34 x 14 (32 x 12 interior), one load per block.
+  // FP32, one load per launch: variant 9 (x-neighbours across lanes), 32 x 8 ghosted block
+  // (30 x 6 interior, rows within a wave) with 24-plane chunks, high-occupancy build: 0.0498 ms per
+  // launch at 191^3 against 0.0569 for variant 3's best (18 x 14, 12 planes).
+  if (single && !fp64) {
+    t.bx = nx + 2 <= 16 ? 16 : 32;
+    t.by = (int)std::min<int64_t>(ny + 2, 8);
+    t.kc = 24;
+    t.group = 1;
+    t.pf = 9;
+    t.order = 1;
+    t.occ = 1;
+    return t;
+  }
+  // Fastest shapes of the 191^3 sweeps for the other cases, all with 12-plane chunks and the loads
+  // of a block staged between one barrier pair per plane.  FP32, several loads per launch: 66 x 7
+  // ghosted block (64 x 5 interior), two loads per block.  FP64: 34 x 14 (32 x 12 interior), one load
+  // per block.
   t.bx = (int)std::min<int64_t>(nx + 2, fp64 ? 34 : (single ? 18 : 66));
   t.by = (int)std::min<int64_t>(ny + 2, fp64 || single ? 14 : 7);
   t.kc = 12;
@@ -612,20 +624,32 @@ struct Engine {
   // Measured on a 703^3 sphere pack with the phase table: one load per launch,
   // 18 x 14 with 12-plane chunks 3.84 ms, 66 x 7 with 48-plane chunks and the
   // high-occupancy variant 3.11 ms; six loads fused, two per block, 66 x 7 with
-  // 12-plane chunks 3.19 ms and with 48-plane chunks 3.08 ms per load.  Applied
-  // to single-image FP32 solves with the phase table whose grid still yields
-  // at least 2048 (tile, chunk) items at that shape.
+  // 12-plane chunks 3.19 ms and with 48-plane chunks 3.08 ms per load.  One load
+  // per launch in variant 9 at 480^3: 64 x 8 blocks with 32-plane chunks
+  // 0.903 ms, with 48-plane chunks 0.960 ms, against 1.000 ms for variant 3 at
+  // 66 x 7 x 48.  Applied to single-image FP32 solves with the phase table whose
+  // grid still yields at least 2048 (tile, chunk) items at that shape.
   void large_grid_shape() {
     if (sizeof(T) != 4 || in.size() != 1 || !ts.pal || ts.ortho || ts.walls || ts.tri) return;
     const SampleIn& s = in[0];
     const double ws = (double)s.nx * s.ny * s.nz * (6.0 * sizeof(T) * (double)Js.size() + 1.0);
     if (ws <= kInfinityCacheBytes) return;
+    if (single()) {
+      const int64_t items = ((s.nx + 61) / 62) * ((s.ny + 5) / 6) * ((s.nz + 31) / 32);
+      if (items < 2048) return;
+      ts.bx = 64;
+      ts.by = 8;
+      ts.kc = 32;
+      ts.pf = 9;
+      ts.occ = 1;
+      return;
+    }
     const int64_t items = ((s.nx + 63) / 64) * ((s.ny + 4) / 5) * ((s.nz + 47) / 48);
     if (items < 2048) return;
     ts.bx = 66;
     ts.by = 7;
     ts.kc = 48;
-    ts.occ = single() ? 1 : 0;
+    ts.occ = 0;
   }
 
   // Pick the launch shape: block extent, loads per block and prefetch.  With
@@ -678,6 +702,15 @@ struct Engine {
                 cand.push_back(t);
               }
       }
+    // variant 9 (one load per block, FP32): rows of 16, 32 or 64 cells
+    if (single() && sizeof(T) == 4 && !ts.walls && !ts.ortho && !ts.tri)
+      for (int bx : {16, 32, 64})
+        for (int by : {4, 6, 8, 12, 16})
+          for (int kc : {12, 24, 32, 48})
+            for (int occ = 0; occ < 2; ++occ) {
+              if (bx * by > 512 || bx * by < 128 || bx > in[0].nx + 2 + 64 || by > in[0].ny + 2 + 8) continue;
+              cand.push_back(with_moduli(TileShape{bx, by, kc, 1, 9, 1, occ, 0}));
+            }
     float best = 1e30f;
     TileShape bt = ts;
     std::vector<unsigned> saved(in.size());

@@ -300,8 +300,9 @@ def test_automatic_load_fusion(n, fields, fused):
 @pytest.mark.parametrize("fuse", [False, True])
 def test_large_grid_launch_shape(monkeypatch, fuse):
     """Beyond the Infinity Cache (a 320^3 pore pack: 0.8 GB for one load) the library
-    switches to 66 x 7 blocks with 48-plane chunks (and the high-occupancy variant
-    for one load per block); the iterate is the one of the cache-resident shape."""
+    switches one load per launch to 64 x 8 blocks of variant 9 with 32-plane chunks,
+    and fused loads to 66 x 7 blocks with 48-plane chunks; the iterate is the one of
+    the cache-resident shape."""
     p = need_gpu()
     m = synth.random_spheres(320, 0.10, 0x320)
     monkeypatch.delenv("CEFF_TILE", raising=False)
@@ -312,7 +313,8 @@ def test_large_grid_launch_shape(monkeypatch, fuse):
         c.set_phases(m.phase, m.K_tab, m.G_tab)
         C, info = c.solve(**opts)
         st = info["stats"]
-        assert (st["tile_bx"], st["tile_by"], st["tile_kc"]) == (66, 7, 48)
+        assert (st["tile_bx"], st["tile_by"], st["tile_kc"], st["tile_variant"]) == \
+            ((66, 7, 48, 3) if fuse else (64, 8, 32, 9))
         assert st["tile_group"] == (2 if fuse else 1)
         monkeypatch.setenv("CEFF_TILE", "18,14,12,1,3,1,0" if not fuse else "66,7,12,2,3,1,0")
         C2, info2 = c.solve(**opts)
