@@ -1024,7 +1024,7 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
 
 // ---- one iteration with x-neighbours across lanes (variant 9) ---------------
 //
-// step_kernel_b for one load per block and periodic isotropic FP32 cells, with the
+// step_kernel_b for one load per block and periodic isotropic cells, with the
 // block's rows exactly 16, 32 or 64 cells wide so that no row crosses a wave:
 // the x-neighbour of a thread is then the next or previous lane of its own wave,
 // and every x-neighbour value (u, 1/(8G), 1/H, sxx, sxy, the carried sxz) moves
@@ -1041,12 +1041,25 @@ __device__ __forceinline__ float lane_next(float v) {  // value of lane + 1 (lan
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v),
                                                                0x130, 0xf, 0xf, false));
 }
+__device__ __forceinline__ double lane_prev(double v) {  // both halves moved by one lane
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = (int)(uint32_t)b, hi = (int)(uint32_t)(b >> 32);
+  const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
+  const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = (int)(uint32_t)b, hi = (int)(uint32_t)(b >> 32);
+  const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
+  const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
+}
 
-template <bool HI, bool PAL, int CAP>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64, CAP), amdgpu_waves_per_eu(MinWaves<float, 1, HI>::value)))
-step_kernel_x(const SampleDesc<float>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
+template <typename T, bool HI, bool PAL, int CAP>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, CAP), amdgpu_waves_per_eu(MinWaves<T, 1, HI>::value)))
+step_kernel_x(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
               int by, int parity, int first, double* __restrict__ partials) {
-  using T = float;
   // rows: 0-1 1/(8G) of two planes, 2 1/H, 3-5 ux, uy of plane k and uz of plane k+1, 6 syy, 7 sxy,
   // 8 the carried syz
   __shared__ __align__(16) T sL[9][CAP];
@@ -2703,22 +2716,22 @@ inline int grid_for(int64_t n, int block = 256) {
 template <typename T, int L, bool HI>
 void launch_step_occ(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts, int parity,
                      int first, double* partials, hipStream_t s, int nt, size_t lds) {
-  if constexpr (sizeof(T) == 4 && L == 1) {
-    if (ts.pf == 9 && !ts.walls) {  // x-neighbours across lanes (FP32, one load per block, bx 16, 32 or 64)
+  if constexpr (L == 1) {
+    if (ts.pf == 9 && !ts.walls) {  // x-neighbours across lanes (one load per block, bx 16, 32 or 64)
       if (nt <= 256) {
         if (ts.pal)
-          hipLaunchKernelGGL((step_kernel_x<HI, true, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
+          hipLaunchKernelGGL((step_kernel_x<T, HI, true, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
                              ts.bx, ts.by, parity, first, partials);
         else
-          hipLaunchKernelGGL((step_kernel_x<HI, false, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
+          hipLaunchKernelGGL((step_kernel_x<T, HI, false, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work,
+                             nwork, ts.bx, ts.by, parity, first, partials);
       } else {
         if (ts.pal)
-          hipLaunchKernelGGL((step_kernel_x<HI, true, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
+          hipLaunchKernelGGL((step_kernel_x<T, HI, true, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
                              ts.bx, ts.by, parity, first, partials);
         else
-          hipLaunchKernelGGL((step_kernel_x<HI, false, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
+          hipLaunchKernelGGL((step_kernel_x<T, HI, false, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work,
+                             nwork, ts.bx, ts.by, parity, first, partials);
       }
       return;
     }

@@ -8,7 +8,8 @@ may contract the update's multiply-adds differently).  Checked after 1, 2 and
 11 steps on grids with ragged tails in x and y, z-chunks of 1 to 12 planes,
 grids 2 to 4 planes thick, blocks with padding rows, all three row widths, moduli
 from K and G fields and from a phase image, and against the oracle's iteration;
-and a full mixed-precision solve (folds, body forces, residual norms)."""
+and full solves in mixed precision (folds, body forces, residual norms) and in
+FP64, where each double crosses lanes as two 32-bit shifts."""
 import numpy as np
 import pytest
 
@@ -28,7 +29,7 @@ CASES = [  # (nx, ny, nz), seed, tile "bx,by,kc"
 ]
 
 
-def _steps(p, monkeypatch, tile, variant, K=None, G=None, m=None, J=1, n=(1, 2, 11)):
+def _steps(p, monkeypatch, tile, variant, K=None, G=None, m=None, J=1, n=(1, 2, 11), prec="mixed"):
     monkeypatch.setenv("CEFF_TILE", f"{tile},1,{variant},1,1")
     out = {}
     with p.Context() as c:
@@ -37,7 +38,7 @@ def _steps(p, monkeypatch, tile, variant, K=None, G=None, m=None, J=1, n=(1, 2, 
         else:
             c.set_material(K, G)
         for k in n:
-            out[k] = c.apt_steps(J, k, "mixed", courant=0.95, strouhal=3.0)
+            out[k] = c.apt_steps(J, k, prec, courant=0.95, strouhal=3.0)
         assert c.stats()["tile_variant"] == variant
     return out
 
@@ -59,6 +60,24 @@ def test_lanes_steps_equal_variant3(monkeypatch, shape, seed, tile):
     assert np.abs(b[11][0] - ref).max() <= 2e-5 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("shape,seed,tile", CASES[::2])
+def test_lanes_fp64_steps_equal_variant3(monkeypatch, shape, seed, tile):
+    """The FP64 build moves each double as two 32-bit lane shifts."""
+    p = need_gpu()
+    K, G = synth.random_fields(shape[::-1], seed + 10, lo=(2.0, 1e-3), hi=(90.0, 45.0))
+    announce("variant 9 vs 3, fp64", shape, tile)
+    a = _steps(p, monkeypatch, tile, 3, K=K, G=G, prec="fp64")
+    b = _steps(p, monkeypatch, tile, 9, K=K, G=G, prec="fp64")
+    for k in a:
+        for x, y in zip(a[k], b[k]):
+            sc = float(np.abs(x).max())
+            d = float(np.abs(x - y).max() / sc) if sc > 0 else float(np.abs(y).max())
+            print(f"  steps {k}: max rel diff {d:.2e}{' (bitwise)' if np.array_equal(x, y) else ''}", flush=True)
+            assert d <= 1e-13, (k, d)
+    ref, _ = oracle.apt_disp(1, 11, 0.95, 3.0, K=K, G=G)
+    assert np.abs(b[11][0] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("shape,seed,tile", CASES[:3])
 def test_lanes_phase_image_equals_variant3(monkeypatch, shape, seed, tile):
     p = need_gpu()
@@ -75,8 +94,8 @@ def test_lanes_phase_image_equals_variant3(monkeypatch, shape, seed, tile):
                 assert np.abs(x - y).max() <= 1e-6 * max(np.abs(x).max(), 1e-30), (J, k)
 
 
-@pytest.mark.parametrize("phases", [False, True])
-def test_lanes_solve_equals_variant3_solve(monkeypatch, phases):
+@pytest.mark.parametrize("phases,prec", [(False, "mixed"), (True, "mixed"), (True, "fp64")])
+def test_lanes_solve_equals_variant3_solve(monkeypatch, phases, prec):
     p = need_gpu()
     m = synth.random_spheres(72, 0.10, 0x7B)
     K, G = m.fields()
@@ -88,10 +107,10 @@ def test_lanes_solve_equals_variant3_solve(monkeypatch, phases):
                 c.set_phases(m.phase, m.K_tab, m.G_tab)
             else:
                 c.set_material(K, G)
-            res[v] = c.solve(precision="mixed", rtol=1e-8, loads=(0, 3), fuse_loads=False)
+            res[v] = c.solve(precision=prec, rtol=1e-8, loads=(0, 3), fuse_loads=False)
             assert res[v][1]["stats"]["tile_variant"] == v
     (C3, i3), (C9, i9) = res[3], res[9]
-    announce("variant 9 solve", phases, i3["iters"].tolist(), i9["iters"].tolist(),
+    announce("variant 9 solve", phases, prec, i3["iters"].tolist(), i9["iters"].tolist(),
              matrix_rel(C9[:, [0, 3]], C3[:, [0, 3]]))
     assert i9["status"] == 0
     assert matrix_rel(C9[:, [0, 3]], C3[:, [0, 3]]) <= 1e-9

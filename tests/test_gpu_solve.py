@@ -129,13 +129,14 @@ def test_batch_mixed_phases_and_sizes():
 
 
 def test_batch_block_spans_largest_sample():
-    """The default block of a batch is sized by its largest sample, not its first."""
+    """The default block of a batch is sized by its largest sample, not its first
+    (32-cell rows for the 70-wide sample; the 8-wide first sample alone gives 16)."""
     p = need_gpu()
     samples = [synth.random_fields(s, 60 + i, lo=(2.0, 1.0), hi=(90.0, 45.0))
                for i, s in enumerate([(8, 8, 8), (70, 9, 6)])]
     announce("batch block extent")
     C, it, info = p.solve_batch(samples, precision="mixed", rtol=1e-9)
-    assert info["stats"]["tile_bx"] == 66 and info["stats"]["tile_by"] == 7
+    assert info["stats"]["tile_bx"] == 32 and info["stats"]["tile_by"] == 8
     for s, (K, G) in enumerate(samples):
         Co, _ = oracle.ceff(K, G, rtol=1e-12)
         assert matrix_rel(C[s], Co) <= 1e-6, s
