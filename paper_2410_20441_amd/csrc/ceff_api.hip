@@ -304,8 +304,8 @@ TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single, bool batc
     const int n = std::sscanf(env, "%d,%d,%d,%d,%d,%d,%d", &bx, &by, &kc, &grp, &pf, &ord, &occ);
     if (n >= 2 && bx >= 3 && by >= 3 && ((bx * by + 63) / 64) * 64 <= 512 &&
         (grp == 1 || grp == 2 || grp == 3 || grp == 6))
-      return TileShape{bx, by, n >= 3 ? kc : 0, pf == 5 || pf == 9 || pf == 10 ? 1 : grp,
-                       (pf >= 0 && pf <= 5) || pf == 9 || pf == 10 ? pf : 0, ord ? 1 : 0, occ ? 1 : 0, 0};
+      return TileShape{bx, by, n >= 3 ? kc : 0, pf == 5 || pf == 9 ? 1 : grp,
+                       (pf >= 0 && pf <= 5) || pf == 9 ? pf : 0, ord ? 1 : 0, occ ? 1 : 0, 0};
   }
   // FP32, one load per launch: variant 9 (x-neighbours across lanes), 32 x 8 ghosted block
   // (30 x 6 interior, rows within a wave) with 24-plane chunks, high-occupancy build: 0.0498 ms per
@@ -363,8 +363,7 @@ bool lookup_tuned(ceff_ctx* c, const std::string& key, TileShape& out) {
         8)
       continue;
     const int nt = ((t.bx * t.by + 63) / 64) * 64;
-    const bool valid = t.bx >= 3 && t.by >= 3 && nt <= 512 && t.kc >= 0 &&
-                       ((t.pf >= 0 && t.pf <= 5) || t.pf == 9 || t.pf == 10) &&
+    const bool valid = t.bx >= 3 && t.by >= 3 && nt <= 512 && t.kc >= 0 && ((t.pf >= 0 && t.pf <= 5) || t.pf == 9) &&
                        (t.group == 1 || t.group == 2 || t.group == 3 || t.group == 6) && (t.order == 0 || t.order == 1) &&
                        (t.occ == 0 || t.occ == 1);
     if (valid && key == k) {  // the last valid entry of a key wins
@@ -395,7 +394,6 @@ struct Engine {
   bool mixed;
   int Lk;                       // 1: one load (slot 0); otherwise slot J holds load J
   std::vector<int> Js;          // requested loads
-  bool one_row = false;         // the iteration work list also serves the one-row residual kernel
   TileShape ts{};
   // device
   std::vector<std::array<DevBuf, 4 * kMaxLoads>> ubuf;  // per sample: u[b][slot] at index b*6+slot
@@ -430,7 +428,7 @@ struct Engine {
   bool single() const { return Js.size() == 1; }
   int slot_of(int J) const { return single() ? 0 : J; }
   int group() const {
-    return single() || ts.pf == 5 || ts.pf == 9 || ts.pf == 10 || ts.ortho || ts.walls || ts.tri ? 1
+    return single() || ts.pf == 5 || ts.pf == 9 || ts.ortho || ts.walls || ts.tri ? 1
                                                                                    : (ts.group > 0 ? ts.group : kMaxLoads);
   }
 
@@ -444,13 +442,13 @@ struct Engine {
     t.tri = in[0].t64 != nullptr ? 1 : 0;
     t.walls = in[0].walls;
     if (t.walls) t.pf = 3;  // the wall-boundary kernels are variant 3, one load per block
-    // variants 9 and 10 (x-neighbours across lanes) need rows that tile a wave
-    if ((t.pf == 9 || t.pf == 10) && t.bx != 16 && t.bx != 32 && t.bx != 64) t.pf = 3;
+    // variant 9 (x-neighbours across lanes) needs rows that tile a wave
+    if (t.pf == 9 && t.bx != 16 && t.bx != 32 && t.bx != 64) t.pf = 3;
     // the phase table is staged once per block from the first sample, so every
     // sample of the launch must use that same table
     bool shared = true;
     for (const SampleIn& s : in) shared = shared && s.phase != nullptr && s.ptab64 == in[0].ptab64;
-    t.pal = !t.ortho && !t.tri && shared && (t.pf == 3 || t.pf == 9 || t.pf == 10) && !fields ? 1 : 0;
+    t.pal = !t.ortho && !t.tri && shared && (t.pf == 3 || t.pf == 9) && !fields ? 1 : 0;
     return t;
   }
 
@@ -478,13 +476,12 @@ struct Engine {
     const int G = (int)slots0.size();
     int64_t total_xy = 0;
     const int gh = t.tb ? 2 : 1;  // ghost ring of the tiles
-    const int cy = t.pf == 10 && !t.tb ? 2 * t.by : t.by;  // cell rows of a block (variant 10: two per thread)
     for (auto& s : in)
-      total_xy += ((s.nx + t.bx - 2 * gh - 1) / (t.bx - 2 * gh)) * ((s.ny + cy - 2 * gh - 1) / (cy - 2 * gh));
+      total_xy += ((s.nx + t.bx - 2 * gh - 1) / (t.bx - 2 * gh)) * ((s.ny + t.by - 2 * gh - 1) / (t.by - 2 * gh));
     for (size_t si = 0; si < in.size(); ++si) {
       const auto& s = in[si];
       const int tx = (int)((s.nx + t.bx - 2 * gh - 1) / (t.bx - 2 * gh));
-      const int ty = (int)((s.ny + cy - 2 * gh - 1) / (cy - 2 * gh));
+      const int ty = (int)((s.ny + t.by - 2 * gh - 1) / (t.by - 2 * gh));
       int kc;
       if (t.kc > 0) {
         kc = t.kc;
@@ -707,18 +704,15 @@ struct Engine {
                 cand.push_back(t);
               }
       }
-    // variants 9 and 10 (one load per block): rows of 16, 32 or 64 cells; variant 10 covers 2 * by
-    // cell rows
+    // variant 9 (one load per block): rows of 16, 32 or 64 cells
     if (single() && !ts.walls && !ts.ortho && !ts.tri)
-      for (int pf : {9, 10})
-        for (int bx : {16, 32, 64})
-          for (int by : {4, 6, 8, 12, 16})
-            for (int kc : {12, 24, 32, 48})
-              for (int occ = 0; occ < 2; ++occ) {
-                const int rows = pf == 10 ? 2 * by : by;
-                if (bx * by > 512 || bx * by < 128 || bx > in[0].nx + 2 + 64 || rows > in[0].ny + 2 + 8) continue;
-                cand.push_back(with_moduli(TileShape{bx, by, kc, 1, pf, 1, occ, 0}));
-              }
+      for (int bx : {16, 32, 64})
+        for (int by : {4, 6, 8, 12, 16})
+          for (int kc : {12, 24, 32, 48})
+            for (int occ = 0; occ < 2; ++occ) {
+              if (bx * by > 512 || bx * by < 128 || bx > in[0].nx + 2 + 64 || by > in[0].ny + 2 + 8) continue;
+              cand.push_back(with_moduli(TileShape{bx, by, kc, 1, 9, 1, occ, 0}));
+            }
     float best = 1e30f;
     TileShape bt = ts;
     std::vector<unsigned> saved(in.size());
@@ -729,7 +723,7 @@ struct Engine {
     for (const TileShape& t : cand) {
       std::vector<WorkItem> w;
       std::vector<int> rg, kcs;
-      const int grp = single() || t.pf == 5 || t.pf == 9 || t.pf == 10 ? 1 : t.group;
+      const int grp = single() || t.pf == 5 || t.pf == 9 ? 1 : t.group;
       STCK(build_work(t, grp, w, rg, kcs));
       DevBuf dw;
       HIPCK(c, dw.alloc(sizeof(WorkItem) * w.size()));
@@ -872,7 +866,6 @@ struct Engine {
     HIPCK(c, d_in.alloc(sizeof(SampleDesc<T>) * ns));
     HIPCK(c, d_out.alloc(sizeof(SampleDesc<double>) * ns));
     STCK(tune());
-    if (one_row && ts.pf == 10) ts.pf = 9;
     std::vector<int> kcs, kcs_o;
     ts.tb = nbuf == 4 ? 1 : 0;  // pairs only where the second buffer pair exists
     STCK(build_work(ts, group(), work, ranges, kcs));
@@ -890,7 +883,6 @@ struct Engine {
     TileShape to = ts;
     to.kc = 0;
     to.tb = 0;  // the residual kernel tiles with a one-cell ghost ring
-    if (to.pf == 10) to.pf = 3;  // and one cell row per thread
     STCK(build_work(to, single() || ts.ortho || ts.walls ? 1 : kMaxLoads, work_o, ranges_o, kcs_o));
     for (int si = 0; si < ns; ++si) {
       h_in[si].kc = kcs[si];
@@ -2042,7 +2034,6 @@ ceff_status ceff_residual(ceff_ctx* c, int J, int precision, const double* u, do
     e.mixed = false;
     e.Lk = 1;
     e.Js = {J};
-    e.one_row = true;  // the residual launch below tiles the iteration work list
     STCK(e.setup());
     DevBuf d64, r, rp, part, nrm;
     HIPCK(c, d64.alloc(sizeof(double) * 3 * N));

@@ -1244,266 +1244,6 @@ step_kernel_x(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
   }
 }
 
-// ---- one iteration, two cell rows per thread (variant 10) ------------------
-//
-// Variant 9 with every thread holding two consecutive cells of its column in y:
-// a block of bx x by threads covers bx x 2*by cells (rows 2*ty and 2*ty + 1 of
-// thread row ty).  The y-neighbour inside a pair is in the thread's own
-// registers; only a pair's outer cells are exchanged through LDS (the upper cell
-// for the thread row above, the lower cell for the one below).  Per cell that
-// halves the LDS traffic and the per-plane scalar set-up (buffer descriptors,
-// plane offsets), and the two ghost rows are 2 of 2*by rows instead of 2 of by.
-// x-neighbours move across lanes as in variant 9.  The values and the
-// arithmetic per cell are those of variant 3.
-template <typename T, bool HI>
-struct MinWavesY {
-  static constexpr int value = sizeof(T) == 4 ? (HI ? 5 : 4) : (HI ? 3 : 2);
-};
-
-template <typename T, bool HI, bool PAL, int CAP>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64, CAP), amdgpu_waves_per_eu(MinWavesY<T, HI>::value)))
-step_kernel_y(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
-              int by, int parity, int first, double* __restrict__ partials) {
-  // rows: 0-1 1/(8G) of the upper cell of two planes, 2 1/H, 3 ux, 4 uz of the next plane and 5 syy of
-  // the upper cell; 6 uy, 7 sxy and 8 the carried syz of the lower cell
-  __shared__ __align__(16) T sL[9][CAP];
-  __shared__ CellCoef<T> tab[PAL ? 256 : 1];
-  __shared__ double red[16];
-  if constexpr (PAL) stage_coef_table(samples[0], tab);
-  T* const sG[2] = {sL[0], sL[1]};
-  T* const sH = sL[2];
-  T* const sUx = sL[3];
-  T* const sUz = sL[4];
-  T* const sSyy = sL[5];
-  T* const sUy = sL[6];
-  T* const sSxy = sL[7];
-  T* const sSyz = sL[8];
-
-  const int tid = threadIdx.x;
-  const int tx = tid % bx, ty = tid / bx;
-  const int TX = bx - 2, TY = 2 * by - 2;
-  const int ym = ty > 0 ? tid - bx : tid;       // its upper cell is the y-neighbour below our lower cell
-  const int yp = ty < by - 1 ? tid + bx : tid;  // its lower cell is the y-neighbour above our upper cell
-
-  const int w = blockIdx.x;  // one work item per block
-  if (w >= nwork) return;
-  const WorkItem wi = work[w];
-  if (wi.sample < 0) {
-    if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
-    return;
-  }
-  const SampleDesc<T>& sd = samples[wi.sample];
-  const int s0 = wi.slot0;
-  if (!((sd.active >> s0) & 1u)) {
-    if (partials != nullptr && tid < kMaxLoads) partials[(int64_t)w * kMaxLoads + tid] = 0.0;
-    return;
-  }
-  const int64_t nx = sd.nx, ny = sd.ny, N = sd.N, plane = nx * ny;
-  const T rhx = sd.rhx, rhy = sd.rhy, rhz = sd.rhz;
-  const T mom = first ? T(0) : sd.mom;
-  const T sfac = first ? sd.sfac_first : sd.sfac;
-  const int64_t gi = (int64_t)wi.tx * TX + tx - 1;
-  const int64_t gj0 = (int64_t)wi.ty * TY + 2 * ty - 1;
-  const int64_t cx = wrap_idx(gi, nx);
-  const uint32_t col[2] = {(uint32_t)(cx + nx * wrap_idx(gj0, ny)), (uint32_t)(cx + nx * wrap_idx(gj0 + 1, ny))};
-  const uint32_t colb[2] = {col[0] * (uint32_t)sizeof(T), col[1] * (uint32_t)sizeof(T)};
-  const bool inx = tx >= 1 && tx <= TX && gi < nx;
-  // cell rows 1 .. TY of the block are its own (threads past bx * by, when the block is rounded up to
-  // whole waves, have none)
-  const bool interior[2] = {inx && ty >= 1 && 2 * ty <= TY && gj0 < ny, inx && 2 * ty + 1 <= TY && gj0 + 1 < ny};
-  const int nz32 = (int)sd.nz;
-  const int k0 = wi.kz * sd.kc;
-  const int k1 = k0 + sd.kc < nz32 ? k0 + sd.kc : nz32;
-
-  const Moduli<T, PAL> mod(sd, tab);
-  const uint32_t pbytes = (uint32_t)(plane * (int64_t)sizeof(T));
-  const T* pcur = sd.u[parity][s0];
-  T* pold = sd.u[parity ^ 1][s0];
-  const T* pfrc = sd.force[s0];
-  const bool hasf = pfrc != nullptr;
-  T E[6];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) E[q] = sd.E[s0][q];
-  auto ldu = [&](int c, int64_t pk, int r) -> T {
-    return PlaneBuf(pcur + (c * N + pk), pbytes).template ld<T>(colb[r]);
-  };
-  auto ldo_ = [&](int c, int64_t pk, int r) -> T {
-    return PlaneBuf(pold + (c * N + pk), pbytes).template ld<T>(colb[r]);
-  };
-  auto ldf = [&](int c, int64_t pk, int r) -> T {
-    return PlaneBuf(pfrc + (c * N + pk), pbytes).template ld<T>(colb[r]);
-  };
-  auto sto_ = [&](int c, int64_t pk, int r, T v) { PlaneBuf(pold + (c * N + pk), pbytes).st(colb[r], v); };
-
-  // [cell][plane parity]
-  T Ux[2][2], Uy[2][2], Uz[2][2], Szz[2][2], Sxz[2][2], Syz[2][2], iHh[2][2];
-  CellCoef<T> Cc[2][2];
-  double nsum = 0.0;
-  {
-    const int kw = k0 - 1 < 0 ? k0 - 1 + nz32 : k0 - 1;
-    const int64_t po = plane * kw;
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      Ux[r][0] = ldu(0, po, r);
-      Uy[r][0] = ldu(1, po, r);
-      Uz[r][0] = ldu(2, po, r);
-      Szz[r][1] = Sxz[r][1] = Syz[r][1] = T(0);
-      Cc[r][0] = mod.coef(mod.load(po, col[r], colb[r]));
-      iHh[r][1] = T(1);
-    }
-    sG[0][tid] = Cc[1][0].iG8;
-  }
-
-  auto plane_step = [&](int k, auto Pc, auto Nc) {
-    constexpr int P = decltype(Pc)::value;
-    constexpr int Q = 1 - P;
-    constexpr bool NORM = decltype(Nc)::value;
-    const int kw = k < 0 ? k + nz32 : k;
-    const int kn = k + 1 >= nz32 ? k + 1 - nz32 : k + 1;
-    const int64_t pc = plane * kw, pn = plane * kn;
-    bool face[2];
-    T uo[2][3], f[2][3];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const auto mr = mod.load(pn, col[r], colb[r]);
-      Ux[r][Q] = ldu(0, pn, r);
-      Uy[r][Q] = ldu(1, pn, r);
-      Uz[r][Q] = ldu(2, pn, r);
-      face[r] = k >= k0 && interior[r];
-      if (face[r]) {
-        if (!first)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) uo[r][c] = ldo_(c, pc, r);
-        if (hasf)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) f[r][c] = ldf(c, pc, r);
-      }
-      Cc[r][Q] = mod.coef(mr);
-      iHh[r][P] = Cc[r][P].iH;
-    }
-    T* gk = sG[P];
-    T* gn = sG[Q];
-    gn[tid] = Cc[1][Q].iG8;
-    sH[tid] = iHh[1][P];
-    sUx[tid] = Ux[1][P];
-    sUz[tid] = Uz[1][Q];
-    sUy[tid] = Uy[0][P];
-    __syncthreads();
-    // y-neighbours: the lower cell's from the thread row below (LDS), the upper cell's from the lower
-    // cell (registers) and from the thread row above (LDS)
-    const T iky[2] = {gk[ym], Cc[0][P].iG8};
-    const T iny[2] = {gn[ym], Cc[0][Q].iG8};
-    const T iHy[2] = {sH[ym], iHh[0][P]};
-    const T uxy[2] = {sUx[ym], Ux[0][P]};
-    const T uzy[2] = {sUz[ym], Uz[0][Q]};
-    const T uyp[2] = {Uy[1][P], sUy[yp]};
-    T sxx[2], syy[2], szz[2], sxy[2], sxz_n[2], syz_n[2], sfx[2], sfy[2], sfz[2];
-    T ikx[2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const T ux = Ux[r][P], uy = Uy[r][P], uz = Uz[r][P];
-      const T unx = Ux[r][Q], uny = Uy[r][Q], unz = Uz[r][Q];
-      const T ik = Cc[r][P].iG8, in = Cc[r][Q].iG8;
-      ikx[r] = lane_prev(ik);
-      const T inx = lane_prev(in);
-      // the lower cell's x-shifted y-neighbour is the cell below's lane shift; the upper cell's is the
-      // lower cell's own
-      const T ikxy = r == 0 ? lane_prev(iky[0]) : ikx[0];
-      const T G2xy = recip(ikxy + iky[r] + ikx[r] + ik);
-      const T G2xz = recip(ikx[r] + ik + inx + in);
-      const T G2yz = recip(iky[r] + ik + iny[r] + in);
-      sfx[r] = sfac * tmin(lane_prev(iHh[r][P]), iHh[r][P]);
-      sfy[r] = sfac * tmin(iHy[r], iHh[r][P]);
-      sfz[r] = sfac * tmin(iHh[r][Q], iHh[r][P]);
-      const T exx = E[0] + (lane_next(ux) - ux) * rhx;
-      const T eyy = E[1] + (uyp[r] - uy) * rhy;
-      const T ezz = E[2] + (unz - uz) * rhz;
-      const T th = exx + eyy + ezz;
-      const T lam = Cc[r][P].lam, twoG = Cc[r][P].twoG;
-      sxx[r] = lam * th + twoG * exx;
-      syy[r] = lam * th + twoG * eyy;
-      szz[r] = lam * th + twoG * ezz;
-      sxy[r] = G2xy * (E[5] + T(0.5) * ((ux - uxy[r]) * rhy + (uy - lane_prev(uy)) * rhx));
-      sxz_n[r] = G2xz * (E[4] + T(0.5) * ((unx - ux) * rhz + (unz - lane_prev(unz)) * rhx));
-      syz_n[r] = G2yz * (E[3] + T(0.5) * ((uny - uy) * rhz + (unz - uzy[r]) * rhy));
-    }
-    sSyy[tid] = syy[1];
-    sSxy[tid] = sxy[0];
-    sSyz[tid] = Syz[0][Q];
-    // Before the second barrier: every residual term whose neighbour is in this thread's
-    // registers (the x-neighbours across lanes, the other cell of the pair), each sum in the
-    // order of the full expression, and the momentum part of the update; after it only the
-    // terms with the thread rows above and below remain.
-    T mu[2][3];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T uc = c == 0 ? Ux[r][P] : (c == 1 ? Uy[r][P] : Uz[r][P]);
-        mu[r][c] = first ? uc : uc + mom * (uc - uo[r][c]);
-      }
-    // lower cell: rx and rz complete, ry up to its y term
-    T rx0 = (sxx[0] - lane_prev(sxx[0])) * rhx + (sxy[1] - sxy[0]) * rhy + (sxz_n[0] - Sxz[0][Q]) * rhz;
-    T rz0 = (lane_next(Sxz[0][Q]) - Sxz[0][Q]) * rhx + (Syz[1][Q] - Syz[0][Q]) * rhy + (szz[0] - Szz[0][Q]) * rhz;
-    const T ry0a = (lane_next(sxy[0]) - sxy[0]) * rhx;
-    const T syy0 = syy[0], dz0 = syz_n[0] - Syz[0][Q];
-    // upper cell: ry complete, rx and rz up to their y terms
-    T ry1 = (lane_next(sxy[1]) - sxy[1]) * rhx + (syy[1] - syy[0]) * rhy + (syz_n[1] - Syz[1][Q]) * rhz;
-    const T rx1a = (sxx[1] - lane_prev(sxx[1])) * rhx;
-    const T rz1a = (lane_next(Sxz[1][Q]) - Sxz[1][Q]) * rhx;
-    const T sxy1 = sxy[1], dx1 = sxz_n[1] - Sxz[1][Q], syzc1 = Syz[1][Q], dzz1 = szz[1] - Szz[1][Q];
-    if (hasf && face[0]) {
-      rx0 += f[0][0];
-      rz0 += f[0][2];
-    }
-    if (hasf && face[1]) ry1 += f[1][1];
-    __syncthreads();
-    if (face[0]) {
-      T ry0 = ry0a + (syy0 - sSyy[ym]) * rhy + dz0 * rhz;
-      if (hasf) ry0 += f[0][1];
-      if (NORM) nsum += (double)rx0 * (double)rx0 + (double)ry0 * (double)ry0 + (double)rz0 * (double)rz0;
-      sto_(0, pc, 0, mu[0][0] + sfx[0] * rx0);
-      sto_(1, pc, 0, mu[0][1] + sfy[0] * ry0);
-      sto_(2, pc, 0, mu[0][2] + sfz[0] * rz0);
-    }
-    if (face[1]) {
-      T rx1 = rx1a + (sSxy[yp] - sxy1) * rhy + dx1 * rhz;
-      T rz1 = rz1a + (sSyz[yp] - syzc1) * rhy + dzz1 * rhz;
-      if (hasf) {
-        rx1 += f[1][0];
-        rz1 += f[1][2];
-      }
-      if (NORM) nsum += (double)rx1 * (double)rx1 + (double)ry1 * (double)ry1 + (double)rz1 * (double)rz1;
-      sto_(0, pc, 1, mu[1][0] + sfx[1] * rx1);
-      sto_(1, pc, 1, mu[1][1] + sfy[1] * ry1);
-      sto_(2, pc, 1, mu[1][2] + sfz[1] * rz1);
-    }
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      Szz[r][P] = szz[r];
-      Sxz[r][P] = sxz_n[r];
-      Syz[r][P] = syz_n[r];
-    }
-  };
-
-  auto march = [&](auto Nc) {
-    for (int k = k0 - 1; k < k1; k += 2) {
-      plane_step(k, std::integral_constant<int, 0>{}, Nc);
-      if (k + 1 < k1) plane_step(k + 1, std::integral_constant<int, 1>{}, Nc);
-    }
-  };
-  if (partials != nullptr)
-    march(std::true_type{});
-  else
-    march(std::false_type{});
-
-  if (partials != nullptr) {
-    const double tot = block_sum(nsum, red);
-    if (tid == 0)
-      for (int q = 0; q < kMaxLoads; ++q) partials[(int64_t)w * kMaxLoads + q] = q == s0 ? tot : 0.0;
-  }
-}
-
 // Two heavy-ball iterations in one z-march (one load per block, periodic
 // boundaries): u^{n+1} from (u^n, u^{n-1}) and u^{n+2} from (u^{n+1}, u^n).
 // u^n and u^{n-1} are buffers parity and parity ^ 1; the results go to the
@@ -2977,24 +2717,6 @@ template <typename T, int L, bool HI>
 void launch_step_occ(const SampleDesc<T>* d_samples, const WorkItem* d_work, int nwork, TileShape ts, int parity,
                      int first, double* partials, hipStream_t s, int nt, size_t lds) {
   if constexpr (L == 1) {
-    if (ts.pf == 10 && !ts.walls) {  // two cell rows per thread (one load per block, bx 16, 32 or 64)
-      if (nt <= 256) {
-        if (ts.pal)
-          hipLaunchKernelGGL((step_kernel_y<T, HI, true, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
-        else
-          hipLaunchKernelGGL((step_kernel_y<T, HI, false, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work,
-                             nwork, ts.bx, ts.by, parity, first, partials);
-      } else {
-        if (ts.pal)
-          hipLaunchKernelGGL((step_kernel_y<T, HI, true, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
-        else
-          hipLaunchKernelGGL((step_kernel_y<T, HI, false, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work,
-                             nwork, ts.bx, ts.by, parity, first, partials);
-      }
-      return;
-    }
     if (ts.pf == 9 && !ts.walls) {  // x-neighbours across lanes (one load per block, bx 16, 32 or 64)
       if (nt <= 256) {
         if (ts.pal)

@@ -1,4 +1,4 @@
-"""Iteration kernels with x-neighbours exchanged across lanes (variants 9 and 10, GPU).
+"""Iteration kernel with x-neighbours exchanged across lanes (variant 9, GPU).
 
 Variant 9 is variant 3 for one load per block with rows 16, 32 or 64 cells wide,
 so that every row lies within one wave: x-neighbour values move between lanes by
@@ -9,10 +9,7 @@ may contract the update's multiply-adds differently).  Checked after 1, 2 and
 grids 2 to 4 planes thick, blocks with padding rows, all three row widths, moduli
 from K and G fields and from a phase image, and against the oracle's iteration;
 and full solves in mixed precision (folds, body forces, residual norms) and in
-FP64, where each double crosses lanes as two 32-bit shifts.  Variant 10 is
-variant 9 with two cells of a column per thread: a tile "bx,by" covers 2*by cell
-rows, so the same tiles test other block heights, odd thread-row counts (blocks
-padded to whole waves) and one-tile grids thinner than a block."""
+FP64, where each double crosses lanes as two 32-bit shifts."""
 import numpy as np
 import pytest
 
@@ -22,9 +19,7 @@ from gpu_common import announce, matrix_rel, need_gpu
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [9, 10]
-
-CASES = [  # (nx, ny, nz), seed, tile "bx,by,kc" (variant 10: by thread rows of two cells each)
+CASES = [  # (nx, ny, nz), seed, tile "bx,by,kc"
     ((40, 33, 29), 1, "16,8,7"),
     ((70, 9, 31), 2, "32,6,3"),
     ((13, 45, 26), 3, "64,5,1"),
@@ -48,14 +43,13 @@ def _steps(p, monkeypatch, tile, variant, K=None, G=None, m=None, J=1, n=(1, 2, 
     return out
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("shape,seed,tile", CASES)
-def test_lanes_steps_equal_variant3(monkeypatch, shape, seed, tile, variant):
+def test_lanes_steps_equal_variant3(monkeypatch, shape, seed, tile):
     p = need_gpu()
     K, G = synth.random_fields(shape[::-1], seed, lo=(2.0, 1e-3), hi=(90.0, 45.0))
-    announce(f"variant {variant} vs 3, fields", shape, tile)
+    announce("variant 9 vs 3, fields", shape, tile)
     a = _steps(p, monkeypatch, tile, 3, K=K, G=G)
-    b = _steps(p, monkeypatch, tile, variant, K=K, G=G)
+    b = _steps(p, monkeypatch, tile, 9, K=K, G=G)
     for k in a:
         for x, y in zip(a[k], b[k]):
             sc = float(np.abs(x).max())  # the previous iterate after one step is zero
@@ -66,15 +60,14 @@ def test_lanes_steps_equal_variant3(monkeypatch, shape, seed, tile, variant):
     assert np.abs(b[11][0] - ref).max() <= 2e-5 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("shape,seed,tile", CASES[::2])
-def test_lanes_fp64_steps_equal_variant3(monkeypatch, shape, seed, tile, variant):
+def test_lanes_fp64_steps_equal_variant3(monkeypatch, shape, seed, tile):
     """The FP64 build moves each double as two 32-bit lane shifts."""
     p = need_gpu()
     K, G = synth.random_fields(shape[::-1], seed + 10, lo=(2.0, 1e-3), hi=(90.0, 45.0))
-    announce(f"variant {variant} vs 3, fp64", shape, tile)
+    announce("variant 9 vs 3, fp64", shape, tile)
     a = _steps(p, monkeypatch, tile, 3, K=K, G=G, prec="fp64")
-    b = _steps(p, monkeypatch, tile, variant, K=K, G=G, prec="fp64")
+    b = _steps(p, monkeypatch, tile, 9, K=K, G=G, prec="fp64")
     for k in a:
         for x, y in zip(a[k], b[k]):
             sc = float(np.abs(x).max())
@@ -85,31 +78,29 @@ def test_lanes_fp64_steps_equal_variant3(monkeypatch, shape, seed, tile, variant
     assert np.abs(b[11][0] - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("shape,seed,tile", CASES[:3])
-def test_lanes_phase_image_equals_variant3(monkeypatch, shape, seed, tile, variant):
+def test_lanes_phase_image_equals_variant3(monkeypatch, shape, seed, tile):
     p = need_gpu()
     nx, ny, nz = shape
     rng = np.random.default_rng(seed)
     phase = rng.integers(0, 3, size=(nz, ny, nx)).astype(np.uint8)
     m = synth.Microstructure(phase, np.array([70.0, 2.2, 35.0]), np.array([32.0, 1e-3, 12.0]))
-    announce(f"variant {variant} vs 3, phase image", shape, tile)
+    announce("variant 9 vs 3, phase image", shape, tile)
     for J in (0, 4):
         a = _steps(p, monkeypatch, tile, 3, m=m, J=J, n=(2, 11))
-        b = _steps(p, monkeypatch, tile, variant, m=m, J=J, n=(2, 11))
+        b = _steps(p, monkeypatch, tile, 9, m=m, J=J, n=(2, 11))
         for k in a:
             for x, y in zip(a[k], b[k]):
                 assert np.abs(x - y).max() <= 1e-6 * max(np.abs(x).max(), 1e-30), (J, k)
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("phases,prec", [(False, "mixed"), (True, "mixed"), (True, "fp64")])
-def test_lanes_solve_equals_variant3_solve(monkeypatch, phases, prec, variant):
+def test_lanes_solve_equals_variant3_solve(monkeypatch, phases, prec):
     p = need_gpu()
     m = synth.random_spheres(72, 0.10, 0x7B)
     K, G = m.fields()
     res = {}
-    for v in (3, variant):
+    for v in (3, 9):
         monkeypatch.setenv("CEFF_TILE", f"16,16,12,1,{v},1,1")
         with p.Context() as c:
             if phases:
@@ -118,8 +109,8 @@ def test_lanes_solve_equals_variant3_solve(monkeypatch, phases, prec, variant):
                 c.set_material(K, G)
             res[v] = c.solve(precision=prec, rtol=1e-8, loads=(0, 3), fuse_loads=False)
             assert res[v][1]["stats"]["tile_variant"] == v
-    (C3, i3), (C9, i9) = res[3], res[variant]
-    announce(f"variant {variant} solve", phases, prec, i3["iters"].tolist(), i9["iters"].tolist(),
+    (C3, i3), (C9, i9) = res[3], res[9]
+    announce("variant 9 solve", phases, prec, i3["iters"].tolist(), i9["iters"].tolist(),
              matrix_rel(C9[:, [0, 3]], C3[:, [0, 3]]))
     assert i9["status"] == 0
     assert matrix_rel(C9[:, [0, 3]], C3[:, [0, 3]]) <= 1e-9
