@@ -630,9 +630,30 @@ struct Engine {
   // per launch in variant 9 at 480^3: 64 x 8 blocks with 32-plane chunks
   // 0.903 ms, with 48-plane chunks 0.960 ms, against 1.000 ms for variant 3 at
   // 66 x 7 x 48.  Applied to single-image FP32 solves with the phase table whose
-  // grid still yields at least 2048 (tile, chunk) items at that shape.
+  // grid still yields at least 2048 (tile, chunk) items at that shape.  FP32
+  // batches (one (sample, load) pair per block, variant 9) beyond the cache take
+  // 64 x 8 blocks with 16-plane chunks: the 48-sample three-phase batch (samples
+  // 48 to 128 wide, 5.4 GB for all six loads) ran in 8.85 s against 9.67 s with
+  // the cache-resident 32 x 8 x 24 blocks (12-, 24-, 32- and 48-plane chunks
+  // 8.85, 8.93, 9.09 and 9.86 s).
   void large_grid_shape() {
-    if (sizeof(T) != 4 || in.size() != 1 || !ts.pal || ts.ortho || ts.walls || ts.tri) return;
+    if (sizeof(T) != 4 || ts.ortho || ts.walls || ts.tri) return;
+    if (in.size() > 1) {
+      if (ts.pf != 9 || ts.bx != 32) return;  // the batch default for samples wider than 14 cells
+      double ws = 0.0;
+      int64_t items = 0;
+      for (const SampleIn& s : in) {
+        ws += (double)s.nx * s.ny * s.nz * (6.0 * sizeof(T) * (double)Js.size() + (ts.pal ? 1.0 : 2.0 * sizeof(T)));
+        items += ((s.nx + 61) / 62) * ((s.ny + 5) / 6) * ((s.nz + 15) / 16) * (int64_t)Js.size();
+      }
+      if (ws <= kInfinityCacheBytes || items < 2048) return;
+      ts.bx = 64;
+      ts.by = 8;
+      ts.kc = 16;
+      ts.occ = 1;
+      return;
+    }
+    if (!ts.pal) return;
     const SampleIn& s = in[0];
     const double ws = (double)s.nx * s.ny * s.nz * (6.0 * sizeof(T) * (double)Js.size() + 1.0);
     if (ws <= kInfinityCacheBytes) return;

@@ -325,6 +325,39 @@ def test_large_grid_launch_shape(monkeypatch, fuse):
     assert np.array_equal(info["iters"], info2["iters"])
 
 
+@pytest.mark.parametrize("phases", [True, False])
+def test_large_batch_launch_shape(monkeypatch, phases):
+    """A batch whose six-load working set exceeds the Infinity Cache (two 160^3 pore packs
+    and a 96^3 one: 2.1 GB) takes 64 x 8 blocks of variant 9 with 16-plane chunks, from
+    phase images and from K and G fields; a batch inside the cache keeps the 32 x 8 x 24
+    default; the iterates and iteration counts are those of the default shape."""
+    p = need_gpu()
+    ms = [synth.random_spheres(160, 0.10, 0x160), synth.random_spheres(160, 0.12, 0x161),
+          synth.random_spheres(96, 0.10, 0x96)]
+    monkeypatch.delenv("CEFF_TILE", raising=False)
+    announce("large-batch shape", phases)
+    opts = dict(precision="mixed", max_iter=300, check_every=100, allow_unconverged=True)
+
+    def run():
+        if phases:
+            return p.solve_batch_phases([m.phase for m in ms], ms[0].K_tab, ms[0].G_tab, **opts)
+        return p.solve_batch([m.fields() for m in ms], **opts)
+
+    C, it, info = run()
+    st = info["stats"]
+    assert (st["tile_bx"], st["tile_by"], st["tile_kc"], st["tile_variant"]) == (64, 8, 16, 9)
+    monkeypatch.setenv("CEFF_TILE", "32,8,24,1,9,1,1")
+    C2, it2, info2 = run()
+    assert (info2["stats"]["tile_bx"], info2["stats"]["tile_kc"]) == (32, 24)
+    assert np.max(np.abs(C - C2)) <= 1e-12 * np.abs(C).max()
+    assert np.array_equal(it, it2)
+    monkeypatch.delenv("CEFF_TILE")
+    _, _, info3 = p.solve_batch_phases([np.ascontiguousarray(m.phase[:48, :48, :48]) for m in ms], ms[0].K_tab,
+                                       ms[0].G_tab, **opts)
+    st3 = info3["stats"]
+    assert (st3["tile_bx"], st3["tile_by"], st3["tile_kc"]) == (32, 8, 24)
+
+
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_warm_start(precision):
     """An initial guess (ceff_solve_opts::warm_u): the oracle's converged fields need no
