@@ -73,10 +73,11 @@ struct TileShape {
   int pf = 0;      // 0: plain z-march; 1: prefetch the next plane into registers; 2: z-march unrolled by two;
                    // 3: unrolled, all loads of the group between one pair of barriers per plane;
                    // 4: as 3, unrolled by three with the next plane's data requested one plane ahead;
-                   // 5: one load per block, no LDS: neighbours read through the caches
+                   // 5: one load per block, no LDS: neighbours read through the caches;
+                   // 9: one load per block, rows of 16, 32 or 64 cells, x-neighbours across lanes
   int order = 0;   // 0: load groups of a tile 8 items apart; 1: each XCD takes a contiguous band
   int occ = 0;     // 1: build that targets more waves per SIMD (fewer registers)
-  int pal = 0;     // 1: moduli from the samples' phase image and table (variant 3 only)
+  int pal = 0;     // 1: moduli from the samples' phase image and table (variants 3 and 9)
   int ortho = 0;   // 1: orthotropic cells (one load per block, its own kernel)
   int walls = 0;   // 1: wall boundaries (variant 3, one load per block)
   int tri = 0;     // 1: general anisotropic cells (their own launches, one load)
