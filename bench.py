@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the iteration kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_trace_and_counters.md and
 # profiles/step_kernel_spheres480_trace_and_counters.md), valid only for the kernel source they were taken on.
-MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "22e568951d4187a4", "bytes_per_launch": 3.184297e+08,
+MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "2ecd94d749874e0c", "bytes_per_launch": 3.185336e+08,
                     # (loads per block, kernel variant, loads fused, moduli from the phase image, high occupancy)
                     "launch_signature": (1, 9, 0, 1, 1),
                     # mean algorithmic bytes per launch of the profiled solve: fixes its mix of
@@ -36,7 +36,7 @@ MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "22e568951d4187a4", "bytes_per
                     "launch": "step_kernel_x<float,1,PAL,high occupancy>, mean over all launches of a full solve"}
 # the same for the HBM-resident measurement (480^3, one load, 200 iterations without body force; the mean over
 # its launches after the first, which reads no u^{n-1})
-MEASURED_TRAFFIC_HBM = {"ceff_kernels_sha256_prefix": "22e568951d4187a4", "n": 480, "bytes_per_launch": 4.356568e+09,
+MEASURED_TRAFFIC_HBM = {"ceff_kernels_sha256_prefix": "2ecd94d749874e0c", "n": 480, "bytes_per_launch": 4.362165e+09,
                         "algorithmic_bytes_per_launch": 4.091904e+09, "launch_shape": "64x8x32 variant 9"}
 
 
