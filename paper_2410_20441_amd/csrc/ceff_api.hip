@@ -498,18 +498,39 @@ struct Engine {
       const size_t base = w.size();
       rg.push_back((int)base);
       if (t.order == 1) {
-        // (kz, ty, tx, group) in lexicographic order, cut into 8 contiguous bands;
-        // band x goes to positions x, x+8, x+16, ... (XCD x under round-robin
-        // dispatch), so blocks running together on one XCD are spatial neighbours
-        // and share halo rows and moduli through that XCD's L2
+        // (kz, ty, tx, group) in lexicographic order, cut into 8 contiguous bands of
+        // equal work; band x goes to positions x, x+8, x+16, ... (XCD x under
+        // round-robin dispatch), so blocks running together on one XCD are spatial
+        // neighbours and share halo rows and moduli through that XCD's L2.  An
+        // item's work is the planes it marches, its chunk's lead plane included:
+        // when the last chunk is short, bands of equal item counts leave the XCD
+        // with the short chunks idle early (480^3 in 28-plane chunks: 0.952 ms per
+        // launch against 0.906 in 32-plane ones).  Shorter bands are padded with
+        // empty items.
         const int64_t n = ntile * G;
-        const int64_t per = (n + 7) / 8;
+        const int64_t slice = (int64_t)tx * ty * G;  // items of one z-chunk
+        auto work_of = [&](int64_t kz) { return std::min<int64_t>(kc, s.nz - kz * kc) + 1; };
+        int64_t total = 0;
+        for (int64_t kz = 0; kz < cz; ++kz) total += work_of(kz) * slice;
+        std::vector<uint8_t> band((size_t)n);
+        int64_t count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int64_t acc = 0;
+        for (int64_t q = 0; q < n; ++q) {
+          const int64_t wq = work_of(q / slice);
+          const int64_t bq = std::min<int64_t>(7, (8 * (2 * acc + wq)) / (2 * total));  // band of its midpoint
+          band[(size_t)q] = (uint8_t)bq;
+          ++count[bq];
+          acc += wq;
+        }
+        const int64_t per = *std::max_element(count, count + 8);
         w.resize(base + (size_t)(per * 8), WorkItem{-1, 0, 0, 0, 0});
+        int64_t next[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int64_t q = 0; q < n; ++q) {
           const int64_t tt = q / G;
           const int g = (int)(q % G);
           const int a = (int)(tt % tx), b = (int)((tt / tx) % ty), kz = (int)(tt / ((int64_t)tx * ty));
-          const int64_t pos = 8 * (q % per) + q / per;
+          const int bq = band[(size_t)q];
+          const int64_t pos = 8 * next[bq]++ + bq;
           w[base + (size_t)pos] = WorkItem{(int)si, a, b, kz, slots0[g]};
         }
       } else {
