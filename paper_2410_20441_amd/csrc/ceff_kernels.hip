@@ -1030,16 +1030,19 @@ step_kernel_b(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
 // and every x-neighbour value (u, 1/(8G), 1/H, sxx, sxy, the carried sxz) moves
 // between lanes with a DPP wave shift instead of a round trip through LDS.  Only
 // the y-neighbours go through LDS (9 reads and 8 writes per plane instead of 19
-// and 10).  The values and the arithmetic are those of step_kernel_b (lane 0 of
-// a wave and the first lane of each further row receive a value that no
-// interior thread consumes, as the clamped index does there).
-__device__ __forceinline__ float lane_prev(float v) {  // value of lane - 1 (lane 0: its own)
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v),
-                                                               0x138, 0xf, 0xf, false));
+// and 10).  The values and the arithmetic are those of step_kernel_b.  Where a
+// shift has no source lane (lane 0 for the previous lane, lane 63 for the next)
+// it yields zero, and the first and last lanes of the wave's other rows receive
+// the neighbouring row's value: these lanes are ghost columns whose shifted
+// values no interior thread reads (as with the clamped index there), and the
+// zero fill lets the compiler fold each shift into the instruction that consumes
+// it as a DPP operand.  Every sum of 1/(8G) terms stays positive, so ghost lanes
+// compute finite values.
+__device__ __forceinline__ float lane_prev(float v) {  // value of lane - 1 (lane 0: zero)
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
 }
-__device__ __forceinline__ float lane_next(float v) {  // value of lane + 1 (lane 63: its own)
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v),
-                                                               0x130, 0xf, 0xf, false));
+__device__ __forceinline__ float lane_next(float v) {  // value of lane + 1 (lane 63: zero)
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double lane_prev(double v) {  // both halves moved by one lane
   const uint64_t b = __builtin_bit_cast(uint64_t, v);

@@ -115,3 +115,27 @@ def test_lanes_solve_equals_variant3_solve(monkeypatch, phases, prec):
     assert i9["status"] == 0
     assert matrix_rel(C9[:, [0, 3]], C3[:, [0, 3]]) <= 1e-9
     assert np.all(np.abs(i9["iters"] - i3["iters"]) <= 100)
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 5), (3, 2, 4), (2, 2, 2), (70, 2, 3), (2, 40, 6), (17, 2, 2)])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_degenerate_grids_default_shape(monkeypatch, shape, prec):
+    """Grids two cells wide in x or y, and two planes deep, on the library's own launch shape
+    (variant 9 in mixed precision, variant 3 in FP64): a row's ghost lanes then wrap onto the
+    same two columns, and a block's ghost rows onto the same two rows.  The iterate after 11
+    steps matches the oracle's paper-form iteration, and C* its PCG solve."""
+    p = need_gpu()
+    monkeypatch.delenv("CEFF_TILE", raising=False)
+    K, G = synth.random_fields(shape[::-1], sum(shape), lo=(2.0, 1e-3), hi=(90.0, 45.0))
+    announce("degenerate grid", shape, prec)
+    ref, _ = oracle.apt_disp(2, 11, 0.95, 3.0, K=K, G=G)
+    with p.Context() as c:
+        c.set_material(K, G)
+        u, _ = c.apt_steps(2, 11, prec, courant=0.95, strouhal=3.0)
+        assert c.stats()["tile_variant"] == (9 if prec == "mixed" else 3)
+        C, info = c.solve(precision=prec, rtol=1e-9)
+    tol = 2e-5 if prec == "mixed" else 1e-11
+    assert np.abs(u - ref).max() <= tol * np.abs(ref).max()
+    Co, _ = oracle.ceff(K, G, rtol=1e-12)
+    assert info["status"] == 0
+    assert matrix_rel(C, Co) <= 1e-6
