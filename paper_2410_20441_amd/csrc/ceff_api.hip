@@ -308,14 +308,15 @@ TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single, bool batc
                        (pf >= 0 && pf <= 5) || pf == 9 ? pf : 0, ord ? 1 : 0, occ ? 1 : 0, 0};
   }
   // FP32, one load per launch: variant 9 (x-neighbours across lanes), 32 x 8 ghosted block
-  // (30 x 6 interior, rows within a wave) with 24-plane chunks, high-occupancy build: 0.0498 ms per
-  // launch at 191^3 against 0.0569 for variant 3's best (18 x 14, 12 planes).  A batch of images
-  // takes the same blocks with one load each: the 48-sample three-phase batch in 9.7 s against
-  // 10.7 s with variant 3 and two loads per block.
+  // (30 x 6 interior, rows within a wave) with 12-plane chunks, high-occupancy build: 0.051-0.054 ms
+  // per launch at 191^3 on every box measured, against 0.0569 for variant 3's best (18 x 14, 12
+  // planes).  24-plane chunks (seven blocks per CU in one round) took 0.050-0.051 ms on some boxes
+  // and 0.056-0.057 on others.  A batch of images takes the same blocks with one load each: the
+  // 48-sample three-phase batch in 9.7 s against 10.7 s with variant 3 and two loads per block.
   if ((single || batch) && !fp64) {
     t.bx = nx + 2 <= 16 ? 16 : 32;
     t.by = (int)std::min<int64_t>(ny + 2, 8);
-    t.kc = 24;
+    t.kc = 12;
     t.group = 1;
     t.pf = 9;
     t.order = 1;

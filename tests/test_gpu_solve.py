@@ -329,7 +329,7 @@ def test_large_grid_launch_shape(monkeypatch, fuse):
 def test_large_batch_launch_shape(monkeypatch, phases):
     """A batch whose six-load working set exceeds the Infinity Cache (two 160^3 pore packs
     and a 96^3 one: 2.1 GB) takes 64 x 8 blocks of variant 9 with 16-plane chunks, from
-    phase images and from K and G fields; a batch inside the cache keeps the 32 x 8 x 24
+    phase images and from K and G fields; a batch inside the cache keeps the 32 x 8 x 12
     default; the iterates and iteration counts are those of the default shape."""
     p = need_gpu()
     ms = [synth.random_spheres(160, 0.10, 0x160), synth.random_spheres(160, 0.12, 0x161),
@@ -355,7 +355,7 @@ def test_large_batch_launch_shape(monkeypatch, phases):
     _, _, info3 = p.solve_batch_phases([np.ascontiguousarray(m.phase[:48, :48, :48]) for m in ms], ms[0].K_tab,
                                        ms[0].G_tab, **opts)
     st3 = info3["stats"]
-    assert (st3["tile_bx"], st3["tile_by"], st3["tile_kc"]) == (32, 8, 24)
+    assert (st3["tile_bx"], st3["tile_by"], st3["tile_kc"]) == (32, 8, 12)
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
