@@ -182,6 +182,8 @@ def parse():
                     help="load fusion: library choice (auto), one launch for all loads (on), one load at a time (off)")
     ap.add_argument("--max-iter", type=int, default=400000)
     ap.add_argument("--loads", default="012345", help="other single-image workloads: the loads to solve")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"],
+                    help="batch48, cracks479, spheres703: precision of the solve (the benchmark line is mixed)")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for counter collection: allow stopping at --max-iter")
     ap.add_argument("--workload", default="spheres191",
@@ -475,7 +477,7 @@ def other_workload(a, torch, synth, ceff, dev):
     if a.workload == "hbm480":
         print(json.dumps(hbm_roofline(a, torch, synth, ceff, dev)), flush=True)
         return
-    opts = dict(precision="mixed", rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, max_iter=a.max_iter,
+    opts = dict(precision=a.precision, rtol=a.rtol, strouhal=a.strouhal, check_every=a.check_every, max_iter=a.max_iter,
                 allow_unconverged=a.profile_run, autotune=a.autotune,
                 fuse_loads={"auto": "auto", "on": True, "off": False}[a.fuse])
     t0 = time.perf_counter()
@@ -493,7 +495,7 @@ def other_workload(a, torch, synth, ceff, dev):
         wall = time.perf_counter() - t1
         vu = float(sum(ms[s].phase.size * it[s].sum() for s in range(len(ms))))
         st = info["stats"]
-        res = {"workload": "batch48", "voxels": N, "samples": len(ms), "status": info["status"],
+        res = {"workload": "batch48", "precision": a.precision, "voxels": N, "samples": len(ms), "status": info["status"],
                "time_s": wall, "gvu_s": vu / wall / 1e9, "max_iterations": int(it.max()),
                "kernel_GB_s": st["step_bytes"] / (st["step_time_ms"] * 1e-3) / 1e9,
                "avg_launch_ms": st["step_time_ms"] / max(st["step_launches"], 1), "launches": st["step_launches"]}
@@ -533,7 +535,8 @@ def other_workload(a, torch, synth, ceff, dev):
                   file=sys.stderr, flush=True)
         wall = time.perf_counter() - t1
         ctx.close()
-        res = {"workload": a.workload, "voxels": N, "info": m.info, "status": status, "time_s": wall,
+        res = {"workload": a.workload, "precision": a.precision, "voxels": N, "info": m.info, "status": status,
+               "time_s": wall,
                "loads": loads, "iterations": iters.tolist(), "final_relres": relres, "strouhal": a.strouhal,
                "gvu_s": N * float(iters.sum()) / wall / 1e9,
                "kernel_GB_s": step_bytes / (step_ms * 1e-3) / 1e9 if step_ms > 0 else None,
