@@ -415,7 +415,7 @@ struct Engine {
   int parity = 0;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
-  int graph_m = 0, graph_parity = -1;
+  int graph_m = 0, graph_parity = -1, graph_force = -1;
   // accounting
   double step_ms = 0.0, step_bytes = 0.0, vu = 0.0;
   int64_t launches = 0, outer = 0;
@@ -597,9 +597,24 @@ struct Engine {
       default: return launch_step<T, 6>(d, dw, nw, t, par, first, partials, c->s);
     }
   }
+  // Body forces of the active loads, from the host copy of the descriptors: 0 none, 1 all, 2 some.
+  // Variant 9 builds the first two cases without the per-block check.
+  int force_state() const {
+    bool any = false, all = true;
+    for (const SampleDesc<T>& d : h_in)
+      for (int l = 0; l < kMaxLoads; ++l)
+        if (d.active & (1u << l)) {
+          const bool f = d.force[l] != nullptr;
+          any = any || f;
+          all = all && f;
+        }
+    return !any ? 0 : (all ? 1 : 2);
+  }
   hipError_t step(int first, double* partials) {
     if (ts.tb) return step_on(d_work_s.as<WorkItem>(), (int)work_s.size(), ts1, 1, parity, first, partials);
-    return step_on(d_work.as<WorkItem>(), (int)work.size(), ts, group(), parity, first, partials);
+    TileShape t = ts;
+    t.force = force_state();
+    return step_on(d_work.as<WorkItem>(), (int)work.size(), t, group(), parity, first, partials);
   }
   // two iterations (ts.tb); the newest iterate is then in the odd buffer of the other pair
   hipError_t step_pair(double* partials) {
@@ -1000,8 +1015,10 @@ struct Engine {
     // its intermediate iterate)
     const double bpl = bytes_per_launch(), vpl = vu_per_launch();
     const int nl = ts.tb ? m / 2 : m;
-    // a captured graph has the buffer parity of its first launch built in
-    if (o.use_graph && (!gexec || graph_m != m || graph_parity != parity)) {
+    // a captured graph has the buffer parity of its first launch and the launches' body-force
+    // case built in
+    const int fs = force_state();
+    if (o.use_graph && (!gexec || graph_m != m || graph_parity != parity || graph_force != fs)) {
       if (gexec) {
         (void)hipGraphExecDestroy(gexec);
         gexec = nullptr;
@@ -1030,6 +1047,7 @@ struct Engine {
       HIPCK(c, hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
       graph_m = m;
       graph_parity = p0;
+      graph_force = fs;
     }
     HIPCK(c, hipEventRecord(c->ev0, c->s));
     if (o.use_graph) {

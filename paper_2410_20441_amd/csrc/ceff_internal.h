@@ -81,6 +81,8 @@ struct TileShape {
   int ortho = 0;   // 1: orthotropic cells (one load per block, its own kernel)
   int walls = 0;   // 1: wall boundaries (variant 3, one load per block)
   int tri = 0;     // 1: general anisotropic cells (their own launches, one load)
+  int force = 2;   // variant 9, body forces of the launch's active loads: 0 none, 1 all of them,
+                   // 2 some (each block checks its own)
   int tb = 0;      // 1: two iterations per launch (one load per block, 2-cell ghost ring; iterations
                    // after the first of a solve come in pairs)
 };

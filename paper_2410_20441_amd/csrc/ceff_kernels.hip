@@ -1059,7 +1059,7 @@ __device__ __forceinline__ double lane_next(double v) {
   return __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
 }
 
-template <typename T, bool HI, bool PAL, int CAP>
+template <typename T, bool HI, bool PAL, int CAP, int FRC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, CAP), amdgpu_waves_per_eu(MinWaves<T, 1, HI>::value)))
 step_kernel_x(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restrict__ work, int nwork, int bx,
               int by, int parity, int first, double* __restrict__ partials) {
@@ -1115,7 +1115,9 @@ step_kernel_x(const SampleDesc<T>* __restrict__ samples, const WorkItem* __restr
   const T* pcur = sd.u[parity][s0];
   T* pold = sd.u[parity ^ 1][s0];
   const T* pfrc = sd.force[s0];
-  const bool hasf = pfrc != nullptr;
+  // FRC: the host knows that no active load of the launch has a body force (0) or that all of
+  // them have one (1); with 2 each block checks its own
+  const bool hasf = FRC == 2 ? pfrc != nullptr : FRC == 1;
   T E[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) E[q] = sd.E[s0][q];
@@ -2721,21 +2723,29 @@ void launch_step_occ(const SampleDesc<T>* d_samples, const WorkItem* d_work, int
                      int first, double* partials, hipStream_t s, int nt, size_t lds) {
   if constexpr (L == 1) {
     if (ts.pf == 9 && !ts.walls) {  // x-neighbours across lanes (one load per block, bx 16, 32 or 64)
-      if (nt <= 256) {
-        if (ts.pal)
-          hipLaunchKernelGGL((step_kernel_x<T, HI, true, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
+      auto go = [&](auto pal, auto cap, auto frc) {
+        hipLaunchKernelGGL((step_kernel_x<T, HI, decltype(pal)::value, decltype(cap)::value, decltype(frc)::value>),
+                           dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork, ts.bx, ts.by, parity, first,
+                           partials);
+      };
+      auto with_cap = [&](auto pal, auto frc) {
+        if (nt <= 256)
+          go(pal, std::integral_constant<int, 256>{}, frc);
         else
-          hipLaunchKernelGGL((step_kernel_x<T, HI, false, 256>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work,
-                             nwork, ts.bx, ts.by, parity, first, partials);
-      } else {
-        if (ts.pal)
-          hipLaunchKernelGGL((step_kernel_x<T, HI, true, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work, nwork,
-                             ts.bx, ts.by, parity, first, partials);
+          go(pal, std::integral_constant<int, 512>{}, frc);
+      };
+      auto with_frc = [&](auto pal) {
+        if (ts.force == 0)
+          with_cap(pal, std::integral_constant<int, 0>{});
+        else if (ts.force == 1)
+          with_cap(pal, std::integral_constant<int, 1>{});
         else
-          hipLaunchKernelGGL((step_kernel_x<T, HI, false, 512>), dim3(nwork), dim3(nt), 0, s, d_samples, d_work,
-                             nwork, ts.bx, ts.by, parity, first, partials);
-      }
+          with_cap(pal, std::integral_constant<int, 2>{});
+      };
+      if (ts.pal)
+        with_frc(std::true_type{});
+      else
+        with_frc(std::false_type{});
       return;
     }
   }
