@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the iteration kernel measured with rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled against a 1 GiB copy kernel; profiles/step_kernel_spheres191_trace_and_counters.md and
 # profiles/step_kernel_spheres480_trace_and_counters.md), valid only for the kernel source they were taken on.
-MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "cee847aef68cec2e", "bytes_per_launch": 3.195988e+08,
+MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "75b988406fdf0a49", "bytes_per_launch": 3.201660e+08,
                     # (loads per block, kernel variant, loads fused, moduli from the phase image, high occupancy,
                     # block x, block y, z-chunk)
                     "launch_signature": (1, 9, 0, 1, 1, 32, 8, 12),
@@ -37,7 +37,7 @@ MEASURED_TRAFFIC = {"ceff_kernels_sha256_prefix": "cee847aef68cec2e", "bytes_per
                     "launch": "step_kernel_x<float,1,PAL,high occupancy>, mean over all launches of a full solve"}
 # the same for the HBM-resident measurement (480^3, one load, 200 iterations without body force; the mean over
 # its launches after the first, which reads no u^{n-1})
-MEASURED_TRAFFIC_HBM = {"ceff_kernels_sha256_prefix": "cee847aef68cec2e", "n": 480, "bytes_per_launch": 4.376351e+09,
+MEASURED_TRAFFIC_HBM = {"ceff_kernels_sha256_prefix": "75b988406fdf0a49", "n": 480, "bytes_per_launch": 4.373917e+09,
                         "algorithmic_bytes_per_launch": 4.091904e+09, "launch_shape": "64x8x32 variant 9"}
 
 
