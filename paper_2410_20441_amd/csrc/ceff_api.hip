@@ -309,8 +309,8 @@ TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single, bool batc
   }
   // FP32, one load per launch: variant 9 (x-neighbours across lanes), 32 x 8 ghosted block
   // (30 x 6 interior, rows within a wave) with 12-plane chunks, high-occupancy build: 0.051-0.054 ms
-  // per launch at 191^3 on every box measured, against 0.0569 for variant 3's best (18 x 14, 12
-  // planes).  24-plane chunks (seven blocks per CU in one round) took 0.050-0.051 ms on some boxes
+  // per launch at 191^3 on every MI355X measured, against 0.0569 for variant 3's best (18 x 14, 12
+  // planes).  24-plane chunks (seven blocks per CU in one round) took 0.050-0.051 ms on some GPUs
   // and 0.056-0.057 on others.  A batch of images takes the same blocks with one load each: the
   // 48-sample three-phase batch in 9.7 s against 10.7 s with variant 3 and two loads per block.
   if ((single || batch) && !fp64) {
@@ -602,7 +602,7 @@ struct Engine {
   // Variant 9 builds the first two cases without the per-block check, for launches whose working set
   // fits in the Infinity Cache: there the 191^3 solve gained 1.7%, while at 480^3 (4.1 GB, from HBM)
   // the build without forces moved 15% more bytes than the per-block test and took 0.934 against
-  // 0.903 ms per launch on the same box.
+  // 0.903 ms per launch on the same GPU.
   int force_state() const {
     if (beyond_cache) return 2;
     bool any = false, all = true;
