@@ -45,6 +45,8 @@ def lib():
         L.or_pcg.restype = ctypes.c_int64
         L.or_apt_steps.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int64, _dp]
+        L.or_apt_steps_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_int64, _dp, _dp, ctypes.c_int]
         L.or_gradient.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.or_stress_ortho.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
         L.or_residual_ortho.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
@@ -150,24 +152,34 @@ def ceff(K, G, h=(1.0, 1.0, 1.0), rtol=1e-11, loads=range(6), return_fields=Fals
     return C, info
 
 
-def apt_steps(K, G, J, nsteps, courant, strouhal, h=(1.0, 1.0, 1.0), state=None):
+def apt_steps(K, G, J, nsteps, courant, strouhal, h=(1.0, 1.0, 1.0), state=None, walls=False):
     """Run `nsteps` APT iterations in the paper's (p, tau, v) variables.
 
     Returns the state dict {p, txx, tyy, tzz, tyz, txz, txy, v} after the
     steps.  With state=None the iteration starts from the affine initial
-    state (v = 0, stresses of the uniform strain)."""
+    state (v = 0, stresses of the uniform strain).  walls: the wall test of
+    load J (normal test for J < 3, simple-shear test for J >= 3); the state
+    then also holds "half1", the side-1 halves of the split edges (indexed
+    like the edge field)."""
     K, G, dims, hh = _prep(K, G, h)
     N = K.size
+    sh = K.shape
     init = 1 if state is None else 0
     buf = np.zeros(10 * N) if state is None else np.concatenate([
         state[k].ravel() for k in ("p", "txx", "tyy", "tzz", "tyz", "txz", "txy")] + [state["v"].ravel()])
     buf = np.ascontiguousarray(buf)
-    lib().or_apt_steps(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(unit_strain(J)), courant, strouhal,
-                       init, nsteps, _d(buf))
-    sh = K.shape
+    if walls:
+        half1 = np.zeros(N) if state is None else np.ascontiguousarray(state["half1"], np.float64).ravel().copy()
+        lib().or_apt_steps_walls(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(unit_strain(J)), courant,
+                                 strouhal, init, nsteps, _d(buf), _d(half1), wall_mode(J))
+    else:
+        lib().or_apt_steps(dims.ctypes.data_as(_ip), _d(hh), _d(K), _d(G), _d(unit_strain(J)), courant, strouhal,
+                           init, nsteps, _d(buf))
     names = ("p", "txx", "tyy", "tzz", "tyz", "txz", "txy")
     out = {nm: buf[i * N:(i + 1) * N].reshape(sh).copy() for i, nm in enumerate(names)}
     out["v"] = buf[7 * N:].reshape((3,) + sh).copy()
+    if walls:
+        out["half1"] = half1.reshape(sh).copy()
     return out
 
 

@@ -720,15 +720,26 @@ int64_t or_pcg_walls(const int64_t dims[3], const double h[3], const double *K, 
  * Initial state: v = 0, p = -K tr E, tau = 2G dev E (cells), tau_e = 2 G_e E_e.
  *
  * state (10N): p, txx, tyy, tzz (cells), tyz, txz, txy (edges), vx, vy, vz (faces).
- * If init != 0 the state is first set to the initial state above.  Runs nsteps. */
-void or_apt_steps(const int64_t dims[3], const double h[3], const double *K, const double *G,
-                  const double E[6], double courant, double strouhal, int init, int64_t nsteps,
-                  double *state) {
-    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+ * If init != 0 the state is first set to the initial state above.  Runs nsteps.
+ *
+ * Under the wall conditions of the direct tests (m->walls as in the other wall
+ * functions; 0 is the periodic medium) wall faces keep v = 0, the free boundary
+ * edges carry no shear stress, and under the simple-shear test s each split edge
+ * holds two half-edge stresses, each relaxed towards its own Hooke stress
+ * (half_edge) as every other stress is.  The side-0 halves are kept in the edge
+ * field, the side-1 halves in half1 (N entries, indexed like the edge; used for
+ * s >= 3 only, may be NULL otherwise); their difference enters the u_d faces of
+ * index n_e - 1, as in the residual.  Initial halves: half_edge of v = 0. */
+static void m_apt_steps(const grid_t *gp, const mat_t *m, const double E[6], double courant, double strouhal,
+                        int init, int64_t nsteps, double *state, double *half1) {
+    const grid_t g = *gp;
+    const double *K = m->K, *G = m->G;
+    const int ws = m->walls;
     const int64_t N = g.nx * g.ny * g.nz;
     double *p = state, *txx = state + N, *tyy = state + 2 * N, *tzz = state + 3 * N;
     double *tyz = state + 4 * N, *txz = state + 5 * N, *txy = state + 6 * N;
     double *v = state + 7 * N;
+    double *tau_e[6] = {NULL, NULL, NULL, tyz, txz, txy};
     double Lx = fmax(fmax(g.nx * g.hx, g.ny * g.hy), g.nz * g.hz);
     double ell = courant / sqrt(1.0 / (g.hx * g.hx) + 1.0 / (g.hy * g.hy) + 1.0 / (g.hz * g.hz));
     double c = ell * strouhal / Lx;           /* pseudo step / physical step */
@@ -746,10 +757,18 @@ void or_apt_steps(const int64_t dims[3], const double h[3], const double *K, con
             txz[t] = 2.0 * edge_modulus(&g, G, 1, i, j, k) * E[4];
             txy[t] = 2.0 * edge_modulus(&g, G, 0, i, j, k) * E[5];
             v[t] = v[N + t] = v[2 * N + t] = 0.0;
+            if (ws)
+                for (int s = 3; s < 6; s++)
+                    if (wall_edge(m, s, i, j, k) == 1) tau_e[s][t] = 0.0;
+        }
+        if (ws >= 3) FOR_SPLIT_EDGES(&g, ws, i, j, k) {
+            const int64_t ce = at(&g, i, j, k);
+            tau_e[ws][ce] = half_edge(&g, m, ws, E, v, i, j, k, 0);
+            half1[ce] = half_edge(&g, m, ws, E, v, i, j, k, 1);
         }
     }
     double *sig = malloc(sizeof(double) * 6 * N), *r = malloc(sizeof(double) * 3 * N);
-    for (int64_t s = 0; s < nsteps; s++) {
+    for (int64_t st = 0; st < nsteps; st++) {
         /* strain rates from the current velocities (with the macroscopic strain) */
         strains(&g, E, v, eps);
         for (int64_t t = 0; t < N; t++) {
@@ -762,14 +781,19 @@ void or_apt_steps(const int64_t dims[3], const double h[3], const double *K, con
             txx[t] = (txx[t] + 2.0 * Gdt * (eps[t] - th / 3.0)) / (1.0 + Gdt / G[t]);
             tyy[t] = (tyy[t] + 2.0 * Gdt * (eps[N + t] - th / 3.0)) / (1.0 + Gdt / G[t]);
             tzz[t] = (tzz[t] + 2.0 * Gdt * (eps[2 * N + t] - th / 3.0)) / (1.0 + Gdt / G[t]);
-            /* edges: pseudo and physical shear modulus are the edge's harmonic G_e */
-            double Ge, Gedt;
-            Ge = edge_modulus(&g, G, 2, i, j, k); Gedt = c * Ge;
-            tyz[t] = (tyz[t] + 2.0 * Gedt * eps[3 * N + t]) / (1.0 + Gedt / Ge);
-            Ge = edge_modulus(&g, G, 1, i, j, k); Gedt = c * Ge;
-            txz[t] = (txz[t] + 2.0 * Gedt * eps[4 * N + t]) / (1.0 + Gedt / Ge);
-            Ge = edge_modulus(&g, G, 0, i, j, k); Gedt = c * Ge;
-            txy[t] = (txy[t] + 2.0 * Gedt * eps[5 * N + t]) / (1.0 + Gedt / Ge);
+            /* edges: pseudo and physical shear modulus are the edge's harmonic G_e; free
+             * boundary edges stay at zero, split edges are relaxed below */
+            for (int s = 3; s < 6; s++) {
+                const int we = ws ? wall_edge(m, s, i, j, k) : 0;
+                if (we) continue;
+                double Ge = edge_modulus(&g, G, 5 - s, i, j, k), Gedt = c * Ge;
+                tau_e[s][t] = (tau_e[s][t] + 2.0 * Gedt * eps[s * N + t]) / (1.0 + Gedt / Ge);
+            }
+        }
+        if (ws >= 3) FOR_SPLIT_EDGES(&g, ws, i, j, k) {
+            const int64_t ce = at(&g, i, j, k);
+            tau_e[ws][ce] = (tau_e[ws][ce] + c * half_edge(&g, m, ws, E, v, i, j, k, 0)) / (1.0 + c);
+            half1[ce] = (half1[ce] + c * half_edge(&g, m, ws, E, v, i, j, k, 1)) / (1.0 + c);
         }
         /* momentum with pseudo inertia: rho~ dv/dt~ = div(-p I + tau) */
         for (int64_t t = 0; t < N; t++) {
@@ -781,6 +805,17 @@ void or_apt_steps(const int64_t dims[3], const double h[3], const double *K, con
             sig[5 * N + t] = txy[t];
         }
         divergence(&g, sig, r);
+        if (ws >= 3) {
+            const int d = pair_d[ws], e = pair_e[ws];
+            const double he = e == 1 ? g.hy : g.hz;
+            FOR_SPLIT_EDGES(&g, ws, i, j, k) {
+                int64_t q[3] = {i, j, k};
+                q[e] = (e == 1 ? g.ny : g.nz) - 1;
+                const int64_t ce = at(&g, i, j, k), cf = at(&g, q[0], q[1], q[2]);
+                r[d * N + cf] += (half1[ce] - sig[ws * N + ce]) / he;
+            }
+        }
+        if (ws) mask_walls(&g, r); /* wall faces are held */
         for (int64_t t = 0; t < N; t++) {
             int64_t i = t % g.nx, j = (t / g.nx) % g.ny, k = t / (g.nx * g.ny);
             double Hc = K[t] + 4.0 * G[t] / 3.0;
@@ -793,6 +828,22 @@ void or_apt_steps(const int64_t dims[3], const double h[3], const double *K, con
         }
     }
     free(eps); free(sig); free(r);
+}
+
+void or_apt_steps(const int64_t dims[3], const double h[3], const double *K, const double *G,
+                  const double E[6], double courant, double strouhal, int init, int64_t nsteps,
+                  double *state) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, NULL, 0, NULL};
+    m_apt_steps(&g, &m, E, courant, strouhal, init, nsteps, state, NULL);
+}
+
+void or_apt_steps_walls(const int64_t dims[3], const double h[3], const double *K, const double *G,
+                        const double E[6], double courant, double strouhal, int init, int64_t nsteps,
+                        double *state, double *half1, int mode) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, NULL, mode, NULL};
+    m_apt_steps(&g, &m, E, courant, strouhal, init, nsteps, state, half1);
 }
 
 /* Gradient of J = sum_IJ W_IJ C_IJ with respect to per-voxel K and G.

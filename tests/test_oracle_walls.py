@@ -7,7 +7,9 @@ Checked against an independent dense energy minimisation with the same walls
 the exact layer averages of a z-laminate (the normal block, whose solution the
 walls do not disturb, and the in-plane shear C66, whose uniform-strain solution
 they do not disturb either), against the mean shear strain (the walls impose it
-exactly) and against the paper's layered-model analytic values."""
+exactly) and against the paper's layered-model analytic values.  The iteration in
+the paper's own variables under the walls is checked against the displacement form
+step by step and against the PCG solution at its fixed point."""
 import json
 import os
 
@@ -132,3 +134,42 @@ def test_walls_residual_and_iteration_fixed_point():
         assert np.all(u_ref[0][:, :, 0] == 0) and np.all(u_ref[1][:, 0, :] == 0) and np.all(u_ref[2][0] == 0)
         u, _ = oracle.apt_disp(J, 3000, 0.95, 4.0, K=K, G=G, walls=True)
         assert np.max(np.abs(u - u_ref)) < 1e-9 * np.max(np.abs(u_ref))
+
+
+def test_walls_paper_form_equals_displacement_form():
+    """Under the walls of every load the paper's (p, tau, v) iteration, with the split
+    edges' two halves relaxed separately, gives the displacement-form iterates."""
+    K, G = synth.random_fields((7, 5, 6), 4, lo=(2.0, 1e-3), hi=(90.0, 45.0))
+    for J in range(6):
+        for k in (1, 2, 9):
+            u, up = oracle.apt_disp(J, k, 0.95, 3.0, K=K, G=G, walls=True)
+            v = oracle.apt_steps(K, G, J, k, 0.95, 3.0, walls=True)["v"]
+            assert np.max(np.abs(u - v)) <= 1e-12 * np.abs(v).max(), (J, k)
+            if k > 1:
+                vp = oracle.apt_steps(K, G, J, k - 1, 0.95, 3.0, walls=True)["v"]
+                assert np.max(np.abs(up - vp)) <= 1e-12 * np.abs(v).max(), (J, k)
+
+
+def test_walls_paper_form_fixed_point_and_restart():
+    """The paper-form wall iteration converges to the wall-mode PCG solution, keeps the
+    wall faces and the free boundary edges' shear stresses at zero, and restarting it
+    from a saved state (with the split edges' side-1 halves) continues the same run."""
+    K, G = synth.random_fields((4, 5, 6), 3, lo=(10.0, 5.0), hi=(80.0, 40.0))
+    for J in (1, 4):
+        u_ref, _, _ = oracle.solve_load_walls(K, G, J, rtol=1e-13)
+        st = oracle.apt_steps(K, G, J, 3000, courant=0.95, strouhal=4.0, walls=True)
+        v = st["v"]
+        assert np.max(np.abs(v - u_ref)) < 1e-9 * np.max(np.abs(u_ref))
+        assert np.all(v[0][:, :, 0] == 0) and np.all(v[1][:, 0, :] == 0) and np.all(v[2][0] == 0)
+        # free-slip edges on the walls: yz-edges with j = 0 or k = 0 carry no stress in the
+        # normal test; in the simple-shear test of xz the xy-edges on the x and y walls
+        # are free, and the xz-edges on the z walls are split (side 0 in txz, side 1 in half1)
+        if J == 1:
+            assert np.all(st["tyz"][:, 0, :] == 0) and np.all(st["tyz"][0] == 0)
+        else:
+            assert np.all(st["txy"][:, :, 0] == 0) and np.all(st["txy"][:, 0, :] == 0)
+            assert np.any(st["half1"][0] != 0) and np.all(st["half1"][1:] == 0)
+        a = oracle.apt_steps(K, G, J, 7, courant=0.95, strouhal=4.0, walls=True)
+        b = oracle.apt_steps(K, G, J, 5, courant=0.95, strouhal=4.0, walls=True, state=a)
+        c = oracle.apt_steps(K, G, J, 12, courant=0.95, strouhal=4.0, walls=True)
+        assert all(np.array_equal(b[n], c[n]) for n in c)
