@@ -4,7 +4,8 @@ simple-shear test (the loaded walls also hold the sheared component through
 split half edges).
 
 Step, residual and average parity with the oracle's wall modes for all six
-loads, C* columns against the oracle's wall-mode PCG solve, the paper's layered
+loads (steps against both the displacement form and the paper's (p, tau, v)
+form), C* columns against the oracle's wall-mode PCG solve, the paper's layered
 Model 1 at its full size against the analytic values (normal block and the
 in-plane C66, which the walls do not disturb) and against the oracle's slab
 solution for C44 and C55, and the error paths."""
@@ -54,6 +55,36 @@ def test_walls_steps_match_oracle(shape, seed):
     assert np.max(np.abs(u32 - ref)) <= 2e-5 * np.abs(ref).max()
     ref, _ = oracle.apt_disp(5, 9, 0.95, 3.0, K=K, G=G, walls=True)
     assert np.max(np.abs(v32 - ref)) <= 2e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("shape,seed", SHAPES[:3])
+@pytest.mark.parametrize("use_phases", [False, True])
+def test_walls_steps_match_paper_form(shape, seed, use_phases):
+    """The iterates under the walls against the oracle's iteration in the paper's own
+    variables (pressure, deviatoric and edge stresses, velocity), all six loads, FP64
+    and mixed precision, from K and G fields and from a phase image."""
+    p = need_gpu()
+    if use_phases:
+        # three phases, soft to stiff, scattered at random
+        ph = np.random.default_rng(seed).integers(0, 3, size=shape).astype(np.uint8)
+        K_tab, G_tab = np.array([2.0, 36.0, 90.0]), np.array([1e-3, 44.0, 45.0])
+        K, G = K_tab[ph], G_tab[ph]
+    else:
+        K, G = fields(shape, seed)
+    announce("walls apt_steps vs paper form", shape, seed, use_phases)
+    with p.Context() as c:
+        if use_phases:
+            c.set_phases(ph, K_tab, G_tab)
+        else:
+            c.set_material(K, G)
+        c.set_boundary("walls")
+        for J in range(6):
+            ref = oracle.apt_steps(K, G, J, 11, 0.95, 3.0, walls=True)["v"]
+            sc = np.abs(ref).max()
+            u, _ = c.apt_steps(J, 11, "fp64", courant=0.95, strouhal=3.0)
+            assert np.max(np.abs(u - ref)) <= 1e-11 * sc, J
+            u, _ = c.apt_steps(J, 11, "mixed", courant=0.95, strouhal=3.0)
+            assert np.max(np.abs(u - ref)) <= 2e-5 * sc, J
 
 
 @pytest.mark.parametrize("shape,seed", SHAPES[:3])
