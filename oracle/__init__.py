@@ -45,6 +45,8 @@ def lib():
         L.or_pcg.restype = ctypes.c_int64
         L.or_apt_steps.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int64, _dp]
+        L.or_apt_stress.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int64, _dp, _dp]
         L.or_apt_steps_walls.argtypes = [_ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                          ctypes.c_int64, _dp, _dp, ctypes.c_int]
         L.or_gradient.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -386,6 +388,30 @@ def apt_disp_tri(C21, J, nsteps, courant, strouhal, h=(1.0, 1.0, 1.0)):
     up = np.empty((3,) + sh)
     lib().or_apt_disp_tri(dims.ctypes.data_as(_ip), _d(hh), _d(C21), _d(unit_strain(J)), courant, strouhal,
                           nsteps, _d(u), _d(up))
+    return u, up
+
+
+def apt_stress(J, nsteps, courant, strouhal, K=None, G=None, C9=None, C21=None, h=(1.0, 1.0, 1.0), walls=False):
+    """Stress-state APT iterate v^nsteps and v^(nsteps-1) (each (3, nz, ny, nx)) for isotropic
+    (K, G), orthotropic (C9) or general (C21) cells, from v = 0 and the stress of the uniform
+    strain; the stresses relax towards Hooke's law of the current strain and drive the
+    velocity, as in the paper's scheme.  walls: the wall test of load J (K, G or C9 cells)."""
+    Kp = Gp = cp = tp = None
+    if C21 is not None:
+        C21, dims, hh = _prep21(C21, h)
+        sh, tp = C21.shape[1:], _d(C21)
+    elif C9 is not None:
+        C9, dims, hh = _prep9(C9, h)
+        sh, cp = C9.shape[1:], _d(C9)
+    else:
+        K, G, dims, hh = _prep(K, G, h)
+        sh, Kp, Gp = K.shape, _d(K), _d(G)
+    if walls and C21 is not None:
+        raise ValueError("the wall tests are defined for isotropic and orthotropic cells")
+    u = np.empty((3,) + sh)
+    up = np.empty((3,) + sh)
+    lib().or_apt_stress(dims.ctypes.data_as(_ip), _d(hh), Kp, Gp, cp, tp, wall_mode(J) if walls else 0,
+                        _d(unit_strain(J)), courant, strouhal, nsteps, _d(u), _d(up))
     return u, up
 
 

@@ -686,6 +686,70 @@ void or_apt_disp_tri(const int64_t dims[3], const double h[3], const double *c21
     m_apt_disp(&g, &m, E, courant, strouhal, nsteps, u, u_prev);
 }
 
+/* The APT iteration with the stress as its state, for any cell law of this file
+ * (isotropic, orthotropic, general) and the wall tests.  It is the paper's
+ * relaxation scheme with pseudo moduli equal to the local moduli: split into
+ * pressure and deviator, the implicit relaxation of each is
+ *   sigma <- (sigma + c * Hooke(E + grad v)) / (1 + c)
+ * for the whole stress, so this is or_apt_steps written for a general Hooke map
+ * (tests check that they agree on isotropic cells), followed by the momentum
+ * update v <- v + (beta / H_f) div sigma with the face step stiffness H_f of the
+ * displacement form.  Unlike the displacement form it keeps the stresses and the
+ * split edges' side-1 halves as state and eliminates nothing.
+ * Starts from v = 0 and sigma = Hooke(E); returns v after nsteps in u (3N) and
+ * after nsteps - 1 in u_prev (3N, may be NULL). */
+static void m_apt_stress(const grid_t *g, const mat_t *m, const double E[6], double courant, double strouhal,
+                         int64_t nsteps, double *u, double *u_prev) {
+    const int64_t N = g->nx * g->ny * g->nz, n3 = 3 * N;
+    const int ws = m->walls;
+    double Lx = fmax(fmax(g->nx * g->hx, g->ny * g->hy), g->nz * g->hz);
+    double ell = courant / sqrt(1.0 / (g->hx * g->hx) + 1.0 / (g->hy * g->hy) + 1.0 / (g->hz * g->hz));
+    double c = ell * strouhal / Lx, beta = ell * Lx / strouhal;
+    double *sig = malloc(sizeof(double) * 6 * N), *hk = malloc(sizeof(double) * 6 * N);
+    double *r = malloc(sizeof(double) * n3), *Hf = malloc(sizeof(double) * n3);
+    double *half1 = calloc(N, sizeof(double));
+    for (int64_t t = 0; t < N; t++) {
+        int64_t i = t % g->nx, j = (t / g->nx) % g->ny, k = t / (g->nx * g->ny);
+        int64_t nb[3] = {at(g, i - 1, j, k), at(g, i, j - 1, k), at(g, i, j, k - 1)};
+        for (int d = 0; d < 3; d++) Hf[d * N + t] = fmax(step_stiffness(m, N, d, t), step_stiffness(m, N, d, nb[d]));
+    }
+    memset(u, 0, sizeof(double) * n3);
+    m_stress(g, m, E, u, sig);
+    if (ws >= 3) FOR_SPLIT_EDGES(g, ws, i, j, k) half1[at(g, i, j, k)] = half_edge(g, m, ws, E, u, i, j, k, 1);
+    for (int64_t st = 0; st < nsteps; st++) {
+        m_stress(g, m, E, u, hk);
+        for (int64_t t = 0; t < 6 * N; t++) sig[t] = (sig[t] + c * hk[t]) / (1.0 + c);
+        if (ws >= 3) FOR_SPLIT_EDGES(g, ws, i, j, k) {
+            const int64_t ce = at(g, i, j, k);
+            half1[ce] = (half1[ce] + c * half_edge(g, m, ws, E, u, i, j, k, 1)) / (1.0 + c);
+        }
+        divergence(g, sig, r);
+        if (ws >= 3) {
+            const int d = pair_d[ws], e = pair_e[ws];
+            const double he = e == 1 ? g->hy : g->hz;
+            FOR_SPLIT_EDGES(g, ws, i, j, k) {
+                int64_t q[3] = {i, j, k};
+                q[e] = (e == 1 ? g->ny : g->nz) - 1;
+                const int64_t ce = at(g, i, j, k), cf = at(g, q[0], q[1], q[2]);
+                r[d * N + cf] += (half1[ce] - sig[ws * N + ce]) / he;
+            }
+        }
+        if (ws) mask_walls(g, r);
+        if (u_prev) memcpy(u_prev, u, sizeof(double) * n3);
+        for (int64_t t = 0; t < n3; t++) u[t] += beta / Hf[t] * r[t];
+    }
+    if (u_prev && nsteps == 0) memset(u_prev, 0, sizeof(double) * n3);
+    free(sig); free(hk); free(r); free(Hf); free(half1);
+}
+
+void or_apt_stress(const int64_t dims[3], const double h[3], const double *K, const double *G, const double *c9,
+                   const double *c21, int walls, const double E[6], double courant, double strouhal, int64_t nsteps,
+                   double *u, double *u_prev) {
+    grid_t g = {dims[0], dims[1], dims[2], h[0], h[1], h[2]};
+    mat_t m = {K, G, c9, walls, c21};
+    m_apt_stress(&g, &m, E, courant, strouhal, nsteps, u, u_prev);
+}
+
 /* Wall-boundary versions (isotropic cells) of the residual, the stress averages
  * and the PCG solve; mode = 1 (normal test) or 3..5 (simple-shear test). */
 void or_residual_walls(const int64_t dims[3], const double h[3], const double *K, const double *G,
