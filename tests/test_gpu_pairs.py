@@ -39,7 +39,7 @@ def test_pairs_equal_single_iterations(monkeypatch, shape, seed):
         announce("pairs vs single", shape, n, d, dp)
         assert d <= 1e-6 and dp <= 1e-6, (n, d, dp)
     # and against the oracle's iteration
-    ref, _ = oracle.apt_disp(4, 11, 0.95, 3.0, K=K, G=G)
+    ref = oracle.apt_steps(K, G, 4, 11, 0.95, 3.0)["v"]
     assert np.abs(out[("1", 11)][0] - ref).max() <= 2e-5 * np.abs(ref).max()
 
 
