@@ -187,9 +187,12 @@ def parse():
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for counter collection: allow stopping at --max-iter")
     ap.add_argument("--workload", default="spheres191",
-                    choices=["spheres191", "batch48", "cracks479", "spheres703", "hsweep", "grad128", "hbm480"],
+                    choices=["spheres191", "batch48", "cracks479", "spheres703", "walls191", "hsweep", "grad128",
+                             "hbm480"],
                     help="spheres191 (default bench line); batch48: 48 uneven three-phase samples in one solve; "
                          "cracks479: 479^3 cracked solid; spheres703: 703^3 sphere pack (the largest grid; --fuse off solves the loads one after another and reports each); "
+                         "walls191: the paper's layered model at 191^3 under the direct tests' walls, with the triaxial "
+                         "off-diagonals; "
                          "hsweep: contribution tensors of single spheroids, aspect ratio x contrast, one batch; "
                          "hbm480: only the HBM-resident roofline measurement (for profiling)")
     ap.add_argument("--hsweep-r", type=int, default=12, help="hsweep: largest semi-axis of the coarse spheroids")
@@ -502,6 +505,8 @@ def other_workload(a, torch, synth, ceff, dev):
     else:
         if a.workload == "cracks479":
             m = synth.workload_cracks()
+        elif a.workload == "walls191":
+            m = synth.laminate_z(191, 191, 191, 6, 15)  # six stiff layers 15 cells thick in a soft host
         else:
             m = synth.random_spheres(703, 0.10, 0xC2)
         N = m.phase.size
@@ -509,6 +514,8 @@ def other_workload(a, torch, synth, ceff, dev):
               flush=True)
         ctx = ceff.Context(0)
         ctx.set_phases(m.phase, m.K_tab, m.G_tab)
+        if a.workload == "walls191":
+            ctx.set_boundary("walls")
         loads = [int(q) for q in a.loads]
         # one load at a time (--fuse off): one solve call per load, each reported as it ends
         groups = [[J] for J in loads] if a.fuse == "off" else [loads]
@@ -542,6 +549,10 @@ def other_workload(a, torch, synth, ceff, dev):
                "kernel_GB_s": step_bytes / (step_ms * 1e-3) / 1e9 if step_ms > 0 else None,
                "avg_launch_ms": step_ms / max(launches, 1),
                "C_eff_GPa": np.round(C, 5).tolist()}
+        if a.workload == "walls191":
+            res["boundary"] = "walls"
+            if not np.isnan(C[:3, :3]).any():
+                res["triaxial_offdiagonals_GPa"] = [round(float(v), 5) for v in ceff.triaxial_offdiagonals(C)]
     print(json.dumps(res), flush=True)
 
 
