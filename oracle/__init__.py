@@ -7,9 +7,12 @@ never imports, links or calls it, and it shares no code with it.
 Contents
 --------
 * ``ceff_oracle.c`` (loaded through ctypes): FP64 operator, Jacobi-PCG solve,
-  stress averages, the paper-form APT step reference, the displacement-form
-  APT iteration and the closed-form gradient; isotropic (K, G) cells, and
-  orthotropic cells with nine constants (``*_ortho``).
+  stress averages, the paper-form APT iteration (``apt_steps``, also under the
+  wall tests), the stress-state APT iteration for every cell law
+  (``apt_stress``), the displacement-form APT iteration (``apt_disp``) and the
+  closed-form gradient; isotropic (K, G) cells, orthotropic cells with nine
+  constants (``*_ortho``), general cells with 21 constants (``*_tri``) and the
+  wall tests (``*_walls``).
 * ``dense.py``: brute-force dense solve for tiny grids, assembled from the
   strain energy alone (an independent route to the same discrete problem).
 
