@@ -295,7 +295,7 @@ struct Prob {
 // MI355X's Infinity Cache (the memory-side last-level cache in front of HBM).
 constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 
-TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single, bool batch) {
+TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single, bool batch, bool plain = true) {
   TileShape t{};
   // CEFF_TILE="bx,by[,kc[,group[,variant[,order[,occ]]]]]" overrides the launch shape (the iterates
   // do not depend on it; tests check that)
@@ -313,14 +313,17 @@ TileShape default_tile(int64_t nx, int64_t ny, bool fp64, bool single, bool batc
   // planes).  24-plane chunks (seven blocks per CU in one round) took 0.050-0.051 ms on some GPUs
   // and 0.056-0.057 on others.  A batch of images takes the same blocks with one load each: the
   // 48-sample three-phase batch in 9.7 s against 10.7 s with variant 3 and two loads per block.
-  if ((single || batch) && !fp64) {
+  // FP64, one load per launch on one image of periodic isotropic cells (plain): the same blocks at
+  // the default occupancy, 0.1227 ms per launch at 191^3 against 0.1326 for variant 3 at 34 x 14 and
+  // 0.1536 with the high-occupancy build.
+  if (fp64 ? single && !batch && plain : single || batch) {
     t.bx = nx + 2 <= 16 ? 16 : 32;
     t.by = (int)std::min<int64_t>(ny + 2, 8);
     t.kc = 12;
     t.group = 1;
     t.pf = 9;
     t.order = 1;
-    t.occ = 1;
+    t.occ = fp64 ? 0 : 1;
     return t;
   }
   // Fastest shapes of the 191^3 sweeps for the other cases, all with 12-plane chunks and the loads
@@ -428,6 +431,8 @@ struct Engine {
   }
 
   bool single() const { return Js.size() == 1; }
+  // periodic boundaries and isotropic cells
+  bool plain_cells() const { return in[0].c64 == nullptr && in[0].t64 == nullptr && !in[0].walls; }
   int slot_of(int J) const { return single() ? 0 : J; }
   int group() const {
     return single() || ts.pf == 5 || ts.pf == 9 || ts.ortho || ts.walls || ts.tri ? 1
@@ -677,9 +682,13 @@ struct Engine {
   // 64 x 8 blocks with 16-plane chunks: the 48-sample three-phase batch (samples
   // 48 to 128 wide, 5.4 GB for all six loads) ran in 8.85 s against 9.67 s with
   // the cache-resident 32 x 8 x 24 blocks (12-, 24-, 32- and 48-plane chunks
-  // 8.85, 8.93, 9.09 and 9.86 s).
+  // 8.85, 8.93, 9.09 and 9.86 s).  FP64 one-load solves of one phase image take the same
+  // 64 x 8 x 32 blocks at the default occupancy: 1.757 ms per launch at 480^3 against 1.875 for the
+  // 32 x 8 x 12 blocks and 1.936 for variant 3 at 34 x 14 x 12.
   void large_grid_shape() {
-    if (sizeof(T) != 4 || ts.ortho || ts.walls || ts.tri) return;
+    const bool fp64 = sizeof(T) == 8;
+    if (ts.ortho || ts.walls || ts.tri) return;
+    if (fp64 && !(single() && in.size() == 1 && ts.pf == 9)) return;
     if (in.size() > 1) {
       if (ts.pf != 9 || ts.bx != 32) return;  // the batch default for samples wider than 14 cells
       double ws = 0.0;
@@ -706,7 +715,7 @@ struct Engine {
       ts.by = 8;
       ts.kc = 32;
       ts.pf = 9;
-      ts.occ = 1;
+      ts.occ = fp64 ? 0 : 1;
       return;
     }
     const int64_t items = ((s.nx + 63) / 64) * ((s.ny + 4) / 5) * ((s.nz + 47) / 48);
@@ -729,10 +738,10 @@ struct Engine {
       nym = std::max(nym, s.ny);
     }
     if (std::getenv("CEFF_TILE")) {
-      ts = with_moduli(default_tile(nxm, nym, fp64, single(), in.size() > 1));
+      ts = with_moduli(default_tile(nxm, nym, fp64, single(), in.size() > 1, plain_cells()));
       return CEFF_OK;
     }
-    ts = with_moduli(default_tile(nxm, nym, fp64, single(), in.size() > 1));
+    ts = with_moduli(default_tile(nxm, nym, fp64, single(), in.size() > 1, plain_cells()));
     large_grid_shape();
     if (!o.autotune || ts.ortho || ts.walls || ts.tri || want_tb()) return CEFF_OK;
     const std::string key = tune_key();

@@ -121,7 +121,7 @@ def test_lanes_solve_equals_variant3_solve(monkeypatch, phases, prec):
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_degenerate_grids_default_shape(monkeypatch, shape, prec):
     """Grids two cells wide in x or y, and two planes deep, on the library's own launch shape
-    (variant 9 in mixed precision, variant 3 in FP64): a row's ghost lanes then wrap onto the
+    (variant 9 in both precisions): a row's ghost lanes then wrap onto the
     same two columns, and a block's ghost rows onto the same two rows.  The iterate after 11
     steps matches the oracle's paper-form iteration, and C* its PCG solve."""
     p = need_gpu()
@@ -132,7 +132,7 @@ def test_degenerate_grids_default_shape(monkeypatch, shape, prec):
     with p.Context() as c:
         c.set_material(K, G)
         u, _ = c.apt_steps(2, 11, prec, courant=0.95, strouhal=3.0)
-        assert c.stats()["tile_variant"] == (9 if prec == "mixed" else 3)
+        assert c.stats()["tile_variant"] == 9
         C, info = c.solve(precision=prec, rtol=1e-9)
     tol = 2e-5 if prec == "mixed" else 1e-11
     assert np.abs(u - ref).max() <= tol * np.abs(ref).max()

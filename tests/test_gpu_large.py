@@ -39,10 +39,10 @@ def test_one_load_beyond_4gib_matches_pointer_form(monkeypatch, n, precision, to
         c.set_phases(phase, TAB_K, TAB_G)
         del phase
         monkeypatch.delenv("CEFF_TILE", raising=False)
-        announce("beyond 4 GiB", n, precision, "default variant (3 in FP64, 9 in FP32)")
+        announce("beyond 4 GiB", n, precision, "default variant 9")
         u3 = _steps(p, c, 2, 10, prec, n)
         st = c.stats()
-        assert st["tile_variant"] == (3 if precision == "fp64" else 9)
+        assert (st["tile_bx"], st["tile_by"], st["tile_kc"], st["tile_variant"]) == (64, 8, 32, 9)
         monkeypatch.setenv("CEFF_TILE", "34,14,12,1,1")
         announce("beyond 4 GiB", n, precision, "variant 1 (pointer form)")
         u1 = _steps(p, c, 2, 10, prec, n)
