@@ -114,7 +114,8 @@ typedef struct {
                               one plane ahead; 5 one load per block, in-plane neighbours read through the
                               caches instead of LDS; 6 two iterations per launch (CEFF_TB=1); 9 one load
                               per block in rows of 16, 32 or 64 cells, x-neighbour values exchanged
-                              between the lanes of a wave (the FP32 default) */
+                              between the lanes of a wave (the default for FP32 and for
+                              one-load FP64 solves of periodic isotropic cells) */
   int fused_loads;         /* 1 if the requested loads advanced together, one launch per iteration */
   int phase_moduli;        /* 1: the iteration kernel read each cell's 1-byte phase id and a per-phase
                               table (material set with ceff_set_phases) instead of the K and G fields */
